@@ -1,0 +1,219 @@
+"""Benchmark of the radiance hot path on one MI355X.
+
+A step is one fitting pass over the whole query set: grid rebuild for the
+current field, forward radiance query, MSE loss and its gradient, backward
+radiance query (gradients to every primitive parameter) and an Adam update.
+
+Default workload: 1,000,000 Gaussians (20% in one caustic cluster under the
+sphere, the rest on the five walls), 32 views at 800x800 = 20,480,000 query
+points, FP32.  Targets are the radiance of a second field (seed 1) rendered
+once before timing.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# Algorithmic work per contributing (query, primitive) pair: forward 34 flops
+# (offset 3, whitening 9 FMA, m^2 5, scale 1, exp 1, accumulate 3 FMA; an FMA
+# counts 2), backward 64 (recompute 28, a and c 6, accumulators 30).
+FLOPS_FWD = 34
+FLOPS_BWD = 64
+PEAK_FP32_VALU = 157.3e12      # published packed-FP32 vector peak
+PEAK_FP32_NONPACKED = 78.6e12  # 256 CU x 4 SIMD x 16 lanes x 2 flops x 2.4 GHz
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(field, x, sample: int, seed: int = 11):
+    """The FP64 oracle (brute force over all primitives) forward + backward on
+    a bounded random sample of query points, over a process pool."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+
+    import numpy as np
+
+    from oracle import cpu_timing
+    rng = np.random.default_rng(seed)
+    sel = np.sort(rng.choice(x.shape[0], sample, replace=False))
+    xs = x[sel]
+    cores = min(16, os.cpu_count() or 1)
+    chunks = np.array_split(np.arange(sample), cores)
+    t0 = time.perf_counter()
+    ctx = mp.get_context("spawn")
+    with cf.ProcessPoolExecutor(cores, mp_context=ctx) as ex:
+        futs = [ex.submit(cpu_timing.fwd_bwd_chunk, field.mu, field.quat, field.log_scale,
+                          field.rgb, xs[c]) for c in chunks if len(c)]
+        pairs = sum(f.result() for f in futs)
+    dt = time.perf_counter() - t0
+    return dict(value=sample / dt, unit="queries/s", cores=cores, kind="oracle",
+                sample=f"{sample} random query points of the same workload, FP64 brute force "
+                       f"over all {field.n} primitives, forward + backward, {cores} processes; "
+                       f"{pairs} contributing pairs; {dt:.1f} s wall")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="caustic1m")
+    ap.add_argument("--views", type=int, default=None)
+    ap.add_argument("--res", type=int, default=None)
+    ap.add_argument("--cell", type=float, default=0.025)
+    ap.add_argument("--lr", type=float, default=5e-4)
+    ap.add_argument("--cpu-sample", type=int, default=192)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2512_12459_amd import radiance as R
+    from paper_2512_12459_amd import scenes as S
+
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    field, x = S.workload(args.workload, views=args.views, res=args.res)
+    gt, _ = S.workload(args.workload, views=1, res=8, seed=1)
+    log(f"workload {args.workload}: n={field.n} q={x.shape[0]} ({time.perf_counter() - t0:.1f} s)")
+    q = x.shape[0]
+    n = field.n
+    dev = torch.device("cuda:0")
+    xd = torch.from_numpy(x).to(dev)
+
+    # parameters in one flat buffer so that one Adam launch updates them all
+    P = torch.empty(13 * n, device=dev)
+    G = torch.zeros(13 * n, device=dev)
+    M = torch.zeros(13 * n, device=dev)
+    V = torch.zeros(13 * n, device=dev)
+
+    def views(buf):
+        return (buf[0:3 * n].view(n, 3), buf[3 * n:7 * n].view(n, 4),
+                buf[7 * n:10 * n].view(n, 3), buf[10 * n:13 * n].view(n, 3))
+
+    mu, quat, ls, rgb = views(P)
+    for t, a in zip((mu, quat, ls, rgb), field.arrays()):
+        t.copy_(torch.from_numpy(a))
+    gmu, gq, gls, grgb = views(G)
+    grads = dict(mu=gmu, quat=gq, log_scale=gls, rgb=grgb)
+
+    t0 = time.perf_counter()
+    qs = R.QuerySet(xd, args.cell)
+    torch.cuda.synchronize()
+    t_bin = time.perf_counter() - t0
+    qinfo = qs.info()
+    log(f"binned: {qinfo} in {t_bin:.2f} s")
+
+    # targets: radiance of a second field, rendered once
+    gt_dev = [torch.from_numpy(a).to(dev) for a in gt.arrays()]
+    gt_grid = R.Grid(qs).build(*gt_dev)
+    T = R.eval_radiance(gt_grid, *gt_dev)
+    gt_grid.close()
+    del gt_dev
+    torch.cuda.synchronize()
+
+    grid = R.Grid(qs)
+    L = torch.empty((q, 3), device=dev)
+    dL = torch.empty((q, 3), device=dev)
+    loss = torch.zeros(1, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+    ev = {k: [] for k in ("build", "fwd", "loss", "bwd", "adam")}
+
+    def step(t, timed):
+        def mark():
+            e = torch.cuda.Event(enable_timing=True)
+            e.record(stream)
+            return e
+        e0 = mark() if timed else None
+        grid.build(mu, quat, ls, rgb)
+        e1 = mark() if timed else None
+        R.eval_radiance(grid, mu, quat, ls, rgb, out=L)
+        e2 = mark() if timed else None
+        loss.zero_()
+        R.mse_loss(L, T, dL=dL, loss_sum=loss)
+        G.zero_()
+        e3 = mark() if timed else None
+        R.eval_radiance_backward(grid, mu, quat, ls, rgb, dL, grads)
+        e4 = mark() if timed else None
+        R.adam_step(P, G, M, V, t, args.lr)
+        e5 = mark() if timed else None
+        if timed:
+            for k, (a, b) in zip(ev, ((e0, e1), (e1, e2), (e2, e3), (e3, e4), (e4, e5))):
+                ev[k].append((a, b))
+
+    for t in range(1, args.warmup + 1):
+        step(t, False)
+    torch.cuda.synchronize()
+    pairs = grid.count_pairs()
+    ginfo = grid.info()
+    log(f"grid: {ginfo}; contributing pairs {pairs} ({pairs / q:.1f} per point)")
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for t in range(args.warmup + 1, args.warmup + args.steps + 1):
+        step(t, True)
+        if (t - args.warmup) % max(1, args.steps // 4) == 0:
+            log(f"step {t - args.warmup}/{args.steps}")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    ms = {k: float(np.mean([a.elapsed_time(b) for a, b in v])) for k, v in ev.items()}
+    step_ms = wall / args.steps * 1e3
+    loss_v = loss.item() / q
+    value = q / (step_ms * 1e-3)
+    fb_ms = ms["fwd"] + ms["bwd"]
+    dom = "bwd" if ms["bwd"] >= ms["fwd"] else "fwd"
+    flops = pairs * (FLOPS_BWD if dom == "bwd" else FLOPS_FWD)
+    achieved = flops / (ms[dom] * 1e-3)
+    result = {
+        "metric": "fwd+bwd radiance queries/s @1M Gaussians",
+        "value": value,
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": step_ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {n} Gaussians, {q} query points "
+                               f"({args.views or 'default'} views, res {args.res or 'default'})",
+                   "step": "grid build + forward + MSE + backward + Adam",
+                   "cell": args.cell},
+        "fwd_bwd_queries_per_s": q / (fb_ms * 1e-3),
+        "kernel_ms": ms,
+        "pairs": pairs,
+        "pairs_per_query": pairs / q,
+        "loss": loss_v,
+        "device_bytes": {"queries": qinfo["device_bytes"], "grid": ginfo["device_bytes"],
+                         "torch_peak": torch.cuda.max_memory_allocated()},
+        "roofline": {"bound": "alu", "kernel": f"eval_{dom}", "achieved": achieved / 1e12,
+                     "peak": PEAK_FP32_VALU / 1e12, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32_VALU, "traffic": None,
+                     "frac_of_nonpacked_peak": achieved / PEAK_FP32_NONPACKED,
+                     "flops_per_pair": FLOPS_BWD if dom == "bwd" else FLOPS_FWD},
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        result["cpu_baseline"] = cpu_baseline(field, x, args.cpu_sample)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

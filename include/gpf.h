@@ -1,0 +1,147 @@
+/*
+ * gpf.h -- C ABI of the Gaussian Photon Field radiance library (libgpf.so).
+ *
+ * The field (Sec. 4.1, Eq. gaussian_contribution) is a set of N anisotropic
+ * 3-D Gaussians with centre mu, rotation quaternion q = (w,x,y,z) (Hamilton,
+ * scalar first), per-axis scale s = exp(log_scale) and RGB flux Phi.  A query
+ * at a surface point x (the first diffuse hit of a camera ray, Sec. 4.2) sums
+ * the flux of every primitive within Mahalanobis distance `cutoff` (3 sigma),
+ * each weighted by exp(-m^2/2), m^2 = |diag(1/s) R^T (x - mu)|^2 (the
+ * aggregation equation of Sec. 4.2 with the local-frame evaluation of the
+ * supplementary hybrid query, Alg. S3; un-normalised, no distance falloff,
+ * no BSDF factor).
+ *
+ * Conventions for every call:
+ *  - Array pointers are DEVICE pointers (hipMalloc'd or torch CUDA tensors),
+ *    FP32, row-major, contiguous, unless a comment says "host".
+ *  - `stream` is a hipStream_t passed as void*; NULL means the default stream.
+ *    Calls enqueue work on it and return without synchronising, except where a
+ *    comment says the call synchronises.
+ *  - The caller owns every input, output and gradient buffer.  The library
+ *    owns the opaque handles (query sets, grids, MLPs) and the device memory
+ *    inside them; destroy them with the matching *_destroy call.
+ *  - No call aborts or throws.  Arguments are validated on the host before any
+ *    launch; failures return a non-zero gpf_status and leave a message for
+ *    gpf_last_error() (thread-local).  Outputs are untouched on failure.
+ */
+#ifndef GPF_H
+#define GPF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  GPF_OK = 0,
+  GPF_ERR_INVALID_ARGUMENT = 1, /* null pointer, bad size, bad option        */
+  GPF_ERR_OUT_OF_MEMORY = 2,    /* device allocation failed or over budget   */
+  GPF_ERR_CAPACITY = 3,         /* a size exceeds a documented maximum       */
+  GPF_ERR_HIP = 4,              /* a HIP runtime call failed                 */
+  GPF_ERR_STALE = 5             /* handle built for a different field/query  */
+} gpf_status;
+
+typedef struct gpf_queries gpf_queries; /* binned query points (opaque)       */
+typedef struct gpf_grid gpf_grid;       /* per-field cull structure (opaque)  */
+typedef struct gpf_mlp gpf_mlp;         /* learned initialiser (opaque)       */
+
+/* A field of n primitives: mu[n][3], quat[n][4] (w,x,y,z; any non-zero norm,
+   normalised inside), log_scale[n][3] (natural log of the per-axis standard
+   deviation), rgb[n][3] (flux Phi). */
+typedef struct {
+  const float *mu, *quat, *log_scale, *rgb;
+  int64_t n;
+} gpf_field;
+
+/* Gradient buffers with the shapes of gpf_field; calls ADD into them. */
+typedef struct {
+  float *mu, *quat, *log_scale, *rgb;
+} gpf_field_grad;
+
+/* Output field buffers with the shapes of gpf_field; calls OVERWRITE them. */
+typedef struct {
+  float *mu, *quat, *log_scale, *rgb;
+} gpf_field_out;
+
+/* ---- status ------------------------------------------------------------ */
+const char *gpf_last_error(void);       /* message of the last failure (host) */
+const char *gpf_version(void);
+
+/* ---- query binning (supports the visible-point set of Sec. 4.3, which is
+ * fixed during training, so it is binned once) ---------------------------
+ * Bins q query points x[q][3] into a uniform grid of cubic cells of edge
+ * `cell_size` (> 0) spanning their bounding box, sorts them by cell and by a
+ * Morton code inside the cell, and cuts each cell's run into tiles of at most
+ * 64 points.  The grid geometry of every later gpf_build_grid comes from this
+ * set.  1 <= q <= 2^31 - 1.  Synchronises `stream` (reads back the bounding
+ * box and the tile count).  *out receives a new handle. */
+gpf_status gpf_bin_queries(const float *x, int64_t q, float cell_size, void *stream,
+                           gpf_queries **out);
+void gpf_queries_destroy(gpf_queries *qs);
+/* Host-side facts about a query set: number of points, of occupied cells and
+ * of tiles, and the device bytes the handle holds. */
+gpf_status gpf_queries_info(const gpf_queries *qs, int64_t *q, int64_t *cells, int64_t *tiles,
+                            size_t *device_bytes);
+
+/* ---- grid build (replaces the KD-tree over Gaussian centres of the paper's
+ * implementation, supplementary Sec. A.2) -----------------------------------
+ * For every primitive: normalise q, build R(q), s = exp(log_scale) and the
+ * whitening W = diag(1/s) R^T in FP64, rounded once to FP32; then register the
+ * primitive in every occupied cell of `qs` whose box its `cutoff`-sigma
+ * ellipsoid may touch (a conservative separating-axis test in the whitened
+ * frame).  The grid keeps FP32 records {mu, W, Phi} of the field as it is now:
+ * rebuild after any parameter change.  `cutoff` in (0, 16].  If *grid is
+ * non-NULL it must come from an earlier call with the same `qs` and is
+ * rebuilt in place (its buffers grow as needed); otherwise a new handle is
+ * returned.  Synchronises `stream` once (reads back the number of
+ * cell-primitive entries). */
+gpf_status gpf_build_grid(const gpf_field *f, float cutoff, const gpf_queries *qs,
+                          void *stream, gpf_grid **grid);
+void gpf_grid_destroy(gpf_grid *grid);
+/* Host-side facts about a built grid: cell-primitive entries, device bytes. */
+gpf_status gpf_grid_info(const gpf_grid *grid, int64_t *entries, size_t *device_bytes);
+
+/* ---- forward radiance query (Sec. 4.2 aggregation; Alg. S3 local frame) ---
+ * L[i][c] = sum over primitives with m^2 <= cutoff^2 of exp(-m^2/2) rgb[c],
+ * for the q points x[q][3] that were binned into the grid's query set (same
+ * buffer, same contents).  L[q][3] is overwritten; a point with no
+ * contributing primitive gets exactly 0.  `f` must be the field the grid was
+ * built from (same pointers and n), else GPF_ERR_STALE. */
+gpf_status gpf_eval_radiance(const gpf_grid *grid, const gpf_field *f, const float *x, int64_t q,
+                             float *L, void *stream);
+
+/* ---- backward (Sec. 4.2 "Differentiable Accumulation") --------------------
+ * Given dL[q][3] = d(loss)/dL, ADDS d(loss)/d(param) into grad for every
+ * primitive parameter: mu, quat (through its normalisation), log_scale and
+ * rgb.  Kernel weights are recomputed per pair, nothing per pair is stored.
+ * The derivative of the cutoff indicator is taken as zero.  Gradient buffers
+ * must not alias the field.  Accumulation order is not deterministic
+ * (floating-point atomics). */
+gpf_status gpf_eval_radiance_backward(const gpf_grid *grid, const gpf_field *f, const float *x,
+                                      int64_t q, const float *dL, gpf_field_grad *grad,
+                                      void *stream);
+
+/* ---- exact pair count (roofline numerator) --------------------------------
+ * Writes to *pairs (host) the number of (query, primitive) pairs with
+ * m^2 <= cutoff^2.  Synchronises `stream`. */
+gpf_status gpf_count_pairs(const gpf_grid *grid, const gpf_field *f, int64_t *pairs, void *stream);
+
+/* ---- loss (Sec. 4.3 MSE over visible points) ------------------------------
+ * loss_sum[0] (device, FP64) += sum_i sum_c (L - T)^2 over the q points and
+ * dL[q][3] = 2 (L - T) / q.  The caller zeroes loss_sum; MSE = loss_sum / q. */
+gpf_status gpf_mse_loss(const float *L, const float *T, int64_t q, double *loss_sum, float *dL,
+                        void *stream);
+
+/* ---- optimiser (Adam, Kingma & Ba 2015; the paper trains with Adam) ------
+ * One fused Adam update of n FP32 values: m = b1 m + (1-b1) g,
+ * v = b2 v + (1-b2) g^2, p -= lr * (m / (1-b1^t)) / (sqrt(v / (1-b2^t)) + eps).
+ * `step` is the 1-based step count t.  p, g, m, v are distinct buffers of n. */
+gpf_status gpf_adam_step(float *p, const float *g, float *m, float *v, int64_t n, float lr,
+                         float beta1, float beta2, float eps, int64_t step, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GPF_H */

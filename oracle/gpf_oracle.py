@@ -120,7 +120,11 @@ def radiance(mu, quat, log_scale, rgb, x, cutoff=3.0, truncate=True, amb_rel=1e-
                     with |m^2 - cutoff^2| <= amb_rel * rho_i (rho = max s / min s):
                     L_lo takes only their negative parts, L_hi only their
                     positive parts, added to the unambiguous sum;
-      n_amb  [q]    number of ambiguous pairs.
+      n_amb  [q]    number of ambiguous pairs;
+      L_cond [q,3]  sum over contributing pairs of w |Phi| sum_k |u_k| eta_k with
+                    eta_k = sum_j |W_kj d_j|: the first-order effect on L of an
+                    absolute error eta_k in each whitened coordinate (the
+                    rounding scale of u_k in a working precision).
     truncate=False drops the cutoff (the untruncated field)."""
     mu = np.asarray(mu, F64)
     rgb = np.asarray(rgb, F64)
@@ -136,8 +140,9 @@ def radiance(mu, quat, log_scale, rgb, x, cutoff=3.0, truncate=True, amb_rel=1e-
     L_hi = np.zeros((q, 3))
     count = np.zeros(q, np.int64)
     n_amb = np.zeros(q, np.int64)
+    L_cond = np.zeros((q, 3))
     for a, b in _chunks(q, n):
-        _, _, m2 = _pair_terms(x[a:b], mu, W)
+        d, u, m2 = _pair_terms(x[a:b], mu, W)
         if truncate:
             inc = m2 <= c2
             amb = np.abs(m2 - c2) <= amb_rel * rho[None, :]
@@ -147,6 +152,9 @@ def radiance(mu, quat, log_scale, rgb, x, cutoff=3.0, truncate=True, amb_rel=1e-
         qi, pi = np.nonzero(inc | amb)
         w = np.exp(-0.5 * m2[qi, pi])
         contrib = w[:, None] * rgb[pi]
+        eta = np.sum(np.abs(W[pi] * d[qi, pi][:, None, :]), axis=2)
+        sens = np.sum(np.abs(u[qi, pi]) * eta, axis=1)
+        np.add.at(L_cond, a + qi[inc[qi, pi]], (np.abs(contrib) * sens[:, None])[inc[qi, pi]])
         is_inc = inc[qi, pi]
         is_amb = amb[qi, pi]
         order = np.argsort(qi, kind="stable")
@@ -170,7 +178,7 @@ def radiance(mu, quat, log_scale, rgb, x, cutoff=3.0, truncate=True, amb_rel=1e-
                 amb_c = cj[aj, ch]
                 L_lo[a + j, ch] = math.fsum(base + list(np.minimum(amb_c, 0.0)))
                 L_hi[a + j, ch] = math.fsum(base + list(np.maximum(amb_c, 0.0)))
-    return dict(L=L, L_abs=L_abs, count=count, L_lo=L_lo, L_hi=L_hi, n_amb=n_amb)
+    return dict(L=L, L_abs=L_abs, count=count, L_lo=L_lo, L_hi=L_hi, n_amb=n_amb, L_cond=L_cond)
 
 
 def isotropic_radiance(mu, h, rgb, x, cutoff=3.0):
@@ -218,7 +226,13 @@ def radiance_backward(mu, quat, log_scale, rgb, x, g, cutoff=3.0):
       dR[j,k] += -c u_k d_j / s_k,
     then dqhat = sum_jk dR[j,k] dR[j,k]/dqhat and dq = (I - qhat qhat^T) dqhat / |q|.
     Returns dict(mu, quat, log_scale, rgb) of [n,*] float64, plus the same keys
-    with suffix ``_abs``: sums of |per-pair contribution| (error scale)."""
+    with suffix ``_abs``: sums of |per-pair contribution| (error scale), and
+    suffix ``_cond``: the first-order effect on each per-pair contribution of
+    an absolute error eta_k = sum_j |W_kj d_j| in each whitened coordinate u_k,
+    summed as absolute values over pairs.  eta_k is the scale of the rounding
+    error of u_k = W_k . d when it is evaluated in a working precision (one
+    unit roundoff times eta_k), so a caller comparing a single-precision
+    evaluation uses  |err| <= rtol * abs + C * eps_32 * cond."""
     mu = np.asarray(mu, F64)
     rgb = np.asarray(rgb, F64)
     x = np.asarray(x, F64)
@@ -234,6 +248,10 @@ def radiance_backward(mu, quat, log_scale, rgb, x, g, cutoff=3.0):
     as_ = np.zeros((n, 3))
     ap = np.zeros((n, 3))
     aR = np.zeros((n, 3, 3))
+    cm = np.zeros((n, 3))
+    cs = np.zeros((n, 3))
+    cp = np.zeros((n, 3))
+    cR = np.zeros((n, 3, 3))
     c2 = cutoff * cutoff
     for a, b in _chunks(x.shape[0], n):
         d, u, m2 = _pair_terms(x[a:b], mu, W)
@@ -257,13 +275,28 @@ def radiance_backward(mu, quat, log_scale, rgb, x, g, cutoff=3.0):
         np.add.at(am, pi, np.abs(t_m))
         np.add.at(as_, pi, np.abs(t_s))
         np.add.at(aR, pi, np.abs(t_R))
+        # sensitivity of each contribution to the whitened coordinates u_l
+        # (w, c carry exp(-|u|^2/2), so dc/du_l = -c u_l), weighted by eta_l
+        Wp = W[pi]
+        eta = np.sum(np.abs(Wp * dd[:, None, :]), axis=2)                 # [p,l]
+        J_m = c[:, None, None] * Wp - t_m[:, None, :] * uu[:, :, None]     # [p,l,j]
+        np.add.at(cm, pi, np.einsum("plj,pl->pj", np.abs(J_m), eta))
+        eye = np.eye(3)
+        J_s = 2 * (c[:, None] * uu)[:, None, :] * eye[None] - t_s[:, None, :] * uu[:, :, None]
+        np.add.at(cs, pi, np.einsum("plk,pl->pk", np.abs(J_s), eta))
+        np.add.at(cp, pi, np.abs(t_p) * np.sum(np.abs(uu) * eta, axis=1)[:, None])
+        J_R = (-(c[:, None, None] * dd[:, :, None] / s[pi][:, None, :]))[:, None, :, :] * \
+            eye[None, :, None, :] - t_R[:, None, :, :] * uu[:, :, None, None]  # [p,l,j,k]
+        np.add.at(cR, pi, np.einsum("pljk,pl->pjk", np.abs(J_R), eta))
     D = rotation_matrix_grad(qhat)
     gqhat = np.einsum("njk,njkc->nc", gR, D)
     proj = gqhat - np.sum(gqhat * qhat, axis=1, keepdims=True) * qhat
     gq_ = proj / qn[:, None]
     aq = np.einsum("njk,njkc->nc", aR, np.abs(D)) / qn[:, None]
+    cq = np.einsum("njk,njkc->nc", cR, np.abs(D)) / qn[:, None]
     return dict(mu=gm, quat=gq_, log_scale=gs, rgb=gp,
-                mu_abs=am, quat_abs=aq, log_scale_abs=as_, rgb_abs=ap)
+                mu_abs=am, quat_abs=aq, log_scale_abs=as_, rgb_abs=ap,
+                mu_cond=cm, quat_cond=cq, log_scale_cond=cs, rgb_cond=cp)
 
 
 def loss_of_params(mu, quat, log_scale, rgb, x, T, cutoff=3.0):

@@ -1,0 +1,62 @@
+"""Parity bars between an FP32 evaluation and the FP64 oracle (test
+infrastructure only).
+
+Forward: per query and channel |L - L_ref| <= 1e-5 * L_abs + C eps32 L_cond,
+or inside the cutoff-ambiguity envelope [L_lo, L_hi] widened by the same
+amount; a point with no contributing primitive must be exactly 0.
+Gradients: per element |g - g_ref| <= 1e-4 * g_abs + C eps32 g_cond, and per
+parameter group ||g - g_ref||_2 <= 1e-4 ||g_ref||_2.
+
+L_abs / g_abs are sums of |per-pair contributions|; L_cond / g_cond carry the
+first-order effect of rounding the whitened coordinates u_k = W_k . d, whose
+single-precision evaluation has absolute error of order eps32 * sum_j |W_kj d_j|
+(for a thin primitive and a point near its plane that is far larger, relative
+to u_k, than any relative bar).  C = 4 covers the representation error of W
+and the rounding of a three-term fused multiply-add chain.
+"""
+import numpy as np
+
+FWD_RTOL = 1e-5
+GRAD_RTOL = 1e-4
+EPS32 = 2.0 ** -24
+COND_C = 4.0
+
+
+def check_forward(L_gpu, ref, rtol=FWD_RTOL):
+    L_gpu = np.asarray(L_gpu, np.float64)
+    L, L_abs = ref["L"], ref["L_abs"]
+    tol = rtol * np.maximum(L_abs, np.abs(ref["L_hi"])) + COND_C * EPS32 * ref["L_cond"] + 1e-30
+    ok = np.abs(L_gpu - L) <= tol
+    amb = ref["n_amb"] > 0
+    if np.any(amb):
+        lo = ref["L_lo"] - tol
+        hi = ref["L_hi"] + tol
+        ok[amb] |= (L_gpu[amb] >= lo[amb]) & (L_gpu[amb] <= hi[amb])
+    empty = (ref["count"] == 0) & (ref["n_amb"] == 0)
+    ok[empty] = L_gpu[empty] == 0.0
+    bad = np.argwhere(~ok)
+    if bad.size:
+        i, c = bad[0]
+        raise AssertionError(
+            f"{len(bad)} forward mismatches; first q={i} c={c} gpu={L_gpu[i, c]!r} "
+            f"ref={L[i, c]!r} abs={L_abs[i, c]!r} count={ref['count'][i]} amb={ref['n_amb'][i]}")
+    return int(np.sum(amb))
+
+
+def check_grads(gpu, ref, rows=None, rtol=GRAD_RTOL):
+    for name in ("mu", "quat", "log_scale", "rgb"):
+        g = np.asarray(gpu[name], np.float64)
+        r, a, c = ref[name], ref[name + "_abs"], ref[name + "_cond"]
+        if rows is not None:
+            g, r, a, c = g[rows], r[rows], a[rows], c[rows]
+        err = np.abs(g - r)
+        tol = rtol * a + COND_C * EPS32 * c + 1e-30
+        bad = np.argwhere(err > tol)
+        if bad.size:
+            b = tuple(bad[0])
+            raise AssertionError(f"{name}: {len(bad)} elements off; first {b} gpu={g[b]!r} "
+                                 f"ref={r[b]!r} abs={a[b]!r} cond={c[b]!r}")
+        nr = np.linalg.norm(r)
+        ne = np.linalg.norm(g - r)
+        if ne > rtol * nr:
+            raise AssertionError(f"{name}: group error {ne / nr:.3g} above {rtol}")

@@ -1,0 +1,309 @@
+// Query binning: sort the (static) visible points by grid cell and by a Morton
+// code inside the cell, then cut every cell's run into tiles of <= 64 points
+// with a tight bounding box each.  Runs once per query set.
+#include <rocprim/device/device_radix_sort.hpp>
+
+#include <algorithm>
+#include <cmath>
+
+#include "common.h"
+#include "scan.h"
+
+namespace gpf {
+namespace {
+
+constexpr int kRedBlocks = 256;
+constexpr int kMaxDim = 1024;            // cells per axis (10-bit Morton)
+constexpr int64_t kMaxDense = 1 << 26;   // dense cell table entries
+
+__device__ __forceinline__ uint64_t spread3(uint32_t v) {
+  uint64_t x = v & 0x3ff;
+  x = (x | (x << 16)) & 0x030000FFull;
+  x = (x | (x << 8)) & 0x0300F00Full;
+  x = (x | (x << 4)) & 0x030C30C3ull;
+  x = (x | (x << 2)) & 0x09249249ull;
+  return x;
+}
+
+__device__ __forceinline__ uint64_t morton3(uint32_t a, uint32_t b, uint32_t c) {
+  return spread3(a) | (spread3(b) << 1) | (spread3(c) << 2);
+}
+
+__global__ void bbox_partial_kernel(const float* __restrict__ x, int64_t q, float* part) {
+  float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < q;
+       i += (int64_t)gridDim.x * blockDim.x) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      float v = x[i * 3 + a];
+      lo[a] = fminf(lo[a], v);
+      hi[a] = fmaxf(hi[a], v);
+    }
+  }
+  __shared__ float s[6][256];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    s[a][threadIdx.x] = lo[a];
+    s[3 + a][threadIdx.x] = hi[a];
+  }
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        s[a][threadIdx.x] = fminf(s[a][threadIdx.x], s[a][threadIdx.x + st]);
+        s[3 + a][threadIdx.x] = fmaxf(s[3 + a][threadIdx.x], s[3 + a][threadIdx.x + st]);
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < 6) part[blockIdx.x * 6 + threadIdx.x] = s[threadIdx.x][0];
+}
+
+__global__ void bbox_final_kernel(const float* part, int nparts, float* out) {
+  int a = threadIdx.x;
+  if (a >= 6) return;
+  float v = part[a];
+  for (int b = 1; b < nparts; ++b) v = a < 3 ? fminf(v, part[b * 6 + a]) : fmaxf(v, part[b * 6 + a]);
+  out[a] = v;
+}
+
+struct GridGeom {
+  float ox, oy, oz, inv;
+  int dx, dy, dz;
+};
+
+__device__ __forceinline__ void cell_of(const GridGeom& g, float x, float y, float z, int* c,
+                                        float* f) {
+  float p[3] = {(x - g.ox) * g.inv, (y - g.oy) * g.inv, (z - g.oz) * g.inv};
+  int d[3] = {g.dx, g.dy, g.dz};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    int ci = (int)floorf(p[a]);
+    ci = min(max(ci, 0), d[a] - 1);
+    c[a] = ci;
+    f[a] = fminf(fmaxf(p[a] - (float)ci, 0.f), 0.99999994f);
+  }
+}
+
+__global__ void key_kernel(const float* __restrict__ x, int64_t q, GridGeom g, uint64_t* keys,
+                           int* idx) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= q) return;
+  int c[3];
+  float f[3];
+  cell_of(g, x[i * 3], x[i * 3 + 1], x[i * 3 + 2], c, f);
+  uint64_t cm = morton3(c[0], c[1], c[2]);
+  uint64_t sm = morton3((uint32_t)(f[0] * 1024.f), (uint32_t)(f[1] * 1024.f), (uint32_t)(f[2] * 1024.f));
+  keys[i] = (cm << 30) | sm;
+  idx[i] = (int)i;
+}
+
+__global__ void gather_kernel(const float* __restrict__ x, const uint64_t* __restrict__ keys,
+                              const int* __restrict__ perm, int64_t q, float4* xs, int* flag) {
+  int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k >= q) return;
+  int i = perm[k];
+  xs[k] = make_float4(x[(int64_t)i * 3], x[(int64_t)i * 3 + 1], x[(int64_t)i * 3 + 2], 0.f);
+  flag[k] = (k == 0 || (keys[k] >> 30) != (keys[k - 1] >> 30)) ? 1 : 0;
+}
+
+// flag[] was exclusive-scanned in place: slot of point k = scanned[k] for a
+// run start.  Records the first point and dense cell of each occupied slot.
+__global__ void cell_runs_kernel(const float4* __restrict__ xs, const uint64_t* __restrict__ keys,
+                                 const int* __restrict__ scanned, int64_t q, GridGeom g,
+                                 int* cell_first, int* occ_dense) {
+  int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k >= q) return;
+  bool start = (k == 0 || (keys[k] >> 30) != (keys[k - 1] >> 30));
+  if (!start) return;
+  int slot = scanned[k];
+  float4 p = xs[k];
+  int c[3];
+  float f[3];
+  cell_of(g, p.x, p.y, p.z, c, f);
+  cell_first[slot] = (int)k;
+  occ_dense[slot] = (c[2] * g.dy + c[1]) * g.dx + c[0];
+}
+
+__global__ void occ_table_kernel(const int* __restrict__ occ_dense, int ncells, int* occ_of_dense) {
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < ncells) occ_of_dense[occ_dense[s]] = s;
+}
+
+__global__ void tiles_per_cell_kernel(const int* __restrict__ cell_first, int ncells, int q,
+                                      int* ntile) {
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= ncells) return;
+  int end = (s + 1 < ncells) ? cell_first[s + 1] : q;
+  int cnt = end - cell_first[s];
+  ntile[s] = (cnt + kTile - 1) / kTile;
+}
+
+__global__ void tiles_fill_kernel(const int* __restrict__ cell_first, const int* __restrict__ toff,
+                                  int ncells, int q, TileInfo* tiles) {
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= ncells) return;
+  int start = cell_first[s];
+  int end = (s + 1 < ncells) ? cell_first[s + 1] : q;
+  int t = toff[s];
+  for (int a = start; a < end; a += kTile, ++t) {
+    TileInfo ti;
+    ti.start = a;
+    ti.count = min(kTile, end - a);
+    ti.cell = s;
+    ti.pad = 0;
+    tiles[t] = ti;
+  }
+}
+
+// One wave per tile: tight box of its points.
+__global__ void __launch_bounds__(256) tile_box_kernel(const float4* __restrict__ xs,
+                                                       const TileInfo* __restrict__ tiles,
+                                                       int ntiles, float4* lo, float4* hi) {
+  int t = blockIdx.x * 4 + (threadIdx.x >> 6);
+  int lane = threadIdx.x & 63;
+  if (t >= ntiles) return;
+  TileInfo ti = tiles[t];
+  float4 p = xs[ti.start + min(lane, ti.count - 1)];
+  float l[3] = {p.x, p.y, p.z}, h[3] = {p.x, p.y, p.z};
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      l[a] = fminf(l[a], __shfl_xor(l[a], off, 64));
+      h[a] = fmaxf(h[a], __shfl_xor(h[a], off, 64));
+    }
+  }
+  if (lane == 0) {
+    lo[t] = make_float4(l[0], l[1], l[2], 0.f);
+    hi[t] = make_float4(h[0], h[1], h[2], 0.f);
+  }
+}
+
+}  // namespace
+
+gpf_status launch_bin_queries(const float* x, int64_t q, float cell, hipStream_t s,
+                              gpf_queries* out) {
+  out->x_user = x;
+  out->q = q;
+  out->cell = cell;
+  // 1. bounding box
+  float* part = nullptr;
+  gpf_status st = dev_alloc((void**)&part, (kRedBlocks * 6 + 6) * sizeof(float), "bbox");
+  if (st != GPF_OK) return st;
+  hipLaunchKernelGGL(bbox_partial_kernel, dim3(kRedBlocks), dim3(256), 0, s, x, q, part);
+  hipLaunchKernelGGL(bbox_final_kernel, dim3(1), dim3(64), 0, s, part, kRedBlocks,
+                     part + kRedBlocks * 6);
+  float box[6];
+  hipError_t e = hipMemcpyAsync(box, part + kRedBlocks * 6, sizeof(box), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  dev_free(part, (kRedBlocks * 6 + 6) * sizeof(float));
+  if (e != hipSuccess) return hip_fail(e, "bin_queries bbox");
+  for (int a = 0; a < 6; ++a)
+    if (!std::isfinite(box[a]))
+      return set_error(GPF_ERR_INVALID_ARGUMENT, "query points contain NaN or Inf");
+  int64_t dense = 1;
+  for (int a = 0; a < 3; ++a) {
+    out->origin[a] = box[a];
+    double ext = (double)box[3 + a] - (double)box[a];
+    int64_t d = (int64_t)std::floor(ext / cell) + 1;
+    if (d > kMaxDim)
+      return set_error(GPF_ERR_CAPACITY, "cell_size too small: more than 1024 cells per axis");
+    out->dims[a] = (int)d;
+    dense *= d;
+  }
+  if (dense > kMaxDense)
+    return set_error(GPF_ERR_CAPACITY, "cell_size too small: more than 2^26 cells");
+  GridGeom g{out->origin[0], out->origin[1], out->origin[2], 1.f / cell, out->dims[0],
+             out->dims[1], out->dims[2]};
+
+  // 2. keys and sort
+  uint64_t *keys = nullptr, *keys_s = nullptr;
+  int* idx = nullptr;
+  void* tmp = nullptr;
+  size_t tmp_bytes = 0;
+  int* flag = nullptr;
+  int* cell_first = nullptr;
+  int* ntile = nullptr;
+  auto cleanup = [&]() {
+    dev_free(keys, q * 8);
+    dev_free(keys_s, q * 8);
+    dev_free(idx, q * 4);
+    dev_free(tmp, tmp_bytes);
+    dev_free(flag, (q + 1) * 4);
+    dev_free(cell_first, (q + 1) * 4);
+    dev_free(ntile, (q + 1) * 4);
+  };
+#define TRY(x)              \
+  do {                      \
+    gpf_status s_ = (x);    \
+    if (s_ != GPF_OK) {     \
+      cleanup();            \
+      return s_;            \
+    }                       \
+  } while (0)
+#define TRYH(x, what)                               \
+  do {                                              \
+    hipError_t e_ = (x);                            \
+    if (e_ != hipSuccess) {                         \
+      cleanup();                                    \
+      return hip_fail(e_, what);                    \
+    }                                               \
+  } while (0)
+  TRY(dev_alloc((void**)&keys, q * 8, "keys"));
+  TRY(dev_alloc((void**)&keys_s, q * 8, "keys"));
+  TRY(dev_alloc((void**)&idx, q * 4, "idx"));
+  TRY(dev_alloc((void**)&out->perm, q * 4, "perm"));
+  TRY(dev_alloc((void**)&out->xs, q * sizeof(float4), "xs"));
+  TRY(dev_alloc((void**)&flag, (q + 1) * 4, "flag"));
+  int nb = (int)((q + 255) / 256);
+  hipLaunchKernelGGL(key_kernel, dim3(nb), dim3(256), 0, s, x, q, g, keys, idx);
+  TRYH(rocprim::radix_sort_pairs(nullptr, tmp_bytes, keys, keys_s, idx, out->perm, (size_t)q, 0, 60,
+                                 s),
+       "radix_sort size");
+  TRY(dev_alloc(&tmp, tmp_bytes, "sort scratch"));
+  TRYH(rocprim::radix_sort_pairs(tmp, tmp_bytes, keys, keys_s, idx, out->perm, (size_t)q, 0, 60, s),
+       "radix_sort");
+  hipLaunchKernelGGL(gather_kernel, dim3(nb), dim3(256), 0, s, x, keys_s, out->perm, q, out->xs,
+                     flag);
+  hipLaunchKernelGGL(scan_exclusive_kernel, dim3(1), dim3(kScanThreads), 0, s, flag, flag, (int)q);
+  int ncells = 0;
+  TRYH(hipMemcpyAsync(&ncells, flag + q, 4, hipMemcpyDeviceToHost, s), "ncells readback");
+  TRYH(hipStreamSynchronize(s), "ncells sync");
+  out->ncells = ncells;
+  TRY(dev_alloc((void**)&cell_first, (int64_t)(ncells + 1) * 4, "cell_first"));
+  TRY(dev_alloc((void**)&out->occ_dense, (int64_t)ncells * 4, "occ_dense"));
+  TRY(dev_alloc((void**)&out->occ_of_dense, dense * 4, "occ_of_dense"));
+  hipLaunchKernelGGL(cell_runs_kernel, dim3(nb), dim3(256), 0, s, out->xs, keys_s, flag, q, g,
+                     cell_first, out->occ_dense);
+  TRYH(hipMemsetAsync(out->occ_of_dense, 0xff, dense * 4, s), "occ table clear");
+  int cb = (ncells + 255) / 256;
+  hipLaunchKernelGGL(occ_table_kernel, dim3(cb), dim3(256), 0, s, out->occ_dense, ncells,
+                     out->occ_of_dense);
+  TRY(dev_alloc((void**)&ntile, (int64_t)(ncells + 1) * 4, "ntile"));
+  hipLaunchKernelGGL(tiles_per_cell_kernel, dim3(cb), dim3(256), 0, s, cell_first, ncells, (int)q,
+                     ntile);
+  hipLaunchKernelGGL(scan_exclusive_kernel, dim3(1), dim3(kScanThreads), 0, s, ntile, ntile, ncells);
+  int ntiles = 0;
+  TRYH(hipMemcpyAsync(&ntiles, ntile + ncells, 4, hipMemcpyDeviceToHost, s), "ntiles readback");
+  TRYH(hipStreamSynchronize(s), "ntiles sync");
+  out->ntiles = ntiles;
+  TRY(dev_alloc((void**)&out->tiles, (int64_t)ntiles * sizeof(TileInfo), "tiles"));
+  TRY(dev_alloc((void**)&out->tile_lo, (int64_t)ntiles * sizeof(float4), "tile_lo"));
+  TRY(dev_alloc((void**)&out->tile_hi, (int64_t)ntiles * sizeof(float4), "tile_hi"));
+  hipLaunchKernelGGL(tiles_fill_kernel, dim3(cb), dim3(256), 0, s, cell_first, ntile, ncells, (int)q,
+                     out->tiles);
+  hipLaunchKernelGGL(tile_box_kernel, dim3((ntiles + 3) / 4), dim3(256), 0, s, out->xs, out->tiles,
+                     ntiles, out->tile_lo, out->tile_hi);
+  TRYH(hipGetLastError(), "bin_queries launch");
+  TRYH(hipStreamSynchronize(s), "bin_queries sync");
+  cleanup();
+#undef TRY
+#undef TRYH
+  out->bytes = q * (sizeof(float4) + 4) + dense * 4 + (int64_t)ncells * 4 +
+               (int64_t)ntiles * (sizeof(TileInfo) + 2 * sizeof(float4));
+  return GPF_OK;
+}
+
+}  // namespace gpf

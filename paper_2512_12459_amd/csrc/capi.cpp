@@ -1,0 +1,249 @@
+// C ABI entry points: argument validation, handle lifetime, error reporting.
+// Every compute step runs in the HIP kernels of the sibling .hip files.
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <string>
+
+#include "common.h"
+
+namespace gpf {
+
+static thread_local std::string g_last_error;
+
+gpf_status set_error(gpf_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+gpf_status hip_fail(hipError_t e, const char* what) {
+  if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) {
+    (void)hipGetLastError();
+    return set_error(GPF_ERR_OUT_OF_MEMORY, std::string(what) + ": " + hipGetErrorString(e));
+  }
+  return set_error(GPF_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// Optional cap on the bytes this library holds on the device at once, read
+// from GPF_DEVICE_BYTES_LIMIT; lets tests force the out-of-memory path.
+static std::mutex g_mem_mu;
+static size_t g_mem_used = 0;
+
+static size_t byte_limit() {
+  const char* s = std::getenv("GPF_DEVICE_BYTES_LIMIT");
+  if (!s || !*s) return SIZE_MAX;
+  return (size_t)std::strtoull(s, nullptr, 10);
+}
+
+gpf_status dev_alloc(void** p, size_t bytes, const char* what) {
+  *p = nullptr;
+  if (bytes == 0) bytes = 16;
+  {
+    std::lock_guard<std::mutex> lk(g_mem_mu);
+    if (g_mem_used + bytes > byte_limit())
+      return set_error(GPF_ERR_OUT_OF_MEMORY,
+                       std::string(what) + ": device byte budget exceeded");
+    g_mem_used += bytes;
+  }
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    std::lock_guard<std::mutex> lk(g_mem_mu);
+    g_mem_used -= bytes;
+    *p = nullptr;
+    return hip_fail(e, what);
+  }
+  return GPF_OK;
+}
+
+void dev_free(void* p, size_t bytes) {
+  if (!p) return;
+  (void)hipFree(p);
+  if (bytes == 0) bytes = 16;
+  std::lock_guard<std::mutex> lk(g_mem_mu);
+  g_mem_used -= bytes;
+}
+
+static bool field_ok(const gpf_field* f, std::string* why) {
+  if (!f) { *why = "field is NULL"; return false; }
+  if (f->n < 1 || f->n > (int64_t)INT32_MAX) { *why = "field n out of range [1, 2^31-1]"; return false; }
+  if (!f->mu || !f->quat || !f->log_scale || !f->rgb) { *why = "field has a NULL array"; return false; }
+  return true;
+}
+
+static gpf_status check_grid_use(const gpf_grid* g, const gpf_field* f, const float* x, int64_t q) {
+  if (!g) return set_error(GPF_ERR_INVALID_ARGUMENT, "grid is NULL");
+  std::string why;
+  if (!field_ok(f, &why)) return set_error(GPF_ERR_INVALID_ARGUMENT, why);
+  if (!x) return set_error(GPF_ERR_INVALID_ARGUMENT, "x is NULL");
+  if (g->mu != f->mu || g->quat != f->quat || g->log_scale != f->log_scale ||
+      g->rgb != f->rgb || g->n != f->n)
+    return set_error(GPF_ERR_STALE, "field differs from the one the grid was built from");
+  if (x != g->qs->x_user || q != g->qs->q)
+    return set_error(GPF_ERR_STALE, "query points differ from the binned query set");
+  return GPF_OK;
+}
+
+}  // namespace gpf
+
+using namespace gpf;
+
+extern "C" {
+
+const char* gpf_last_error(void) { return g_last_error.c_str(); }
+const char* gpf_version(void) { return "gpf 0.1 gfx950"; }
+
+gpf_status gpf_bin_queries(const float* x, int64_t q, float cell_size, void* stream,
+                           gpf_queries** out) {
+  if (!out) return set_error(GPF_ERR_INVALID_ARGUMENT, "out is NULL");
+  *out = nullptr;
+  if (!x) return set_error(GPF_ERR_INVALID_ARGUMENT, "x is NULL");
+  if (q < 1 || q > (int64_t)INT32_MAX - 64)
+    return set_error(GPF_ERR_INVALID_ARGUMENT, "q out of range [1, 2^31-65]");
+  if (!(cell_size > 0.f) || !(cell_size < 1e30f))
+    return set_error(GPF_ERR_INVALID_ARGUMENT, "cell_size must be positive and finite");
+  gpf_queries* qs = new gpf_queries();
+  GPF_HIP(hipGetDevice(&qs->device));
+  gpf_status st = launch_bin_queries(x, q, cell_size, (hipStream_t)stream, qs);
+  if (st != GPF_OK) {
+    gpf_queries_destroy(qs);
+    return st;
+  }
+  *out = qs;
+  return GPF_OK;
+}
+
+void gpf_queries_destroy(gpf_queries* qs) {
+  if (!qs) return;
+  int64_t nd = (int64_t)qs->dims[0] * qs->dims[1] * qs->dims[2];
+  dev_free(qs->xs, qs->q * sizeof(float4));
+  dev_free(qs->perm, qs->q * sizeof(int));
+  dev_free(qs->occ_of_dense, nd * sizeof(int));
+  dev_free(qs->occ_dense, qs->ncells * sizeof(int));
+  dev_free(qs->tiles, qs->ntiles * sizeof(TileInfo));
+  dev_free(qs->tile_lo, qs->ntiles * sizeof(float4));
+  dev_free(qs->tile_hi, qs->ntiles * sizeof(float4));
+  delete qs;
+}
+
+gpf_status gpf_queries_info(const gpf_queries* qs, int64_t* q, int64_t* cells, int64_t* tiles,
+                            size_t* device_bytes) {
+  if (!qs) return set_error(GPF_ERR_INVALID_ARGUMENT, "query set is NULL");
+  if (q) *q = qs->q;
+  if (cells) *cells = qs->ncells;
+  if (tiles) *tiles = qs->ntiles;
+  if (device_bytes) *device_bytes = qs->bytes;
+  return GPF_OK;
+}
+
+gpf_status gpf_build_grid(const gpf_field* f, float cutoff, const gpf_queries* qs, void* stream,
+                          gpf_grid** grid) {
+  if (!grid) return set_error(GPF_ERR_INVALID_ARGUMENT, "grid out-pointer is NULL");
+  std::string why;
+  if (!field_ok(f, &why)) return set_error(GPF_ERR_INVALID_ARGUMENT, why);
+  if (!qs) return set_error(GPF_ERR_INVALID_ARGUMENT, "query set is NULL");
+  if (!(cutoff > 0.f) || !(cutoff <= 16.f))
+    return set_error(GPF_ERR_INVALID_ARGUMENT, "cutoff must lie in (0, 16]");
+  gpf_grid* g = *grid;
+  bool fresh = (g == nullptr);
+  if (!fresh && g->qs != qs)
+    return set_error(GPF_ERR_STALE, "grid was built for a different query set");
+  if (fresh) g = new gpf_grid();
+  g->qs = qs;
+  g->mu = f->mu;
+  g->quat = f->quat;
+  g->log_scale = f->log_scale;
+  g->rgb = f->rgb;
+  g->n = f->n;
+  g->cutoff = cutoff;
+  gpf_status st = launch_build_grid(g, (hipStream_t)stream);
+  if (st != GPF_OK) {
+    if (fresh) gpf_grid_destroy(g);
+    else g->n = -1;  // poison: the handle no longer matches any field
+    return st;
+  }
+  *grid = g;
+  return GPF_OK;
+}
+
+void gpf_grid_destroy(gpf_grid* g) {
+  if (!g) return;
+  int64_t nc = g->qs ? g->qs->ncells + 1 : 0;
+  dev_free(g->rec, g->rec_cap * sizeof(PrimRec));
+  dev_free(g->ext, g->rec_cap * sizeof(float4));
+  dev_free(g->cell_count, nc * sizeof(int));
+  dev_free(g->cell_start, nc * sizeof(int));
+  dev_free(g->cell_prims, g->cap * sizeof(int));
+  delete g;
+}
+
+gpf_status gpf_grid_info(const gpf_grid* g, int64_t* entries, size_t* device_bytes) {
+  if (!g) return set_error(GPF_ERR_INVALID_ARGUMENT, "grid is NULL");
+  if (entries) *entries = g->entries;
+  if (device_bytes) *device_bytes = g->bytes;
+  return GPF_OK;
+}
+
+gpf_status gpf_eval_radiance(const gpf_grid* g, const gpf_field* f, const float* x, int64_t q,
+                             float* L, void* stream) {
+  gpf_status st = check_grid_use(g, f, x, q);
+  if (st != GPF_OK) return st;
+  if (!L) return set_error(GPF_ERR_INVALID_ARGUMENT, "L is NULL");
+  return launch_eval_fwd(g, L, (hipStream_t)stream);
+}
+
+gpf_status gpf_eval_radiance_backward(const gpf_grid* g, const gpf_field* f, const float* x,
+                                      int64_t q, const float* dL, gpf_field_grad* grad,
+                                      void* stream) {
+  gpf_status st = check_grid_use(g, f, x, q);
+  if (st != GPF_OK) return st;
+  if (!dL) return set_error(GPF_ERR_INVALID_ARGUMENT, "dL is NULL");
+  if (!grad || !grad->mu || !grad->quat || !grad->log_scale || !grad->rgb)
+    return set_error(GPF_ERR_INVALID_ARGUMENT, "gradient buffers must be non-NULL");
+  const void* fp[4] = {f->mu, f->quat, f->log_scale, f->rgb};
+  const void* gp[4] = {grad->mu, grad->quat, grad->log_scale, grad->rgb};
+  for (auto a : fp)
+    for (auto b : gp)
+      if (a == b) return set_error(GPF_ERR_INVALID_ARGUMENT, "gradient buffer aliases the field");
+  return launch_eval_bwd(g, dL, grad, (hipStream_t)stream);
+}
+
+gpf_status gpf_count_pairs(const gpf_grid* g, const gpf_field* f, int64_t* pairs, void* stream) {
+  if (!g) return set_error(GPF_ERR_INVALID_ARGUMENT, "grid is NULL");
+  if (!pairs) return set_error(GPF_ERR_INVALID_ARGUMENT, "pairs is NULL");
+  gpf_status st = check_grid_use(g, f, g->qs->x_user, g->qs->q);
+  if (st != GPF_OK) return st;
+  unsigned long long* d = nullptr;
+  st = dev_alloc((void**)&d, sizeof(*d), "count_pairs");
+  if (st != GPF_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  unsigned long long h = 0;
+  st = launch_count_pairs(g, d, s);
+  if (st == GPF_OK) {
+    hipError_t e = hipMemcpyAsync(&h, d, sizeof(h), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) st = hip_fail(e, "count_pairs readback");
+  }
+  dev_free(d, sizeof(*d));
+  if (st == GPF_OK) *pairs = (int64_t)h;
+  return st;
+}
+
+gpf_status gpf_mse_loss(const float* L, const float* T, int64_t q, double* loss_sum, float* dL,
+                        void* stream) {
+  if (!L || !T || !loss_sum || !dL) return set_error(GPF_ERR_INVALID_ARGUMENT, "NULL argument");
+  if (q < 1) return set_error(GPF_ERR_INVALID_ARGUMENT, "q must be >= 1");
+  return launch_mse(L, T, q, loss_sum, dL, (hipStream_t)stream);
+}
+
+gpf_status gpf_adam_step(float* p, const float* g, float* m, float* v, int64_t n, float lr,
+                         float beta1, float beta2, float eps, int64_t step, void* stream) {
+  if (!p || !g || !m || !v) return set_error(GPF_ERR_INVALID_ARGUMENT, "NULL argument");
+  if (n < 0) return set_error(GPF_ERR_INVALID_ARGUMENT, "n must be >= 0");
+  if (step < 1) return set_error(GPF_ERR_INVALID_ARGUMENT, "step must be >= 1");
+  if (!(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps >= 0.f))
+    return set_error(GPF_ERR_INVALID_ARGUMENT, "bad Adam hyper-parameters");
+  if (n == 0) return GPF_OK;
+  return launch_adam(p, g, m, v, n, lr, beta1, beta2, eps, step, (hipStream_t)stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,110 @@
+// Internal definitions shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string>
+
+#include "../../include/gpf.h"
+
+namespace gpf {
+
+// Queries per tile: one wave64 evaluates one tile.
+constexpr int kTile = 64;
+// Scale folded into the whitening rows: u' = kappa * u with kappa^2 = log2(e)/2,
+// so that exp(-m^2/2) = exp2(-|u'|^2).
+constexpr double kKappa2 = 0.72134752044448170368;  // 0.5 * log2(e)
+
+// Primitive record (64 bytes): r0 = {mu, Phi_r}, r1 = {W'_0, Phi_g},
+// r2 = {W'_1, Phi_b}, r3 = {W'_2, 0}; W'_k is row k of kappa * diag(1/s) R^T.
+struct alignas(16) PrimRec {
+  float4 r0, r1, r2, r3;
+};
+
+// Tile descriptor: queries [start, start+count) of the sorted order, all in
+// occupied cell `cell`.
+struct alignas(16) TileInfo {
+  int start, count, cell, pad;
+};
+
+}  // namespace gpf
+
+struct gpf_queries {
+  int device = 0;
+  const float* x_user = nullptr;  // binned buffer (identity check only)
+  int64_t q = 0;
+  float origin[3] = {0, 0, 0};
+  float cell = 0;
+  int dims[3] = {0, 0, 0};
+  int64_t ncells = 0;   // occupied cells
+  int64_t ntiles = 0;
+  float4* xs = nullptr;          // [q] sorted points (w unused)
+  int* perm = nullptr;           // [q] sorted position -> caller index
+  int* occ_of_dense = nullptr;   // [dims product] dense cell -> occupied slot or -1
+  int* occ_dense = nullptr;      // [ncells] occupied slot -> dense cell
+  gpf::TileInfo* tiles = nullptr;  // [ntiles]
+  float4* tile_lo = nullptr;     // [ntiles] tight box of the tile's points
+  float4* tile_hi = nullptr;
+  size_t bytes = 0;
+};
+
+struct gpf_grid {
+  const gpf_queries* qs = nullptr;
+  const float *mu = nullptr, *quat = nullptr, *log_scale = nullptr, *rgb = nullptr;
+  int64_t n = 0;
+  float cutoff = 3.f;
+  gpf::PrimRec* rec = nullptr;  // [n]
+  float4* ext = nullptr;        // [n] half-extents of the cutoff box; w = 1 if valid
+  int64_t rec_cap = 0;
+  int* cell_count = nullptr;    // [ncells + 1]
+  int* cell_start = nullptr;    // [ncells + 1]
+  int* cell_prims = nullptr;    // [cap]
+  int64_t cap = 0;
+  int64_t entries = 0;
+  size_t bytes = 0;
+};
+
+namespace gpf {
+
+// Error plumbing (capi.cpp).
+gpf_status set_error(gpf_status s, const std::string& msg);
+gpf_status hip_fail(hipError_t e, const char* what);
+#define GPF_HIP(call)                                         \
+  do {                                                        \
+    hipError_t e_ = (call);                                   \
+    if (e_ != hipSuccess) return ::gpf::hip_fail(e_, #call);  \
+  } while (0)
+
+// Device allocation under an optional byte budget (GPF_DEVICE_BYTES_LIMIT).
+gpf_status dev_alloc(void** p, size_t bytes, const char* what);
+void dev_free(void* p, size_t bytes);
+
+// Launchers implemented in the .hip files.  They only enqueue work.
+gpf_status launch_bin_queries(const float* x, int64_t q, float cell, hipStream_t s,
+                              gpf_queries* out);
+gpf_status launch_build_grid(gpf_grid* g, hipStream_t s);
+gpf_status launch_eval_fwd(const gpf_grid* g, float* L, hipStream_t s);
+gpf_status launch_eval_bwd(const gpf_grid* g, const float* dL, gpf_field_grad* grad,
+                           hipStream_t s);
+gpf_status launch_count_pairs(const gpf_grid* g, unsigned long long* d_count, hipStream_t s);
+gpf_status launch_mse(const float* L, const float* T, int64_t q, double* loss, float* dL,
+                      hipStream_t s);
+gpf_status launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr,
+                       float b1, float b2, float eps, int64_t step, hipStream_t s);
+
+// Workgroup -> tile remap so that each XCD (workgroups are dealt round-robin
+// over the 8 XCDs) walks a contiguous, spatially coherent range of tiles and
+// its L2 keeps the same primitives hot.
+__device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
+  const int kXcd = 8;
+  int per = (nblocks + kXcd - 1) / kXcd;
+  int xcd = bid % kXcd;
+  int idx = bid / kXcd;
+  // The first (nblocks % 8) XCDs get `per` blocks, the rest `per - 1`.
+  int full = nblocks % kXcd;
+  if (full == 0) full = kXcd;
+  int base = xcd < full ? xcd * per : full * per + (xcd - full) * (per - 1);
+  return base + idx;
+}
+
+}  // namespace gpf

@@ -1,0 +1,265 @@
+"""GPU parity: the HIP radiance query, its backward and helpers against the
+FP64 oracle, on the 4,096-Gaussian single-camera workload (all 16,384 points:
+many tiles, a ragged last tile per cell) and on edge cases."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import gpf_oracle as O
+from paper_2512_12459_amd import scenes as S
+from tests.gpu_helpers import check_forward, check_grads, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rad():
+    from paper_2512_12459_amd import radiance
+    radiance.C.lib()   # fail loudly if the library is missing
+    assert torch.cuda.is_available(), "GPU test needs a GPU"
+    return radiance
+
+
+@pytest.fixture(scope="module")
+def c1():
+    f, x = S.workload("plain4k")
+    ref = O.radiance(*f.arrays(), x)
+    return f, x, ref
+
+
+def _eval(rad, f_arrays, x, cell=0.025):
+    mu, q, ls, rgb = to_dev(*f_arrays)
+    (xd,) = to_dev(x)
+    qs = rad.QuerySet(xd, cell)
+    g = rad.Grid(qs).build(mu, q, ls, rgb)
+    L = rad.eval_radiance(g, mu, q, ls, rgb)
+    torch.cuda.synchronize()
+    return L.cpu().numpy(), g, (mu, q, ls, rgb), qs
+
+
+def test_c1_forward_all_points(rad, c1):
+    f, x, ref = c1
+    say("case: plain4k forward, 16384 points, cell 0.025")
+    L, g, _, qs = _eval(rad, f.arrays(), x)
+    info = qs.info()
+    assert info["tiles"] > 256 and info["cells"] > 50
+    check_forward(L, ref)
+
+
+@pytest.mark.parametrize("cell", [0.0125, 0.05, 0.1])
+def test_c1_grid_invariance(rad, c1, cell):
+    f, x, ref = c1
+    say(f"case: plain4k forward, cell {cell}")
+    L, *_ = _eval(rad, f.arrays(), x, cell)
+    check_forward(L, ref)
+
+
+def test_c1_reading_b_forward(rad):
+    f, x = S.workload("plain4k", reading="b")
+    ref = O.radiance(*f.arrays(), x)
+    say("case: plain4k reading b forward")
+    L, *_ = _eval(rad, f.arrays(), x)
+    check_forward(L, ref)
+    assert ref["count"].mean() > 3
+
+
+def test_count_pairs_exact(rad, c1):
+    f, x, ref = c1
+    say("case: plain4k pair count")
+    _, g, *_ = _eval(rad, f.arrays(), x)
+    n = g.count_pairs()
+    lo = int(np.sum(ref["count"]) - np.sum(ref["n_amb"]))
+    hi = int(np.sum(ref["count"]) + np.sum(ref["n_amb"]))
+    assert lo <= n <= hi
+
+
+def test_edge_cases(rad):
+    rng = np.random.default_rng(0)
+    # n = 1, ragged single tile of 65 points, with points outside the support
+    mu = np.array([[0.5, 0.5, 0.5]])
+    q = np.array([[0.9, 0.2, -0.1, 0.3]])
+    ls = np.log(np.array([[0.05, 0.02, 0.004]]))
+    rgb = np.array([[1.0, 2.0, 0.5]])
+    x = 0.5 + rng.normal(0, 0.04, (65, 3))
+    x[0] = [5.0, 5.0, 5.0]
+    # both sides consume the same FP32 values
+    mu, q, ls, rgb, x = (a.astype(np.float32) for a in (mu, q, ls, rgb, x))
+    ref = O.radiance(mu, q, ls, rgb, x)
+    say("case: n=1, q=65")
+    L, *_ = _eval(rad, (mu, q, ls, rgb), x)
+    check_forward(L, ref)
+    assert L[0].tolist() == [0.0, 0.0, 0.0]
+    # a single query point
+    say("case: q=1")
+    L, *_ = _eval(rad, (mu, q, ls, rgb), x[1:2])
+    check_forward(L, O.radiance(mu, q, ls, rgb, x[1:2]))
+    # a crowded cell: 3000 primitives on one spot (survivor list overflows and
+    # is flushed several times), with repeated query points
+    n = 3000
+    mu = 0.5 + rng.normal(0, 0.002, (n, 3))
+    q = rng.normal(size=(n, 4))
+    ls = np.log(0.01) + rng.normal(0, 0.2, (n, 3))
+    rgb = np.exp(rng.normal(0, 1, (n, 3)))
+    x = np.concatenate([0.5 + rng.normal(0, 0.01, (300, 3)), np.full((40, 3), 0.5)])
+    mu, q, ls, rgb, x = (a.astype(np.float32) for a in (mu, q, ls, rgb, x))
+    ref = O.radiance(mu, q, ls, rgb, x)
+    assert ref["count"].max() > 1000
+    say("case: crowded cell n=3000")
+    L, *_ = _eval(rad, (mu, q, ls, rgb), x, cell=0.05)
+    check_forward(L, ref)
+
+
+def test_errors_are_reported(rad):
+    from paper_2512_12459_amd._lib import GPFError
+    mu, q, ls, rgb = to_dev(np.zeros((4, 3)), np.zeros((4, 4)), np.zeros((4, 3)), np.ones((4, 3)))
+    (x,) = to_dev(np.random.default_rng(1).random((100, 3)))
+    qs = rad.QuerySet(x, 0.1)
+    say("case: zero quaternion -> invalid argument")
+    with pytest.raises(GPFError) as e:
+        rad.Grid(qs).build(mu, q, ls, rgb)
+    assert e.value.status == 1
+    with pytest.raises(GPFError):
+        rad.QuerySet(x, -1.0)
+    q2 = q.clone()
+    q2[:, 0] = 1.0
+    g = rad.Grid(qs).build(mu, q2, ls, rgb)
+    other = rgb.clone()
+    with pytest.raises(GPFError) as e:
+        rad.eval_radiance(g, mu, q2, ls, other)
+    assert e.value.status == 5
+
+
+def _grad_problem(seed, n, nq, spread):
+    rng = np.random.default_rng(seed)
+    mu = rng.random((n, 3)) * spread
+    q = rng.normal(size=(n, 4))
+    ls = math.log(0.03) + rng.normal(0, 0.3, (n, 3))
+    ls[:, 2] += math.log(0.2)
+    rgb = np.exp(rng.normal(0, 1, (n, 3)))
+    x = rng.random((nq, 3)) * spread
+    x[:, 1] = np.round(x[:, 1] * 8) / 8 * spread   # points on a few planes
+    return [a.astype(np.float32) for a in (mu, q, ls, rgb, x)]
+
+
+def _gpu_grads(rad, f_arrays, x, dL, cell=0.025):
+    L, g, dev, qs = _eval(rad, f_arrays, x, cell)
+    (dLd,) = to_dev(dL)
+    grads = rad.eval_radiance_backward(g, *dev, dLd)
+    torch.cuda.synchronize()
+    return L, {k: v.cpu().numpy() for k, v in grads.items()}
+
+
+def _mask_ambiguous(ref, g):
+    g = np.array(g, np.float64)
+    g[ref["n_amb"] > 0] = 0.0
+    return g
+
+
+def test_backward_random_volume(rad):
+    mu, q, ls, rgb, x = _grad_problem(3, 400, 3000, 0.2)
+    ref = O.radiance(mu, q, ls, rgb, x)
+    T = np.random.default_rng(4).random((len(x), 3)).astype(np.float32)
+    _, dL = O.mse_loss(ref["L"], T)
+    dL = _mask_ambiguous(ref, dL).astype(np.float32)
+    gref = O.radiance_backward(mu, q, ls, rgb, x, dL)
+    say("case: backward, 400 prims x 3000 points")
+    _, gg = _gpu_grads(rad, (mu, q, ls, rgb), x, dL)
+    check_grads(gg, gref)
+
+
+def test_backward_c1_all_points(rad, c1):
+    f, x, ref = c1
+    T = np.random.default_rng(5).random((len(x), 3)).astype(np.float32) * 0.5
+    _, dL = O.mse_loss(ref["L"], T)
+    dL = _mask_ambiguous(ref, dL).astype(np.float32)
+    gref = O.radiance_backward(*f.arrays(), x, dL)
+    say("case: backward plain4k, all points")
+    _, gg = _gpu_grads(rad, f.arrays(), x, dL)
+    check_grads(gg, gref)
+
+
+def test_autograd_function_matches_direct_call(rad):
+    mu, q, ls, rgb, x = _grad_problem(6, 200, 1000, 0.15)
+    dev = [t.clone().requires_grad_(True) for t in to_dev(mu, q, ls, rgb)]
+    (xd,) = to_dev(x)
+    qs = rad.QuerySet(xd, 0.03)
+    grid = rad.Grid(qs).build(*[t.detach() for t in dev])
+    # build from the exact tensors that autograd will see
+    grid.build(*dev)
+    say("case: autograd function")
+    L = rad.GPFRadiance.apply(*dev, grid)
+    # the function keeps only the four parameter tensors: no per-pair storage
+    saved = L.grad_fn.saved_tensors
+    assert len(saved) == 4 and all(a is b for a, b in zip(saved, dev))
+    w = torch.randn_like(L)
+    (L * w).sum().backward()
+    direct = rad.eval_radiance_backward(grid, *[t.detach() for t in dev], w.contiguous())
+    for t, k in zip(dev, ("mu", "quat", "log_scale", "rgb")):
+        # same kernel, atomics in a different order: equal to rounding
+        scale = direct[k].abs().max().item()
+        assert torch.allclose(t.grad, direct[k], rtol=1e-5, atol=1e-6 * scale), k
+
+
+def test_gpu_gradient_vs_finite_differences(rad):
+    """GPU gradients against central differences of the FP64 oracle's loss
+    (stencils that flip a cutoff decision are skipped)."""
+    mu, q, ls, rgb, x = _grad_problem(8, 40, 600, 0.08)
+    T = np.random.default_rng(9).random((len(x), 3)).astype(np.float32)
+    ref = O.radiance(mu, q, ls, rgb, x)
+    assert ref["n_amb"].sum() == 0
+    _, dL = O.mse_loss(ref["L"], T)
+    say("case: backward vs finite differences")
+    _, gg = _gpu_grads(rad, (mu, q, ls, rgb), x, dL.astype(np.float32))
+    fr = O.primitive_frames(q, ls)
+    u = np.einsum("nkj,qnj->qnk", fr["W"], x[:, None, :].astype(np.float64) - mu[None])
+    counts = np.sum(np.sum(u * u, -1) <= 9, axis=0)
+    idx = [int(i) for i in np.argsort(-counts)[:5] if counts[i] > 0]
+    base = dict(mu=mu.astype(np.float64), quat=q.astype(np.float64),
+                log_scale=ls.astype(np.float64), rgb=rgb.astype(np.float64))
+    checked = 0
+    for name in ("mu", "quat", "log_scale", "rgb"):
+        for i in idx:
+            for c in range(base[name].shape[1]):
+                h = 1e-6 * (abs(base[name][i, c]) if name == "rgb" else 1.0)
+                vals = []
+                flips = False
+                for sgn in (1, -1):
+                    p = {k: v.copy() for k, v in base.items()}
+                    p[name][i, c] += sgn * h
+                    r = O.radiance(p["mu"], p["quat"], p["log_scale"], p["rgb"], x)
+                    if not np.array_equal(r["count"], ref["count"]):
+                        flips = True
+                    vals.append(O.mse_loss(r["L"], T)[0])
+                if flips:
+                    continue
+                fd = (vals[0] - vals[1]) / (2 * h)
+                scale = max(abs(fd), 1e-2 * np.max(np.abs(gg[name][idx])))
+                assert abs(gg[name][i, c] - fd) <= 1e-4 * scale + 1e-9, (name, i, c, gg[name][i, c], fd)
+                checked += 1
+    assert checked >= 40
+
+
+def test_loss_and_adam_kernels(rad):
+    rng = np.random.default_rng(10)
+    L = rng.random((1000, 3)).astype(np.float32)
+    T = rng.random((1000, 3)).astype(np.float32)
+    Ld, Td = to_dev(L, T)
+    say("case: mse + adam kernels")
+    ls, dL = rad.mse_loss(Ld, Td)
+    want, gwant = O.mse_loss(L, T)
+    # differences are taken in FP32 and squared/summed in FP64
+    assert abs(ls.item() / 1000 - want) <= 1e-6 * want
+    np.testing.assert_allclose(dL.cpu().numpy(), gwant, rtol=1e-6, atol=1e-12)
+    p = rng.normal(size=5000).astype(np.float32)
+    m = np.zeros(5000)
+    v = np.zeros(5000)
+    pd, md, vd = to_dev(p, m, v)
+    pr = p.astype(np.float64)
+    for t in range(1, 4):
+        g = rng.normal(size=5000).astype(np.float32)
+        (gd,) = to_dev(g)
+        rad.adam_step(pd, gd, md, vd, t, 5e-4)
+        pr, m, v = O.adam_step(pr, g, m, v, t, 5e-4)
+    np.testing.assert_allclose(pd.cpu().numpy(), pr, rtol=0, atol=1e-6)
