@@ -74,6 +74,9 @@ def main():
     ap.add_argument("--lr", type=float, default=5e-4)
     ap.add_argument("--cpu-sample", type=int, default=192)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MB",
+                    help="only run a plain device-to-device copy of MB megabytes (5 times), "
+                         "to scale hardware byte counters")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -83,6 +86,16 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.calibrate_copy:
+        nbytes = args.calibrate_copy * (1 << 20)
+        a = torch.empty(nbytes // 4, device="cuda:0")
+        b = torch.ones(nbytes // 4, device="cuda:0")
+        for _ in range(5):
+            a.copy_(b)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": nbytes, "copies": 5}))
+        return
 
     from paper_2512_12459_amd import radiance as R
     from paper_2512_12459_amd import scenes as S

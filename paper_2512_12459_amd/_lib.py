@@ -10,7 +10,8 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libgpf.so")
+# GPF_LIBRARY may point at another build of the same library (e.g. a tuning variant)
+LIB_PATH = os.environ.get("GPF_LIBRARY") or os.path.join(HERE, "libgpf.so")
 
 GPF_OK = 0
 STATUS = {0: "OK", 1: "INVALID_ARGUMENT", 2: "OUT_OF_MEMORY", 3: "CAPACITY", 4: "HIP", 5: "STALE"}

@@ -181,6 +181,48 @@ __global__ void __launch_bounds__(256) tile_box_kernel(const float4* __restrict_
   }
 }
 
+__global__ void groups_per_cell_kernel(const int* __restrict__ toff, int ncells, int* ngroup) {
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= ncells) return;
+  int nt = toff[s + 1] - toff[s];
+  ngroup[s] = (nt + kGroupTiles - 1) / kGroupTiles;
+}
+
+__global__ void groups_fill_kernel(const int* __restrict__ toff, const int* __restrict__ goff,
+                                   const TileInfo* __restrict__ tiles, int ncells,
+                                   GroupInfo* groups) {
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= ncells) return;
+  int t0 = toff[s], t1 = toff[s + 1];
+  int g = goff[s];
+  for (int t = t0; t < t1; t += kGroupTiles, ++g) {
+    int tl = min(t + kGroupTiles, t1) - 1;
+    GroupInfo gi;
+    gi.start = tiles[t].start;
+    gi.count = tiles[tl].start + tiles[tl].count - gi.start;
+    gi.cell = s;
+    gi.first_tile = t;
+    groups[g] = gi;
+  }
+}
+
+__global__ void group_box_kernel(const GroupInfo* __restrict__ groups, int ngroups,
+                                 const float4* __restrict__ tlo, const float4* __restrict__ thi,
+                                 float4* glo, float4* ghi) {
+  int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= ngroups) return;
+  GroupInfo gi = groups[g];
+  float4 lo = tlo[gi.first_tile], hi = thi[gi.first_tile];
+  int nt = (gi.count + kTile - 1) / kTile;
+  for (int t = gi.first_tile + 1; t < gi.first_tile + nt; ++t) {
+    float4 a = tlo[t], b = thi[t];
+    lo.x = fminf(lo.x, a.x); lo.y = fminf(lo.y, a.y); lo.z = fminf(lo.z, a.z);
+    hi.x = fmaxf(hi.x, b.x); hi.y = fmaxf(hi.y, b.y); hi.z = fmaxf(hi.z, b.z);
+  }
+  glo[g] = lo;
+  ghi[g] = hi;
+}
+
 }  // namespace
 
 gpf_status launch_bin_queries(const float* x, int64_t q, float cell, hipStream_t s,
@@ -226,7 +268,9 @@ gpf_status launch_bin_queries(const float* x, int64_t q, float cell, hipStream_t
   int* flag = nullptr;
   int* cell_first = nullptr;
   int* ntile = nullptr;
+  int* cell_first_g = nullptr;
   auto cleanup = [&]() {
+    dev_free(cell_first_g, (q + 1) * 4);
     dev_free(keys, q * 8);
     dev_free(keys_s, q * 8);
     dev_free(idx, q * 4);
@@ -296,13 +340,31 @@ gpf_status launch_bin_queries(const float* x, int64_t q, float cell, hipStream_t
                      out->tiles);
   hipLaunchKernelGGL(tile_box_kernel, dim3((ntiles + 3) / 4), dim3(256), 0, s, out->xs, out->tiles,
                      ntiles, out->tile_lo, out->tile_hi);
+  // groups of consecutive tiles per cell (ntile[] now holds the tile offsets)
+  TRY(dev_alloc((void**)&cell_first_g, (q + 1) * 4, "group offsets"));
+  hipLaunchKernelGGL(groups_per_cell_kernel, dim3(cb), dim3(256), 0, s, ntile, ncells, cell_first_g);
+  hipLaunchKernelGGL(scan_exclusive_kernel, dim3(1), dim3(kScanThreads), 0, s, cell_first_g,
+                     cell_first_g, ncells);
+  int ngroups = 0;
+  TRYH(hipMemcpyAsync(&ngroups, cell_first_g + ncells, 4, hipMemcpyDeviceToHost, s),
+       "ngroups readback");
+  TRYH(hipStreamSynchronize(s), "ngroups sync");
+  out->ngroups = ngroups;
+  TRY(dev_alloc((void**)&out->groups, (int64_t)ngroups * sizeof(GroupInfo), "groups"));
+  TRY(dev_alloc((void**)&out->group_lo, (int64_t)ngroups * sizeof(float4), "group_lo"));
+  TRY(dev_alloc((void**)&out->group_hi, (int64_t)ngroups * sizeof(float4), "group_hi"));
+  hipLaunchKernelGGL(groups_fill_kernel, dim3(cb), dim3(256), 0, s, ntile, cell_first_g, out->tiles,
+                     ncells, out->groups);
+  hipLaunchKernelGGL(group_box_kernel, dim3((ngroups + 255) / 256), dim3(256), 0, s, out->groups,
+                     ngroups, out->tile_lo, out->tile_hi, out->group_lo, out->group_hi);
   TRYH(hipGetLastError(), "bin_queries launch");
   TRYH(hipStreamSynchronize(s), "bin_queries sync");
   cleanup();
 #undef TRY
 #undef TRYH
   out->bytes = q * (sizeof(float4) + 4) + dense * 4 + (int64_t)ncells * 4 +
-               (int64_t)ntiles * (sizeof(TileInfo) + 2 * sizeof(float4));
+               (int64_t)ntiles * (sizeof(TileInfo) + 2 * sizeof(float4)) +
+               (int64_t)ngroups * (sizeof(GroupInfo) + 2 * sizeof(float4));
   return GPF_OK;
 }
 

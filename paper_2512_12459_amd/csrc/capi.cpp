@@ -122,6 +122,9 @@ void gpf_queries_destroy(gpf_queries* qs) {
   dev_free(qs->tiles, qs->ntiles * sizeof(TileInfo));
   dev_free(qs->tile_lo, qs->ntiles * sizeof(float4));
   dev_free(qs->tile_hi, qs->ntiles * sizeof(float4));
+  dev_free(qs->groups, qs->ngroups * sizeof(GroupInfo));
+  dev_free(qs->group_lo, qs->ngroups * sizeof(float4));
+  dev_free(qs->group_hi, qs->ngroups * sizeof(float4));
   delete qs;
 }
 
@@ -173,6 +176,7 @@ void gpf_grid_destroy(gpf_grid* g) {
   dev_free(g->cell_count, nc * sizeof(int));
   dev_free(g->cell_start, nc * sizeof(int));
   dev_free(g->cell_prims, g->cap * sizeof(int));
+  dev_free(g->grad_rows, g->grad_cap * sizeof(float4) * 4);
   delete g;
 }
 

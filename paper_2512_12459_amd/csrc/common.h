@@ -11,6 +11,12 @@ namespace gpf {
 
 // Queries per tile: one wave64 evaluates one tile.
 constexpr int kTile = 64;
+// Tiles per backward group: the backward accumulates each primitive's sums
+// over a group of consecutive tiles of one cell before adding them to memory.
+#ifndef GPF_GROUP_TILES
+#define GPF_GROUP_TILES 2
+#endif
+constexpr int kGroupTiles = GPF_GROUP_TILES;
 // Scale folded into the whitening rows: u' = kappa * u with kappa^2 = log2(e)/2,
 // so that exp(-m^2/2) = exp2(-|u'|^2).
 constexpr double kKappa2 = 0.72134752044448170368;  // 0.5 * log2(e)
@@ -25,6 +31,12 @@ struct alignas(16) PrimRec {
 // occupied cell `cell`.
 struct alignas(16) TileInfo {
   int start, count, cell, pad;
+};
+
+// Group of <= kGroupTiles consecutive tiles of one cell: queries
+// [start, start+count), tiles [first_tile, first_tile + ntiles).
+struct alignas(16) GroupInfo {
+  int start, count, cell, first_tile;
 };
 
 }  // namespace gpf
@@ -45,6 +57,10 @@ struct gpf_queries {
   gpf::TileInfo* tiles = nullptr;  // [ntiles]
   float4* tile_lo = nullptr;     // [ntiles] tight box of the tile's points
   float4* tile_hi = nullptr;
+  int64_t ngroups = 0;
+  gpf::GroupInfo* groups = nullptr;  // [ngroups]
+  float4* group_lo = nullptr;        // [ngroups] box of the group's points
+  float4* group_hi = nullptr;
   size_t bytes = 0;
 };
 
@@ -61,6 +77,8 @@ struct gpf_grid {
   int* cell_prims = nullptr;    // [cap]
   int64_t cap = 0;
   int64_t entries = 0;
+  float4* grad_rows = nullptr;  // [n][4] backward scratch: one 64-byte row per primitive
+  int64_t grad_cap = 0;
   size_t bytes = 0;
 };
 
@@ -92,19 +110,28 @@ gpf_status launch_mse(const float* L, const float* T, int64_t q, double* loss, f
 gpf_status launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr,
                        float b1, float b2, float eps, int64_t step, hipStream_t s);
 
-// Workgroup -> tile remap so that each XCD (workgroups are dealt round-robin
-// over the 8 XCDs) walks a contiguous, spatially coherent range of tiles and
-// its L2 keeps the same primitives hot.
-__device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
-  const int kXcd = 8;
-  int per = (nblocks + kXcd - 1) / kXcd;
-  int xcd = bid % kXcd;
-  int idx = bid / kXcd;
-  // The first (nblocks % 8) XCDs get `per` blocks, the rest `per - 1`.
-  int full = nblocks % kXcd;
-  if (full == 0) full = kXcd;
-  int base = xcd < full ? xcd * per : full * per + (xcd - full) * (per - 1);
-  return base + idx;
+// Workgroup -> work-item remap.  Workgroups are dealt round-robin over the 8
+// XCDs; this mapping hands each XCD whole chunks of kXcdChunk consecutive
+// (spatially sorted) work items, so that the primitives a chunk touches stay
+// hot in that XCD's L2, while consecutive chunks go to different XCDs so that
+// dense regions of the scene are spread over the whole chip.  Launch
+// xcd_grid(n) workgroups; work items >= n must return.
+#ifndef GPF_XCD_CHUNK
+#define GPF_XCD_CHUNK 16
+#endif
+constexpr int kXcd = 8;
+constexpr int kXcdChunk = GPF_XCD_CHUNK;
+
+inline unsigned xcd_grid(int64_t n) {
+  const int64_t per = (int64_t)kXcd * kXcdChunk;
+  return (unsigned)(((n + per - 1) / per) * per);
+}
+
+__device__ __forceinline__ int xcd_remap(int bid) {
+  const int xcd = bid % kXcd;
+  const int idx = bid / kXcd;
+  const int chunk = idx / kXcdChunk, within = idx % kXcdChunk;
+  return (chunk * kXcd + xcd) * kXcdChunk + within;
 }
 
 }  // namespace gpf

@@ -4,11 +4,13 @@
 // occupied grid cell).  The wave first culls its cell's primitive list
 // against the tile's tight box with the whitened-frame separating test and
 // compacts the survivors into a per-wave LDS list; then
-//  - forward:  lane = query, loop over survivors (their records are read with
-//              wave-uniform scalar loads), accumulate L in registers;
-//  - backward: lane = survivor, loop over the tile's queries (broadcast from
-//              LDS), accumulate the 18 per-primitive sums in registers, map
-//              them to parameter gradients and add them with atomics.
+//  - forward:  one wave per group of consecutive tiles, lane = query points
+//              (kGroupTiles per lane), loop over survivors read with
+//              wave-uniform scalar loads, accumulate L in registers;
+//  - backward: one workgroup per group of consecutive tiles; lane = survivor,
+//              loop over the group's queries (broadcast from LDS), accumulate
+//              the 18 per-primitive sums in registers, map them to parameter
+//              gradients and add them with row-coalesced atomics.
 // Weights are recomputed in the backward; nothing per pair is stored.
 #include "common.h"
 
@@ -70,20 +72,35 @@ __device__ __forceinline__ int append_survivor(int* sv, int ns, bool pass, int p
 // ---------------------------------------------------------------------------
 // Forward
 // ---------------------------------------------------------------------------
+constexpr int kQpl = kGroupTiles;  // query points per lane in the forward
+
+// One wave per group of consecutive tiles of one cell (kQpl * 64 points):
+// lane l owns points l, l + 64, ...  The cell's candidates are culled against
+// the group box by lane = candidate into a per-wave LDS index list; every
+// survivor's record is then read once with wave-uniform scalar loads and
+// evaluated against all of the lane's points.
 __global__ void __launch_bounds__(kWaves * 64) eval_fwd_kernel(
-    const float4* __restrict__ xs, const int* __restrict__ perm, const TileInfo* __restrict__ tiles,
-    const float4* __restrict__ tlo, const float4* __restrict__ thi, int ntiles,
-    const int* __restrict__ cell_start, const int* __restrict__ cell_prims,
-    const PrimRec* __restrict__ recs, float c2, float* __restrict__ L) {
+    const float4* __restrict__ xs, const int* __restrict__ perm,
+    const GroupInfo* __restrict__ groups, const float4* __restrict__ glo,
+    const float4* __restrict__ ghi, int ngroups, const int* __restrict__ cell_start,
+    const int* __restrict__ cell_prims, const PrimRec* __restrict__ recs, float c2,
+    float* __restrict__ L) {
   __shared__ int surv[kWaves][kSurvCap];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int t = xcd_remap(blockIdx.x, gridDim.x) * kWaves + wave;
-  if (t >= ntiles) return;
-  const TileInfo ti = tiles[t];
-  const TileCtx tc = tile_ctx(tlo, thi, t);
-  const float4 p = xs[ti.start + min(lane, ti.count - 1)];
-  float a0 = 0.f, a1 = 0.f, a2 = 0.f;
-  const int cs = cell_start[ti.cell], ce = cell_start[ti.cell + 1];
+  const int g = xcd_remap(blockIdx.x) * kWaves + wave;
+  if (g >= ngroups) return;
+  const GroupInfo gi = groups[g];
+  const TileCtx tc = tile_ctx(glo, ghi, g);
+  float px[kQpl], py[kQpl], pz[kQpl], acc[kQpl][3];
+#pragma unroll
+  for (int i = 0; i < kQpl; ++i) {
+    const float4 p = xs[gi.start + min(lane + 64 * i, gi.count - 1)];
+    px[i] = p.x;
+    py[i] = p.y;
+    pz[i] = p.z;
+    acc[i][0] = acc[i][1] = acc[i][2] = 0.f;
+  }
+  const int cs = cell_start[gi.cell], ce = cell_start[gi.cell + 1];
   int* sv = surv[wave];
   int ns = 0;
   for (int base = cs; base < ce; base += 64) {
@@ -97,28 +114,44 @@ __global__ void __launch_bounds__(kWaves * 64) eval_fwd_kernel(
     ns = append_survivor(sv, ns, pass, pid, lane);
     if (ns > kSurvCap - 64 || base + 64 >= ce) {
       wave_sync_lds();
-      for (int s = 0; s < ns; ++s) {
-        const int id = __builtin_amdgcn_readfirstlane(sv[s]);
-        const PrimRec r = recs[id];
-        const float dx = p.x - r.r0.x, dy = p.y - r.r0.y, dz = p.z - r.r0.z;
-        const float u0 = r.r1.x * dx + r.r1.y * dy + r.r1.z * dz;
-        const float u1 = r.r2.x * dx + r.r2.y * dy + r.r2.z * dz;
-        const float u2 = r.r3.x * dx + r.r3.y * dy + r.r3.z * dz;
-        const float m2 = u0 * u0 + u1 * u1 + u2 * u2;
-        const float w = (m2 <= c2) ? __builtin_amdgcn_exp2f(-m2) : 0.f;
-        a0 += w * r.r0.w;
-        a1 += w * r.r1.w;
-        a2 += w * r.r2.w;
+      // two survivors per scalar fetch; an odd tail repeats the last record
+      // with its weights masked to zero
+      for (int s = 0; s < ns; s += 2) {
+        const int ida = __builtin_amdgcn_readfirstlane(sv[s]);
+        const int idb = __builtin_amdgcn_readfirstlane(sv[min(s + 1, ns - 1)]);
+        const PrimRec rp[2] = {recs[ida], recs[idb]};
+        const bool has_b = s + 1 < ns;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const PrimRec& r = rp[h];
+#pragma unroll
+          for (int i = 0; i < kQpl; ++i) {
+            const float dx = px[i] - r.r0.x, dy = py[i] - r.r0.y, dz = pz[i] - r.r0.z;
+            const float u0 = r.r1.x * dx + r.r1.y * dy + r.r1.z * dz;
+            const float u1 = r.r2.x * dx + r.r2.y * dy + r.r2.z * dz;
+            const float u2 = r.r3.x * dx + r.r3.y * dy + r.r3.z * dz;
+            const float m2 = u0 * u0 + u1 * u1 + u2 * u2;
+            const bool in = (m2 <= c2) && (h == 0 || has_b);
+            const float w = in ? __builtin_amdgcn_exp2f(-m2) : 0.f;
+            acc[i][0] += w * r.r0.w;
+            acc[i][1] += w * r.r1.w;
+            acc[i][2] += w * r.r2.w;
+          }
+        }
       }
       ns = 0;
       wave_sync_lds();
     }
   }
-  if (lane < ti.count) {
-    const int o = perm[ti.start + lane];
-    L[(int64_t)o * 3 + 0] = a0;
-    L[(int64_t)o * 3 + 1] = a1;
-    L[(int64_t)o * 3 + 2] = a2;
+#pragma unroll
+  for (int i = 0; i < kQpl; ++i) {
+    const int k = lane + 64 * i;
+    if (k < gi.count) {
+      const int o = perm[gi.start + k];
+      L[(int64_t)o * 3 + 0] = acc[i][0];
+      L[(int64_t)o * 3 + 1] = acc[i][1];
+      L[(int64_t)o * 3 + 2] = acc[i][2];
+    }
   }
 }
 
@@ -177,36 +210,55 @@ __global__ void __launch_bounds__(kWaves * 64) count_pairs_kernel(
 // ---------------------------------------------------------------------------
 // Backward
 // ---------------------------------------------------------------------------
-struct GradOut {
-  float *mu, *quat, *ls, *rgb;
-};
+constexpr int kBwdThreads = 256;
+constexpr int kBwdWaves = kBwdThreads / 64;
+constexpr int kGroupQ = kTile * kGroupTiles;  // points per group (max, a multiple of 4)
+constexpr int kGSurvCap = 1024;               // group survivor slots
+constexpr int kRowStride = 14;                // transpose row stride (13 values + flag)
 
-// Maps the per-primitive sums (in the kappa-scaled whitened frame) to
-// parameter gradients and adds them.  With u' = kappa u, W' = kappa W:
-//   dmu = W^T A = W'^T A' / kappa^2,   dsigma_k = S'_k / kappa^2,
-//   dR[j][k] = -M[k][j] / s_k = -M'[k][j] / (kappa s_k),
-//   dq = (I - qhat qhat^T) dqhat / |q|,  dqhat = sum_jk dR[j][k] dR[j][k]/dqhat.
+// Maps the per-primitive sums (kappa-scaled whitened frame, u' = kappa u,
+// W' = kappa W) to the 13 parameter gradients:
+//   GP = sum w g,  A' = sum c u',  U' = sum c u' u'^T   (c = w g.Phi).
+// Since d = W^-1 u = R diag(s) u' / kappa, the sums M[k][j] = sum c u_k d_j
+// follow from U': M[k][j] = sum_l U'[k][l] R[j][l] s_l / kappa^2.  Then
+//   dmu = W^T A = W'^T A' / kappa^2,   dsigma_k = U'[k][k] / kappa^2,
+//   dR[j][k] = -M[k][j] / s_k,
+//   dq = (I - qhat qhat^T) dqhat / |q|,  dqhat = sum_jk dR[j][k] dR[j][k]/dqhat,
+//   dPhi = GP.
+// out: [0..2] mu, [3..6] quat, [7..9] log_scale, [10..12] rgb.
 __device__ __forceinline__ void grad_epilogue(const PrimRec& r, const float* __restrict__ quat,
                                               const float* __restrict__ ls, int pid,
-                                              const float GP[3], const float A[3], const float S[3],
-                                              const float M[3][3], GradOut go) {
+                                              const float GP[3], const float A[3],
+                                              const float U[6], float out[13]) {
   const float ik2 = (float)(1.0 / kKappa2);
-  const float ik = (float)(1.0 / 0.84932180028801904272);  // 1 / sqrt(kKappa2)
   const float4 wr[3] = {r.r1, r.r2, r.r3};
-  float dmu[3];
-  dmu[0] = (wr[0].x * A[0] + wr[1].x * A[1] + wr[2].x * A[2]) * ik2;
-  dmu[1] = (wr[0].y * A[0] + wr[1].y * A[1] + wr[2].y * A[2]) * ik2;
-  dmu[2] = (wr[0].z * A[0] + wr[1].z * A[1] + wr[2].z * A[2]) * ik2;
+  out[0] = (wr[0].x * A[0] + wr[1].x * A[1] + wr[2].x * A[2]) * ik2;
+  out[1] = (wr[0].y * A[0] + wr[1].y * A[1] + wr[2].y * A[2]) * ik2;
+  out[2] = (wr[0].z * A[0] + wr[1].z * A[1] + wr[2].z * A[2]) * ik2;
   float qw = quat[pid * 4], qx = quat[pid * 4 + 1], qy = quat[pid * 4 + 2], qz = quat[pid * 4 + 3];
   const float qn = sqrtf(qw * qw + qx * qx + qy * qy + qz * qz);
   const float iq = 1.f / qn;
   qw *= iq; qx *= iq; qy *= iq; qz *= iq;
-  float G[3][3];  // G[j][k] = d loss / d R[j][k]
+  float R[3][3];
+  R[0][0] = 1.f - 2.f * (qy * qy + qz * qz);
+  R[0][1] = 2.f * (qx * qy - qw * qz);
+  R[0][2] = 2.f * (qx * qz + qw * qy);
+  R[1][0] = 2.f * (qx * qy + qw * qz);
+  R[1][1] = 1.f - 2.f * (qx * qx + qz * qz);
+  R[1][2] = 2.f * (qy * qz - qw * qx);
+  R[2][0] = 2.f * (qx * qz - qw * qy);
+  R[2][1] = 2.f * (qy * qz + qw * qx);
+  R[2][2] = 1.f - 2.f * (qx * qx + qy * qy);
+  const float sc[3] = {__expf(ls[pid * 3]), __expf(ls[pid * 3 + 1]), __expf(ls[pid * 3 + 2])};
+  const float Uf[3][3] = {{U[0], U[1], U[2]}, {U[1], U[3], U[4]}, {U[2], U[4], U[5]}};
+  float G[3][3];  // G[j][k] = d loss / d R[j][k] = -M[k][j] / s_k
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    const float inv_s = __expf(-ls[pid * 3 + k]) * ik;
+    const float f = -ik2 / sc[k];
 #pragma unroll
-    for (int j = 0; j < 3; ++j) G[j][k] = -M[k][j] * inv_s;
+    for (int j = 0; j < 3; ++j)
+      G[j][k] = f * (Uf[k][0] * R[j][0] * sc[0] + Uf[k][1] * R[j][1] * sc[1] +
+                     Uf[k][2] * R[j][2] * sc[2]);
   }
   float gw = 2.f * (qz * (G[1][0] - G[0][1]) + qy * (G[0][2] - G[2][0]) + qx * (G[2][1] - G[1][2]));
   float gx = 2.f * (qy * (G[0][1] + G[1][0]) + qz * (G[0][2] + G[2][0]) + qw * (G[2][1] - G[1][2]) -
@@ -216,115 +268,179 @@ __device__ __forceinline__ void grad_epilogue(const PrimRec& r, const float* __r
   float gz = 2.f * (qx * (G[0][2] + G[2][0]) + qy * (G[1][2] + G[2][1]) + qw * (G[1][0] - G[0][1]) -
                     2.f * qz * (G[0][0] + G[1][1]));
   const float dot = qw * gw + qx * gx + qy * gy + qz * gz;
-  gw = (gw - dot * qw) * iq;
-  gx = (gx - dot * qx) * iq;
-  gy = (gy - dot * qy) * iq;
-  gz = (gz - dot * qz) * iq;
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    unsafeAtomicAdd(go.mu + pid * 3 + a, dmu[a]);
-    unsafeAtomicAdd(go.ls + pid * 3 + a, S[a] * ik2);
-    unsafeAtomicAdd(go.rgb + pid * 3 + a, GP[a]);
-  }
-  unsafeAtomicAdd(go.quat + pid * 4 + 0, gw);
-  unsafeAtomicAdd(go.quat + pid * 4 + 1, gx);
-  unsafeAtomicAdd(go.quat + pid * 4 + 2, gy);
-  unsafeAtomicAdd(go.quat + pid * 4 + 3, gz);
+  out[3] = (gw - dot * qw) * iq;
+  out[4] = (gx - dot * qx) * iq;
+  out[5] = (gy - dot * qy) * iq;
+  out[6] = (gz - dot * qz) * iq;
+  out[7] = U[0] * ik2;
+  out[8] = U[3] * ik2;
+  out[9] = U[5] * ik2;
+  out[10] = GP[0];
+  out[11] = GP[1];
+  out[12] = GP[2];
 }
 
-__global__ void __launch_bounds__(kWaves * 64) eval_bwd_kernel(
-    const float4* __restrict__ xs, const int* __restrict__ perm, const TileInfo* __restrict__ tiles,
-    const float4* __restrict__ tlo, const float4* __restrict__ thi, int ntiles,
-    const int* __restrict__ cell_start, const int* __restrict__ cell_prims,
-    const PrimRec* __restrict__ recs, const float* __restrict__ quat, const float* __restrict__ ls,
-    float c2, const float* __restrict__ dL, GradOut go) {
-  __shared__ int surv[kWaves][kSurvCap];
-  __shared__ float4 qx_s[kWaves][kTile];
-  __shared__ float4 qg_s[kWaves][kTile];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int t = xcd_remap(blockIdx.x, gridDim.x) * kWaves + wave;
-  if (t >= ntiles) return;
-  const TileInfo ti = tiles[t];
-  const TileCtx tc = tile_ctx(tlo, thi, t);
-  {
-    const int k = ti.start + min(lane, ti.count - 1);
-    const float4 p = xs[k];
-    const int o = perm[k];
-    qx_s[wave][lane] = p;
-    qg_s[wave][lane] = lane < ti.count
-                           ? make_float4(dL[(int64_t)o * 3], dL[(int64_t)o * 3 + 1],
-                                         dL[(int64_t)o * 3 + 2], 0.f)
-                           : make_float4(0.f, 0.f, 0.f, 0.f);
+// One workgroup per group of consecutive tiles of one cell.  The cell's
+// candidates are culled once against the group's box into an LDS list; each
+// wave then takes 64 survivors at a time (lane = primitive), loops over all of
+// the group's points (broadcast from LDS), and adds the resulting 13-value
+// gradient rows to a padded per-primitive buffer with row-coalesced atomics
+// (16 lanes update one 64-byte row per instruction).
+__global__ void __launch_bounds__(kBwdThreads) eval_bwd_kernel(
+    const float4* __restrict__ xs, const int* __restrict__ perm,
+    const GroupInfo* __restrict__ groups, const float4* __restrict__ glo,
+    const float4* __restrict__ ghi, int ngroups, const int* __restrict__ cell_start,
+    const int* __restrict__ cell_prims, const PrimRec* __restrict__ recs,
+    const float* __restrict__ quat, const float* __restrict__ ls, float c2,
+    const float* __restrict__ dL, float* __restrict__ grad_rows) {
+  __shared__ int sv[kGSurvCap];
+  __shared__ int sv_count;
+  __shared__ float4 qx_s[kGroupQ];
+  __shared__ float4 qg_s[kGroupQ];
+  __shared__ float rows_s[kBwdWaves][64 * kRowStride];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int gidx = xcd_remap(blockIdx.x);
+  if (gidx >= ngroups) return;  // uniform for the workgroup
+  const GroupInfo gi = groups[gidx];
+  const TileCtx tc = tile_ctx(glo, ghi, gidx);
+  // points relative to the group centre; the tail up to a multiple of 4 gets
+  // a zero upstream gradient, so its pairs contribute exactly nothing
+  const int nq4 = (gi.count + 3) & ~3;
+  for (int k = tid; k < nq4; k += kBwdThreads) {
+    if (k < gi.count) {
+      const int o = perm[gi.start + k];
+      const float4 p = xs[gi.start + k];
+      qx_s[k] = make_float4(p.x - tc.cx, p.y - tc.cy, p.z - tc.cz, 0.f);
+      qg_s[k] = make_float4(dL[(int64_t)o * 3], dL[(int64_t)o * 3 + 1], dL[(int64_t)o * 3 + 2], 0.f);
+    } else {
+      qx_s[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+      qg_s[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
   }
-  const int nq = ti.count;
-  const int cs = cell_start[ti.cell], ce = cell_start[ti.cell + 1];
-  int* sv = surv[wave];
-  int ns = 0;
-  for (int base = cs; base < ce; base += 64) {
-    const int j = base + lane;
+  if (tid == 0) sv_count = 0;
+  __syncthreads();
+  const int cs = cell_start[gi.cell], ce = cell_start[gi.cell + 1];
+  for (int base = cs; base < ce; base += kBwdThreads) {
+    const int j = base + tid;
     bool pass = false;
     int pid = 0;
     if (j < ce) {
       pid = cell_prims[j];
       pass = tile_may_touch(recs[pid], tc, c2);
     }
-    ns = append_survivor(sv, ns, pass, pid, lane);
-    const bool last = base + 64 >= ce;
-    if (ns >= 64 || (last && ns > 0)) {
-      wave_sync_lds();
-      // consume survivors 64 at a time: lane = primitive
-      int done = 0;
-      while (ns - done >= 64 || (last && done < ns)) {
-        const bool valid = done + lane < ns;
-        const int id = valid ? sv[done + lane] : 0;
+    const uint64_t b = __ballot(pass);
+    int off = 0;
+    if (lane == 0 && b) off = atomicAdd(&sv_count, (int)__popcll(b));
+    off = __shfl(off, 0, 64);
+    if (pass) {
+      const uint64_t below = b & ((lane == 0) ? 0ull : (~0ull >> (64 - lane)));
+      sv[off + __popcll(below)] = pid;
+    }
+    __syncthreads();
+    const int nsv = sv_count;
+    // every wave must read the count before any wave appends again
+    __syncthreads();
+    const bool last = base + kBwdThreads >= ce;
+    if (nsv > kGSurvCap - kBwdThreads || (last && nsv > 0)) {
+      for (int chunk = wave * 64; chunk < nsv; chunk += kBwdThreads) {
+        const bool valid = chunk + lane < nsv;
+        const int id = valid ? sv[chunk + lane] : 0;
         const PrimRec r = recs[id];
-        float GP[3] = {0.f, 0.f, 0.f}, A[3] = {0.f, 0.f, 0.f}, S[3] = {0.f, 0.f, 0.f};
-        float M[3][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
+        // offsets are taken from the group centre: u' = W' x' - b', b' = W' (mu - centre)
+        const float mx = r.r0.x - tc.cx, my = r.r0.y - tc.cy, mz = r.r0.z - tc.cz;
+        const float b0 = r.r1.x * mx + r.r1.y * my + r.r1.z * mz;
+        const float b1 = r.r2.x * mx + r.r2.y * my + r.r2.z * mz;
+        const float b2 = r.r3.x * mx + r.r3.y * my + r.r3.z * mz;
+        float GP[3] = {0.f, 0.f, 0.f}, A[3] = {0.f, 0.f, 0.f};
+        float U[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
         bool any = false;
-        for (int k = 0; k < nq; ++k) {
-          const float4 x = qx_s[wave][k];
-          const float dx = x.x - r.r0.x, dy = x.y - r.r0.y, dz = x.z - r.r0.z;
-          const float u0 = r.r1.x * dx + r.r1.y * dy + r.r1.z * dz;
-          const float u1 = r.r2.x * dx + r.r2.y * dy + r.r2.z * dz;
-          const float u2 = r.r3.x * dx + r.r3.y * dy + r.r3.z * dz;
-          const float m2 = u0 * u0 + u1 * u1 + u2 * u2;
-          if (m2 <= c2) {
-            const float4 g = qg_s[wave][k];
-            const float w = __builtin_amdgcn_exp2f(-m2);
-            const float a = g.x * r.r0.w + g.y * r.r1.w + g.z * r.r2.w;
-            const float c = a * w;
-            GP[0] += w * g.x;
-            GP[1] += w * g.y;
-            GP[2] += w * g.z;
-            const float cu[3] = {c * u0, c * u1, c * u2};
-            const float uu[3] = {u0, u1, u2};
+        for (int k = 0; k < nq4; k += 4) {
+          float4 xq[4], gq[4];
 #pragma unroll
-            for (int q = 0; q < 3; ++q) {
-              A[q] += cu[q];
-              S[q] += cu[q] * uu[q];
-              M[q][0] += cu[q] * dx;
-              M[q][1] += cu[q] * dy;
-              M[q][2] += cu[q] * dz;
-            }
-            any = true;
+          for (int i = 0; i < 4; ++i) {
+            xq[i] = qx_s[k + i];
+            gq[i] = qg_s[k + i];
+          }
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const float u0 = fmaf(r.r1.z, xq[i].z, fmaf(r.r1.y, xq[i].y, fmaf(r.r1.x, xq[i].x, -b0)));
+            const float u1 = fmaf(r.r2.z, xq[i].z, fmaf(r.r2.y, xq[i].y, fmaf(r.r2.x, xq[i].x, -b1)));
+            const float u2 = fmaf(r.r3.z, xq[i].z, fmaf(r.r3.y, xq[i].y, fmaf(r.r3.x, xq[i].x, -b2)));
+            const float m2 = u0 * u0 + u1 * u1 + u2 * u2;
+            const bool in = m2 <= c2;
+            const float w = in ? __builtin_amdgcn_exp2f(-m2) : 0.f;
+            any |= in;
+            const float a = gq[i].x * r.r0.w + gq[i].y * r.r1.w + gq[i].z * r.r2.w;
+            const float c = a * w;
+            GP[0] += w * gq[i].x;
+            GP[1] += w * gq[i].y;
+            GP[2] += w * gq[i].z;
+            const float cu0 = c * u0, cu1 = c * u1, cu2 = c * u2;
+            A[0] += cu0;
+            A[1] += cu1;
+            A[2] += cu2;
+            U[0] += cu0 * u0;
+            U[1] += cu0 * u1;
+            U[2] += cu0 * u2;
+            U[3] += cu1 * u1;
+            U[4] += cu1 * u2;
+            U[5] += cu2 * u2;
           }
         }
-        if (valid && any) grad_epilogue(r, quat, ls, id, GP, A, S, M, go);
-        done += 64;
-      }
-      // keep the unconsumed tail at the front of the list
-      const int rem = ns - done;
-      if (rem > 0) {
-        const int v = lane < rem ? sv[done + lane] : 0;
+        float out[13];
+        grad_epilogue(r, quat, ls, id, GP, A, U, out);
+        const bool write = valid && any;
+        float* rw = rows_s[wave];
+#pragma unroll
+        for (int e = 0; e < 13; ++e) rw[lane * kRowStride + e] = write ? out[e] : 0.f;
+        rw[lane * kRowStride + 13] = write ? 1.f : 0.f;
         wave_sync_lds();
-        if (lane < rem) sv[lane] = v;
-        ns = rem;
-      } else {
-        ns = 0;
+        // row-coalesced atomics: instruction r covers rows 4r..4r+3, 16 lanes each
+        const int sub = lane >> 4, e = lane & 15;
+#pragma unroll 4
+        for (int rr = 0; rr < 16; ++rr) {
+          const int row = rr * 4 + sub;
+          if (e < 13 && rw[row * kRowStride + 13] != 0.f) {
+            const int rid = sv[chunk + row];
+            unsafeAtomicAdd(grad_rows + (int64_t)rid * 16 + e, rw[row * kRowStride + e]);
+          }
+        }
+        wave_sync_lds();
       }
-      wave_sync_lds();
+      __syncthreads();
+      if (tid == 0) sv_count = 0;
+      __syncthreads();
     }
   }
+}
+
+// grads += rows; rows = 0 (leaves the scratch clean for the next call).
+__global__ void __launch_bounds__(256) grad_finalize_kernel(float4* __restrict__ rows, int n,
+                                                            float* __restrict__ gmu,
+                                                            float* __restrict__ gq,
+                                                            float* __restrict__ gls,
+                                                            float* __restrict__ grgb) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float4 a = rows[i * 4], b = rows[i * 4 + 1], c = rows[i * 4 + 2], d = rows[i * 4 + 3];
+  const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+  rows[i * 4] = z;
+  rows[i * 4 + 1] = z;
+  rows[i * 4 + 2] = z;
+  rows[i * 4 + 3] = z;
+  gmu[i * 3] += a.x;
+  gmu[i * 3 + 1] += a.y;
+  gmu[i * 3 + 2] += a.z;
+  gq[i * 4] += a.w;
+  gq[i * 4 + 1] += b.x;
+  gq[i * 4 + 2] += b.y;
+  gq[i * 4 + 3] += b.z;
+  gls[i * 3] += b.w;
+  gls[i * 3 + 1] += c.x;
+  gls[i * 3 + 2] += c.y;
+  grgb[i * 3] += c.z;
+  grgb[i * 3 + 1] += c.w;
+  grgb[i * 3 + 2] += d.x;
 }
 
 }  // namespace
@@ -334,21 +450,35 @@ static int fwd_blocks(int64_t ntiles) { return (int)((ntiles + kWaves - 1) / kWa
 gpf_status launch_eval_fwd(const gpf_grid* g, float* L, hipStream_t s) {
   const gpf_queries* qs = g->qs;
   const float c2 = (float)(kKappa2 * g->cutoff * g->cutoff);
-  hipLaunchKernelGGL(eval_fwd_kernel, dim3(fwd_blocks(qs->ntiles)), dim3(kWaves * 64), 0, s,
-                     qs->xs, qs->perm, qs->tiles, qs->tile_lo, qs->tile_hi, (int)qs->ntiles,
+  hipLaunchKernelGGL(eval_fwd_kernel, dim3(xcd_grid(fwd_blocks(qs->ngroups))), dim3(kWaves * 64), 0, s,
+                     qs->xs, qs->perm, qs->groups, qs->group_lo, qs->group_hi, (int)qs->ngroups,
                      g->cell_start, g->cell_prims, g->rec, c2, L);
   GPF_HIP(hipGetLastError());
   return GPF_OK;
 }
 
-gpf_status launch_eval_bwd(const gpf_grid* g, const float* dL, gpf_field_grad* grad,
+gpf_status launch_eval_bwd(const gpf_grid* gc, const float* dL, gpf_field_grad* grad,
                            hipStream_t s) {
+  gpf_grid* g = const_cast<gpf_grid*>(gc);  // scratch rows live in the handle
   const gpf_queries* qs = g->qs;
   const float c2 = (float)(kKappa2 * g->cutoff * g->cutoff);
-  GradOut go{grad->mu, grad->quat, grad->log_scale, grad->rgb};
-  hipLaunchKernelGGL(eval_bwd_kernel, dim3(fwd_blocks(qs->ntiles)), dim3(kWaves * 64), 0, s,
-                     qs->xs, qs->perm, qs->tiles, qs->tile_lo, qs->tile_hi, (int)qs->ntiles,
-                     g->cell_start, g->cell_prims, g->rec, g->quat, g->log_scale, c2, dL, go);
+  if (g->grad_cap < g->n) {
+    dev_free(g->grad_rows, g->grad_cap * sizeof(float4) * 4);
+    g->grad_rows = nullptr;
+    g->grad_cap = 0;
+    gpf_status st = dev_alloc((void**)&g->grad_rows, (size_t)g->n * sizeof(float4) * 4,
+                              "gradient rows");
+    if (st != GPF_OK) return st;
+    GPF_HIP(hipMemsetAsync(g->grad_rows, 0, (size_t)g->n * sizeof(float4) * 4, s));
+    g->grad_cap = g->n;
+    g->bytes += (size_t)g->n * sizeof(float4) * 4;
+  }
+  hipLaunchKernelGGL(eval_bwd_kernel, dim3(xcd_grid(qs->ngroups)), dim3(kBwdThreads), 0, s, qs->xs,
+                     qs->perm, qs->groups, qs->group_lo, qs->group_hi, (int)qs->ngroups,
+                     g->cell_start, g->cell_prims, g->rec, g->quat, g->log_scale, c2, dL,
+                     (float*)g->grad_rows);
+  hipLaunchKernelGGL(grad_finalize_kernel, dim3((unsigned)((g->n + 255) / 256)), dim3(256), 0, s,
+                     g->grad_rows, (int)g->n, grad->mu, grad->quat, grad->log_scale, grad->rgb);
   GPF_HIP(hipGetLastError());
   return GPF_OK;
 }
