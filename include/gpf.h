@@ -141,6 +141,71 @@ gpf_status gpf_mse_loss(const float *L, const float *T, int64_t q, double *loss_
 gpf_status gpf_adam_step(float *p, const float *g, float *m, float *v, int64_t n, float lr,
                          float beta1, float beta2, float eps, int64_t step, void *stream);
 
+/* ---- photon-to-Gaussian initialisation (Sec. 4.1 physically-inspired
+ * initialisation: one Gaussian per photon, centre = photon position, flux =
+ * photon flux; supplementary Sec. A.2 gives the paper's defaults) ---------- */
+
+/* k nearest other photons of every photon: idx[p][k] (int32, device) and
+ * FP32 squared distances d2[p][k], ordered by (distance, index); distances are
+ * ((dx*dx + dy*dy) + dz*dz) with each operation rounded to FP32 (no fused
+ * multiply-add).  pos[p][3].  3 <= k <= 32, p >= k + 1, p <= 2^28.
+ * Synchronises `stream`. */
+gpf_status gpf_photon_knn(const float *pos, int64_t p, int k, int32_t *idx, float *d2,
+                          void *stream);
+
+/* Network inputs X[p][96] (bfloat16 bits, device) from 16 neighbours (idx, d2
+ * from gpf_photon_knn with k = 16): for each neighbour j in order,
+ * (pos_j - pos_i) / r16 (3 values) then log(power_j / power_i) per channel. */
+gpf_status gpf_photon_features(const float *pos, const float *power, int64_t p,
+                               const int32_t *idx, const float *d2, uint16_t *X, void *stream);
+
+/* Gaussians from photons, written to out (overwritten, p primitives):
+ * mu = pos, rgb = power, and
+ *  - mlp == NULL (plain initialisation): q = (1,0,0,0), isotropic
+ *    log_scale = log(clamp(r3, 1e-4, 0.1)) with r3 the distance to the
+ *    third-nearest photon (k >= 3);
+ *  - mlp != NULL (learned initialisation, k must be 16): the network maps each
+ *    photon's features to o[10]; q = normalise((1,0,0,0) + o[0:4]),
+ *    log_scale = plain + o[4:7], rgb = power * exp(o[7:10]).
+ * pos, power: [p][3] device.  Synchronises `stream`. */
+gpf_status gpf_init_from_photons(const float *pos, const float *power, int64_t p, int k,
+                                 const gpf_mlp *mlp, gpf_field_out *out, void *stream);
+
+/* ---- learned initialiser network (not in the paper): 96 -> 128 -> 128 -> 10
+ * with exact-erf GELU after both hidden layers, bfloat16 operands on MFMA with
+ * FP32 accumulation, FP32 master parameters trained by Adam. --------------
+ * Parameter vector (FP32, gpf_mlp_num_params() = 30218 values), matrices
+ * W[in][out] row-major: W1[96][128] b1[128] W2[128][128] b2[128] W3[128][10]
+ * b3[10]; a layer computes y = x W + b. */
+int64_t gpf_mlp_num_params(void);
+/* New network with all parameters zero (its outputs are zero: plain
+ * initialisation).  Synchronises the device. */
+gpf_status gpf_mlp_create(gpf_mlp **out);
+void gpf_mlp_destroy(gpf_mlp *mlp);
+/* Copies params (HOST, gpf_mlp_num_params() floats) into the network and
+ * resets the optimiser state.  Synchronises the device. */
+gpf_status gpf_mlp_set_params(gpf_mlp *mlp, const float *params);
+/* Copies the FP32 parameters to params (HOST).  Synchronises the device. */
+gpf_status gpf_mlp_get_params(const gpf_mlp *mlp, float *params);
+/* Y[b][10] (FP32) = network(X[b][96] bfloat16 bits). */
+gpf_status gpf_mlp_forward(const gpf_mlp *mlp, const uint16_t *X, int64_t b, float *Y,
+                           void *stream);
+/* Gradient of the mean squared error mean((Y - T)^2) over the b x 10 outputs:
+ * grad[gpf_mlp_num_params()] (device) is overwritten; loss_sum (device FP64,
+ * may be NULL) += sum of squared errors.  T[b][10] FP32. */
+gpf_status gpf_mlp_gradient(gpf_mlp *mlp, const uint16_t *X, const float *T, int64_t b,
+                            float *grad, double *loss_sum, void *stream);
+/* One training step: the gradient above, then Adam (beta 0.9/0.999, eps 1e-8,
+ * learning rate lr) on the FP32 parameters. */
+gpf_status gpf_mlp_train_step(gpf_mlp *mlp, const uint16_t *X, const float *T, int64_t b, float lr,
+                              double *loss_sum, void *stream);
+/* Training targets T[p][10] that would map photon i onto Gaussian i of a
+ * fitted field: o[0:4] = qhat - (1,0,0,0) (sign chosen so qhat_w >= 0),
+ * o[4:7] = log_scale - log(clamp(r3)), o[7:10] = log(max(rgb, 1e-6 power) / power).
+ * d2 from gpf_photon_knn (k columns). */
+gpf_status gpf_mlp_targets(const float *power, int64_t p, const float *d2, int k,
+                           const gpf_field *fitted, float *T, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -55,6 +55,19 @@ _SIG = {
     "gpf_count_pairs": (ctypes.c_int, [_P, ctypes.POINTER(Field), ctypes.POINTER(_I64), _P]),
     "gpf_mse_loss": (ctypes.c_int, [_P, _P, _I64, _P, _P, _P]),
     "gpf_adam_step": (ctypes.c_int, [_P, _P, _P, _P, _I64, _F, _F, _F, _F, _I64, _P]),
+    "gpf_photon_knn": (ctypes.c_int, [_P, _I64, ctypes.c_int, _P, _P, _P]),
+    "gpf_photon_features": (ctypes.c_int, [_P, _P, _I64, _P, _P, _P, _P]),
+    "gpf_init_from_photons": (ctypes.c_int, [_P, _P, _I64, ctypes.c_int, _P,
+                                             ctypes.POINTER(FieldGrad), _P]),
+    "gpf_mlp_num_params": (ctypes.c_int64, []),
+    "gpf_mlp_create": (ctypes.c_int, [ctypes.POINTER(_P)]),
+    "gpf_mlp_destroy": (None, [_P]),
+    "gpf_mlp_set_params": (ctypes.c_int, [_P, _P]),
+    "gpf_mlp_get_params": (ctypes.c_int, [_P, _P]),
+    "gpf_mlp_forward": (ctypes.c_int, [_P, _P, _I64, _P, _P]),
+    "gpf_mlp_gradient": (ctypes.c_int, [_P, _P, _P, _I64, _P, _P, _P]),
+    "gpf_mlp_train_step": (ctypes.c_int, [_P, _P, _P, _I64, _F, _P, _P]),
+    "gpf_mlp_targets": (ctypes.c_int, [_P, _I64, _P, ctypes.c_int, ctypes.POINTER(Field), _P, _P]),
 }
 
 
