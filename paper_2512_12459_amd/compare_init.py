@@ -1,0 +1,102 @@
+"""Plain vs learned initialisation: fit iterations and wall time to a PSNR
+target on the same field, views and optimiser.
+
+Default: ground truth = the 1,000,000-Gaussian caustic field (seed 7), one
+photon per Gaussian, 32 ring views at 800x800 (20,480,000 points), target
+35 dB; the network is trained first on 200 density-matched 4,096-Gaussian
+fields fitted by the library itself (seeds 100-299).
+
+    python -m paper_2512_12459_amd.compare_init [--train-fields 200] [--views 32 --res 800]
+
+Prints one JSON object.  Wall time of the learned run includes the kNN,
+features and network inference of the initialisation.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+import time
+
+import torch
+
+from . import learned_init as LI
+from . import photons as PH
+from . import radiance as R
+from . import scenes as S
+from .fit import Field, Fitter
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def compare(net, workload="caustic1m", gt_seed=7, views=32, res=800, target_psnr=35.0,
+            max_steps=1500, check_every=10, cell=0.025, lr=None):
+    gt, x = S.workload(workload, views=views, res=res, seed=gt_seed)
+    pos, power = S.photons_from_field(gt, gt_seed + 1)
+    dev = "cuda"
+    qs = R.QuerySet(torch.from_numpy(x).to(dev), cell)
+    T = LI.render(qs, gt.arrays())
+    pd = torch.from_numpy(pos).to(dev)
+    wd = torch.from_numpy(power).to(dev)
+    out = {}
+    for name, mlp in (("plain", None), ("learned", net)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        f = Field(*PH.init_from_photons(pd, wd, k=16, mlp=mlp))
+        torch.cuda.synchronize()
+        t_init = time.perf_counter() - t0
+        fitter = Fitter(f, qs, T, lr=lr)
+        p0 = fitter.current_psnr()
+        res_ = fitter.run(max_steps, target_psnr, check_every, log=lambda s: log(f"[{name}] {s}"))
+        out[name] = dict(init_psnr=p0, steps_to_target=res_["reached"],
+                         seconds_to_target=(t_init + res_["seconds"]) if res_["reached"] else None,
+                         init_seconds=t_init, final_psnr=res_["history"][-1][1],
+                         steps_run=res_["history"][-1][0], history=res_["history"])
+        log(f"{name}: init {p0:.2f} dB, reached {res_['reached']}, final {out[name]['final_psnr']:.2f} dB")
+    return dict(workload=workload, n=gt.n, q=int(x.shape[0]), target_psnr=target_psnr, runs=out)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--train-fields", type=int, default=200)
+    ap.add_argument("--train-n", type=int, default=4096)
+    ap.add_argument("--train-views", type=int, default=8)
+    ap.add_argument("--train-res", type=int, default=256)
+    ap.add_argument("--fit-steps", type=int, default=300)
+    ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--workload", default="caustic1m")
+    ap.add_argument("--views", type=int, default=32)
+    ap.add_argument("--res", type=int, default=800)
+    ap.add_argument("--target", type=float, default=35.0)
+    ap.add_argument("--max-steps", type=int, default=1500)
+    ap.add_argument("--weights", default=None, help="load trained parameters (.npy) instead of training")
+    ap.add_argument("--save-weights", default=None)
+    a = ap.parse_args()
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    if a.weights:
+        net = LI.load(a.weights)
+        train_info = dict(weights=a.weights)
+    else:
+        gt_probe, _ = S.workload(a.workload, views=1, res=2, seed=7)
+        n_wall = int((gt_probe.surface != S.SURF_CLUSTER).sum()) if gt_probe.surface is not None else gt_probe.n
+        box = S.matched_box(a.train_n, n_wall)
+        seeds = list(range(100, 100 + a.train_fields))
+        X, Y = LI.build_dataset(seeds, a.train_n, box, a.train_views, a.train_res, a.fit_steps, log=log)
+        t_data = time.perf_counter() - t0
+        net, hist = LI.train(X, Y, a.epochs, log=log)
+        train_info = dict(fields=a.train_fields, n=a.train_n, box=box, samples=int(X.shape[0]),
+                          dataset_seconds=t_data, train_seconds=time.perf_counter() - t0 - t_data,
+                          epoch_mse=hist)
+        if a.save_weights:
+            LI.save(net, a.save_weights)
+    res = compare(net, a.workload, views=a.views, res=a.res, target_psnr=a.target,
+                  max_steps=a.max_steps)
+    res["training"] = train_info
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()

@@ -321,11 +321,12 @@ def hit_points(cams, return_surface=False):
 # ----------------------------------------------------------------------------
 # Photons (synthetic stand-in for the first photon-tracing pass)
 # ----------------------------------------------------------------------------
-def photons_from_field(f: Field, seed: int):
+def photons_from_field(f: Field, seed: int, box: float = 1.0):
     """One photon per Gaussian of a ground-truth field: the position is the
     centre plus isotropic noise of std 0.25 * (s0 s1 s2)^(1/3), projected back
     onto the Gaussian's surface (walls, sphere; cluster photons stay in the
     volume); the power is the flux times exp(N(0, 0.2^2)) per channel.
+    ``box`` is the edge of the scene box (1 for the unit box).
     Returns (pos [n,3] f32, power [n,3] f32)."""
     rng = np.random.default_rng(seed)
     n = f.n
@@ -333,16 +334,35 @@ def photons_from_field(f: Field, seed: int):
     pos = f.mu.astype(np.float64) + rng.normal(0, 1, (n, 3)) * (0.25 * s_geo)[:, None]
     pw = f.rgb.astype(np.float64) * np.exp(rng.normal(0, 0.2, (n, 3)))
     if f.surface is not None:
-        planes = {0: (1, 0.0), 1: (1, 1.0), 2: (0, 0.0), 3: (0, 1.0), 4: (2, 0.0)}
+        planes = {0: (1, 0.0), 1: (1, box), 2: (0, 0.0), 3: (0, box), 4: (2, 0.0)}
         for s, (axis, val) in planes.items():
             m = f.surface == s
             pos[m, axis] = val
             others = [a for a in range(3) if a != axis]
-            pos[np.ix_(m, others)] = np.clip(pos[np.ix_(m, others)], 0.0, 1.0)
+            pos[np.ix_(m, others)] = np.clip(pos[np.ix_(m, others)], 0.0, box)
         m = f.surface == SURF_SPHERE
-        v = pos[m] - SPHERE_C
-        pos[m] = SPHERE_C + SPHERE_R * v / np.linalg.norm(v, axis=1, keepdims=True)
+        c = SPHERE_C * box
+        v = pos[m] - c
+        pos[m] = c + SPHERE_R * box * v / np.linalg.norm(v, axis=1, keepdims=True)
     return _f32(pos), _f32(pw)
+
+
+def scaled_scene(n: int, seed: int, box: float, views: int, res: int):
+    """The box + sphere surface field of n Gaussians (seed) with every centre,
+    camera and hit point scaled into a box of edge ``box``; Gaussian shapes are
+    unchanged, so shrinking the box raises the photon density.  Returns
+    (field, hit points [views*res*res, 3] f32)."""
+    f = make_surface_field(n, seed)
+    f = Field(_f32(f.mu.astype(np.float64) * box), f.quat, f.log_scale, f.rgb, f.surface)
+    x = hit_points(camera_ring(views, res)).astype(np.float64) * box
+    return f, _f32(x)
+
+
+def matched_box(n_train: int, wall_photons_eval: int) -> float:
+    """Box edge at which n_train surface photons (five walls and the sphere)
+    have the wall density of ``wall_photons_eval`` photons on the five unit walls."""
+    area_unit = 5.0 + 4 * np.pi * SPHERE_R ** 2
+    return float(np.sqrt(n_train / area_unit / (wall_photons_eval / 5.0)))
 
 
 # ----------------------------------------------------------------------------
