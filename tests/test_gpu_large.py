@@ -1,0 +1,185 @@
+"""GPU parity at full workload sizes, in the launch configuration the
+benchmark times (cell 0.025, one grid over all views), on sampled outputs the
+FP64 oracle evaluates one by one:
+
+- 1,000,000 Gaussians (caustic cluster), 32 views at 800x800: forward on
+  sampled points; backward rows of 64 sampled primitives for a seeded
+  upstream gradient.
+- 200,000 Gaussians (fitting start field), 8 views at 512x512: loss gradient
+  of a 64-Gaussian subset against the oracle's analytic gradient and central
+  differences of the FP64 loss.
+- 4,000,000 Gaussians (anisotropy up to 100:1, two clusters), 64 views at
+  1024x1024: forward on sampled points.
+"""
+import numpy as np
+import pytest
+import torch
+from scipy.spatial import cKDTree
+
+from oracle import exact_cull as E
+from oracle import gpf_oracle as O
+from oracle.tolerances import check_forward, check_grads
+from paper_2512_12459_amd import scenes as S
+from tests.gpu_helpers import say
+
+pytestmark = pytest.mark.gpu
+CELL = 0.025
+
+
+@pytest.fixture(scope="module")
+def R():
+    from paper_2512_12459_amd import radiance
+    radiance.C.lib()
+    return radiance
+
+
+def _gpu_forward(R, f, x):
+    dev = [torch.from_numpy(a).cuda() for a in f.arrays()]
+    xd = torch.from_numpy(x).cuda()
+    qs = R.QuerySet(xd, CELL)
+    g = R.Grid(qs).build(*dev)
+    L = R.eval_radiance(g, *dev)
+    torch.cuda.synchronize()
+    return L, g, dev, qs
+
+
+def _support_queries(tree, f, rows):
+    """Indices of points within cutoff * max scale of any primitive in rows."""
+    rad = 3.0 * np.exp(f.log_scale[rows].astype(np.float64)).max(axis=1) * 1.001
+    hits = tree.query_ball_point(f.mu[rows].astype(np.float64), rad)
+    return np.unique(np.concatenate([np.asarray(h, np.int64) for h in hits]))
+
+
+def _pair_flags(f, rows, x, chunk=20000):
+    """Per point: does some primitive in rows contribute, or sit on its cutoff?"""
+    fr = O.primitive_frames(f.quat[rows], f.log_scale[rows])
+    s = fr["s"]
+    rho = s.max(1) / s.min(1)
+    mu = f.mu[rows].astype(np.float64)
+    inc = np.zeros(len(x), bool)
+    amb = np.zeros(len(x), bool)
+    for a in range(0, len(x), chunk):
+        d = x[a:a + chunk, None, :].astype(np.float64) - mu[None]
+        u = np.einsum("nkj,qnj->qnk", fr["W"], d)
+        m2 = np.sum(u * u, -1)
+        amb[a:a + chunk] = np.any(np.abs(m2 - 9.0) <= 1e-5 * rho[None], axis=1)
+        inc[a:a + chunk] = np.any(m2 <= 9.0, axis=1)
+    return inc, amb
+
+
+def test_caustic1m_full_size_forward_and_backward_rows(R):
+    f, x = S.workload("caustic1m")
+    q = x.shape[0]
+    say(f"case: caustic1m forward, n={f.n} q={q}")
+    L, g, dev, qs = _gpu_forward(R, f, x)
+    rng = np.random.default_rng(20)
+    sel = np.sort(rng.choice(q, 20000, replace=False))
+    ref = E.radiance(*f.arrays(), x[sel])
+    check_forward(L.cpu().numpy()[sel], ref)
+    assert ref["count"].mean() > 200
+
+    # backward: seeded upstream gradient; rows of 64 primitives with support
+    tree = cKDTree(x.astype(np.float64))
+    cand = rng.choice(f.n, 400, replace=False)
+    rows = []
+    for i in cand:
+        if len(_support_queries(tree, f, [i])) > 0:
+            rows.append(int(i))
+        if len(rows) == 64:
+            break
+    rows = np.array(sorted(rows))
+    sq = _support_queries(tree, f, rows)
+    inc, amb = _pair_flags(f, rows, x[sq])
+    dL = rng.normal(size=(q, 3)).astype(np.float32)
+    dL[sq[amb]] = 0.0            # points on a subset primitive's cutoff: either decision is valid
+    say(f"case: caustic1m backward rows, {len(rows)} primitives, {len(sq)} support points")
+    grads = R.eval_radiance_backward(g, *dev, torch.from_numpy(dL).cuda())
+    torch.cuda.synchronize()
+    gg = {k: v.cpu().numpy()[rows] for k, v in grads.items()}
+    gref = O.radiance_backward(*(a[rows] for a in f.arrays()), x[sq], dL[sq])
+    check_grads(gg, gref)
+
+
+def test_fit200k_subset_gradient_and_finite_differences(R):
+    gt, x = S.workload("fit200k")
+    f = S.perturb_field(gt, 2)       # fitting start field
+    q = x.shape[0]
+    rng = np.random.default_rng(3)
+    T = np.exp(rng.normal(0, 1, (q, 3))).astype(np.float32)   # synthetic targets
+    say(f"case: fit200k forward + loss gradient, n={f.n} q={q}")
+    L, g, dev, qs = _gpu_forward(R, f, x)
+    Ld = L
+    Td = torch.from_numpy(T).cuda()
+    _, dLd = R.mse_loss(Ld, Td)
+    tree = cKDTree(x.astype(np.float64))
+    rows = []
+    for i in rng.permutation(f.n):
+        if len(_support_queries(tree, f, [int(i)])) > 0:
+            inc, _ = _pair_flags(f, [int(i)], x[_support_queries(tree, f, [int(i)])])
+            if inc.any():
+                rows.append(int(i))
+        if len(rows) == 64:
+            break
+    rows = np.array(sorted(rows))
+    sq = _support_queries(tree, f, rows)
+    inc, amb = _pair_flags(f, rows, x[sq])
+    # oracle radiance (whole field) at the support points, and the loss gradient there
+    ref = E.radiance(*f.arrays(), x[sq])
+    check_forward(L.cpu().numpy()[sq], ref)
+    amb_any = amb | (ref["n_amb"] > 0)
+    dL_ref = 2.0 * (ref["L"] - T[sq]) / q
+    dL_ref[amb_any] = 0.0
+    dL_gpu = dLd.cpu().numpy()
+    dL_gpu[sq[amb_any]] = 0.0
+    # the GPU backward runs on its own loss gradient (the same up to the forward's rounding)
+    grads = R.eval_radiance_backward(g, *dev, torch.from_numpy(dL_gpu).cuda())
+    torch.cuda.synchronize()
+    gg = {k: v.cpu().numpy()[rows] for k, v in grads.items()}
+    gref = O.radiance_backward(*(a[rows] for a in f.arrays()), x[sq], dL_ref)
+    check_grads(gg, gref)
+
+    # central differences of the FP64 loss: only the perturbed primitive's
+    # contribution changes, L' = L - c_i(theta) + c_i(theta + h), on its own
+    # support points
+    base = {k: a.astype(np.float64) for k, a in zip(("mu", "quat", "log_scale", "rgb"), f.arrays())}
+    keys = ("mu", "quat", "log_scale", "rgb")
+    checked = 0
+    for j, i in enumerate(rows[:12]):
+        pts = _support_queries(tree, f, [i])
+        at = np.searchsorted(sq, pts)
+        own = O.radiance(*(base[k][i:i + 1] for k in keys), x[pts])
+        if own["n_amb"].any() or np.any(amb_any[at] & (own["count"] > 0)):
+            continue
+        L0, T0 = ref["L"][at], T[pts]
+        for name in keys:
+            for c in range(base[name].shape[1]):
+                h = 1e-6 * (abs(base[name][i, c]) if name == "rgb" else 1.0)
+                vals, flip = [], False
+                for sgn in (1, -1):
+                    p = {k: base[k][i:i + 1].copy() for k in keys}
+                    p[name][0, c] += sgn * h
+                    r = O.radiance(*(p[k] for k in keys), x[pts])
+                    flip |= not np.array_equal(r["count"], own["count"]) or bool(r["n_amb"].any())
+                    vals.append(np.sum((L0 - own["L"] + r["L"] - T0) ** 2) / q)
+                if flip:
+                    continue
+                fd = (vals[0] - vals[1]) / (2 * h)
+                scale = max(abs(fd), 1e-2 * np.max(np.abs(gg[name][j])))
+                assert abs(gg[name][j, c] - fd) <= 1e-4 * scale + 1e-12, (name, i, c, gg[name][j, c], fd)
+                checked += 1
+    assert checked >= 40
+
+
+def test_stress4m_full_size_forward(R):
+    f, x = S.workload("stress4m")
+    q = x.shape[0]
+    say(f"case: stress4m forward, n={f.n} q={q}")
+    L, g, dev, qs = _gpu_forward(R, f, x)
+    info = g.info()
+    say(f"grid bytes {info['device_bytes']}, query bytes {qs.info()['device_bytes']}, "
+        f"torch peak {torch.cuda.max_memory_allocated()}")
+    rng = np.random.default_rng(21)
+    sel = np.sort(rng.choice(q, 8000, replace=False))
+    ref = E.radiance(*f.arrays(), x[sel])
+    check_forward(L.cpu().numpy()[sel], ref)
+    assert ref["count"].mean() > 1000
