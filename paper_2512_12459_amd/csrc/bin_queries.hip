@@ -126,9 +126,13 @@ __global__ void cell_runs_kernel(const float4* __restrict__ xs, const uint64_t* 
   occ_dense[slot] = (c[2] * g.dy + c[1]) * g.dx + c[0];
 }
 
-__global__ void occ_table_kernel(const int* __restrict__ occ_dense, int ncells, int* occ_of_dense) {
+__global__ void occ_table_kernel(const int* __restrict__ occ_dense, int ncells, int* occ_of_dense,
+                                 uint32_t* occ_bits) {
   int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s < ncells) occ_of_dense[occ_dense[s]] = s;
+  if (s >= ncells) return;
+  const int d = occ_dense[s];
+  occ_of_dense[d] = s;
+  atomicOr(occ_bits + (d >> 5), 1u << (d & 31));
 }
 
 __global__ void tiles_per_cell_kernel(const int* __restrict__ cell_first, int ncells, int q,
@@ -322,9 +326,11 @@ gpf_status launch_bin_queries(const float* x, int64_t q, float cell, hipStream_t
   hipLaunchKernelGGL(cell_runs_kernel, dim3(nb), dim3(256), 0, s, out->xs, keys_s, flag, q, g,
                      cell_first, out->occ_dense);
   TRYH(hipMemsetAsync(out->occ_of_dense, 0xff, dense * 4, s), "occ table clear");
+  TRY(dev_alloc((void**)&out->occ_bits, ((dense + 31) / 32) * 4, "occupancy bits"));
+  TRYH(hipMemsetAsync(out->occ_bits, 0, ((dense + 31) / 32) * 4, s), "occupancy bits clear");
   int cb = (ncells + 255) / 256;
   hipLaunchKernelGGL(occ_table_kernel, dim3(cb), dim3(256), 0, s, out->occ_dense, ncells,
-                     out->occ_of_dense);
+                     out->occ_of_dense, out->occ_bits);
   TRY(dev_alloc((void**)&ntile, (int64_t)(ncells + 1) * 4, "ntile"));
   hipLaunchKernelGGL(tiles_per_cell_kernel, dim3(cb), dim3(256), 0, s, cell_first, ncells, (int)q,
                      ntile);
@@ -362,7 +368,7 @@ gpf_status launch_bin_queries(const float* x, int64_t q, float cell, hipStream_t
   cleanup();
 #undef TRY
 #undef TRYH
-  out->bytes = q * (sizeof(float4) + 4) + dense * 4 + (int64_t)ncells * 4 +
+  out->bytes = q * (sizeof(float4) + 4) + dense * 4 + ((dense + 31) / 32) * 4 + (int64_t)ncells * 4 +
                (int64_t)ntiles * (sizeof(TileInfo) + 2 * sizeof(float4)) +
                (int64_t)ngroups * (sizeof(GroupInfo) + 2 * sizeof(float4));
   return GPF_OK;

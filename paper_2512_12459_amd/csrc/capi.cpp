@@ -119,6 +119,7 @@ void gpf_queries_destroy(gpf_queries* qs) {
   dev_free(qs->perm, qs->q * sizeof(int));
   dev_free(qs->occ_of_dense, nd * sizeof(int));
   dev_free(qs->occ_dense, qs->ncells * sizeof(int));
+  dev_free(qs->occ_bits, ((nd + 31) / 32) * 4);
   dev_free(qs->tiles, qs->ntiles * sizeof(TileInfo));
   dev_free(qs->tile_lo, qs->ntiles * sizeof(float4));
   dev_free(qs->tile_hi, qs->ntiles * sizeof(float4));
@@ -173,9 +174,13 @@ void gpf_grid_destroy(gpf_grid* g) {
   int64_t nc = g->qs ? g->qs->ncells + 1 : 0;
   dev_free(g->rec, g->rec_cap * sizeof(PrimRec));
   dev_free(g->ext, g->rec_cap * sizeof(float4));
-  dev_free(g->cell_count, nc * sizeof(int));
+  dev_free(g->prim_off, (2 * g->rec_cap + 3) * sizeof(int));
   dev_free(g->cell_start, nc * sizeof(int));
+  dev_free(g->keys, g->cap * sizeof(int));
+  dev_free(g->vals, g->cap * sizeof(int));
+  dev_free(g->keys_sorted, g->cap * sizeof(int));
   dev_free(g->cell_prims, g->cap * sizeof(int));
+  dev_free(g->sort_tmp, g->sort_tmp_bytes);
   dev_free(g->grad_rows, g->grad_cap * sizeof(float4) * 4);
   delete g;
 }

@@ -54,6 +54,7 @@ struct gpf_queries {
   int* perm = nullptr;           // [q] sorted position -> caller index
   int* occ_of_dense = nullptr;   // [dims product] dense cell -> occupied slot or -1
   int* occ_dense = nullptr;      // [ncells] occupied slot -> dense cell
+  uint32_t* occ_bits = nullptr;  // [ceil(dims product / 32)] occupancy bit per dense cell
   gpf::TileInfo* tiles = nullptr;  // [ntiles]
   float4* tile_lo = nullptr;     // [ntiles] tight box of the tile's points
   float4* tile_hi = nullptr;
@@ -72,9 +73,14 @@ struct gpf_grid {
   gpf::PrimRec* rec = nullptr;  // [n]
   float4* ext = nullptr;        // [n] half-extents of the cutoff box; w = 1 if valid
   int64_t rec_cap = 0;
-  int* cell_count = nullptr;    // [ncells + 1]
+  int* prim_off = nullptr;      // [n + 1] per-primitive entry counts, scanned in place
   int* cell_start = nullptr;    // [ncells + 1]
-  int* cell_prims = nullptr;    // [cap]
+  int* keys = nullptr;          // [cap] cell slot per entry (primitive-major)
+  int* vals = nullptr;          // [cap] primitive per entry (primitive-major)
+  int* keys_sorted = nullptr;   // [cap]
+  int* cell_prims = nullptr;    // [cap] primitives of each cell, ascending
+  void* sort_tmp = nullptr;
+  size_t sort_tmp_bytes = 0;
   int64_t cap = 0;
   int64_t entries = 0;
   float4* grad_rows = nullptr;  // [n][4] backward scratch: one 64-byte row per primitive

@@ -1,9 +1,14 @@
 // Grid build: per-primitive frame (FP64 -> FP32 record), then registration of
-// every primitive in the occupied query cells its cutoff ellipsoid may touch.
+// every primitive in the occupied query cells its cutoff ellipsoid may touch:
+// count per primitive -> scan -> emit (cell, primitive) entries in primitive
+// order -> stable radix sort by cell, so each cell lists its primitives in
+// ascending index order (deterministic sums downstream).
+#include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/device/device_scan.hpp>
+
 #include <cmath>
 
 #include "common.h"
-#include "scan.h"
 
 namespace gpf {
 namespace {
@@ -84,61 +89,105 @@ __device__ __forceinline__ bool box_may_touch(const PrimRec& r, float bx, float 
   return acc <= c2 * 1.001f;
 }
 
+// Visits the occupied cells of the primitive's cutoff box that pass the
+// whitened-frame test; counts them, or (kEmit) writes (cell slot, primitive)
+// entries from `base` on.  Both passes read the same stored record and
+// extents, so they make identical decisions.
 template <bool kEmit>
-__global__ void __launch_bounds__(256) register_kernel(
-    const float* __restrict__ mu, const float* __restrict__ quat, const float* __restrict__ ls,
-    const float* __restrict__ rgb, int n, float cutoff, Geom g, const int* __restrict__ occ_of_dense,
-    PrimRec* __restrict__ recs, float4* __restrict__ exts, int* __restrict__ cell_count,
-    const int* __restrict__ cell_start, int* __restrict__ cell_prims, int* __restrict__ bad) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  PrimRec r;
-  float ext[3];
-  if (!kEmit) {
-    bool ok = prim_frame(mu, quat, ls, rgb, i, cutoff, &r, ext);
-    recs[i] = r;
-    exts[i] = make_float4(ext[0], ext[1], ext[2], ok ? 1.f : 0.f);
-    if (!ok) {
-      atomicAdd(bad, 1);
-      return;
-    }
-  } else {
-    float4 e = exts[i];
-    if (e.w == 0.f) return;
-    r = recs[i];
-    ext[0] = e.x;
-    ext[1] = e.y;
-    ext[2] = e.z;
-  }
-  const float c2 = (float)(kKappa2 * cutoff * cutoff);
+__device__ __forceinline__ int visit_cells(const PrimRec& r, const float ext[3], const Geom& g,
+                                           const uint32_t* __restrict__ bits,
+                                           const int* __restrict__ occ_of_dense, float c2, int pid,
+                                           int* __restrict__ keys, int* __restrict__ vals,
+                                           int base, int limit) {
   const float inv = 1.f / g.h;
-  float m[3] = {r.r0.x, r.r0.y, r.r0.z};
-  float o[3] = {g.ox, g.oy, g.oz};
-  int d[3] = {g.dx, g.dy, g.dz};
+  const float m[3] = {r.r0.x, r.r0.y, r.r0.z};
+  const float o[3] = {g.ox, g.oy, g.oz};
+  const int d[3] = {g.dx, g.dy, g.dz};
   int lo[3], hi[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    float a0 = (m[a] - ext[a] - o[a]) * inv;
-    float a1 = (m[a] + ext[a] - o[a]) * inv;
-    if (a1 < -1e-3f || a0 > (float)d[a] + 1e-3f) return;  // box misses the grid
+    const float a0 = (m[a] - ext[a] - o[a]) * inv;
+    const float a1 = (m[a] + ext[a] - o[a]) * inv;
+    if (a1 < -1e-3f || a0 > (float)d[a] + 1e-3f) return 0;  // box misses the grid
     lo[a] = max(0, (int)floorf(a0 - 1e-3f));
     hi[a] = min(d[a] - 1, (int)floorf(a1 + 1e-3f));
   }
   const float hh = 0.5f * g.h;
+  int cnt = 0;
   for (int cz = lo[2]; cz <= hi[2]; ++cz)
-    for (int cy = lo[1]; cy <= hi[1]; ++cy)
+    for (int cy = lo[1]; cy <= hi[1]; ++cy) {
+      const int row = (cz * g.dy + cy) * g.dx;
       for (int cx = lo[0]; cx <= hi[0]; ++cx) {
-        int slot = occ_of_dense[(cz * g.dy + cy) * g.dx + cx];
-        if (slot < 0) continue;
-        float bx = o[0] + (cx + 0.5f) * g.h, by = o[1] + (cy + 0.5f) * g.h,
-              bz = o[2] + (cz + 0.5f) * g.h;
+        const int dc = row + cx;
+        if (!((bits[dc >> 5] >> (dc & 31)) & 1u)) continue;
+        const float bx = o[0] + (cx + 0.5f) * g.h, by = o[1] + (cy + 0.5f) * g.h,
+                    bz = o[2] + (cz + 0.5f) * g.h;
         if (!box_may_touch(r, bx, by, bz, hh, c2)) continue;
-        int pos = atomicAdd(&cell_count[slot], 1);
-        // the emit pass repeats the counting pass's decisions on the same
-        // stored record; the bound keeps every write inside the cell's range
-        if (kEmit && pos < cell_start[slot + 1] - cell_start[slot])
-          cell_prims[cell_start[slot] + pos] = i;
+        if (kEmit && cnt < limit) {
+          keys[base + cnt] = occ_of_dense[dc];
+          vals[base + cnt] = pid;
+        }
+        ++cnt;
       }
+    }
+  return cnt;
+}
+
+// Pass 1: frame of every primitive (FP64 -> FP32 record, cutoff box) and the
+// number of cells it registers in; `bad` counts degenerate primitives.
+__global__ void __launch_bounds__(256) count_kernel(
+    const float* __restrict__ mu, const float* __restrict__ quat, const float* __restrict__ ls,
+    const float* __restrict__ rgb, int n, float cutoff, Geom g, const uint32_t* __restrict__ bits,
+    const int* __restrict__ occ_of_dense, PrimRec* __restrict__ recs, float4* __restrict__ exts,
+    int* __restrict__ prim_cnt, int* __restrict__ bad) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  PrimRec r;
+  float ext[3];
+  const bool ok = prim_frame(mu, quat, ls, rgb, i, cutoff, &r, ext);
+  recs[i] = r;
+  exts[i] = make_float4(ext[0], ext[1], ext[2], ok ? 1.f : 0.f);
+  if (!ok) {
+    prim_cnt[i] = 0;
+    atomicAdd(bad, 1);
+    return;
+  }
+  const float c2 = (float)(kKappa2 * cutoff * cutoff);
+  prim_cnt[i] = visit_cells<false>(r, ext, g, bits, occ_of_dense, c2, i, nullptr, nullptr, 0, 0);
+}
+
+// Pass 2: entries in primitive-major order at the scanned offsets.
+__global__ void __launch_bounds__(256) emit_kernel(int n, float cutoff, Geom g,
+                                                   const uint32_t* __restrict__ bits,
+                                                   const int* __restrict__ occ_of_dense,
+                                                   const PrimRec* __restrict__ recs,
+                                                   const float4* __restrict__ exts,
+                                                   const int* __restrict__ prim_off,
+                                                   int* __restrict__ keys, int* __restrict__ vals) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float4 e = exts[i];
+  if (e.w == 0.f) return;
+  const float ext[3] = {e.x, e.y, e.z};
+  const float c2 = (float)(kKappa2 * cutoff * cutoff);
+  const int base = prim_off[i];
+  // never write past this primitive's range, whatever the visit decides
+  visit_cells<true>(recs[i], ext, g, bits, occ_of_dense, c2, i, keys, vals, base,
+                    prim_off[i + 1] - base);
+}
+
+// cell_start[c] = first sorted entry with key >= c (binary search).
+__global__ void cell_start_kernel(const int* __restrict__ keys, int E, int ncells,
+                                  int* __restrict__ cell_start) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c > ncells) return;
+  int lo = 0, hi = E;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (keys[mid] < c) lo = mid + 1;
+    else hi = mid;
+  }
+  cell_start[c] = lo;
 }
 
 }  // namespace
@@ -150,61 +199,101 @@ gpf_status launch_build_grid(gpf_grid* g, hipStream_t s) {
   if (g->rec_cap < n) {
     dev_free(g->rec, g->rec_cap * sizeof(PrimRec));
     dev_free(g->ext, g->rec_cap * sizeof(float4));
+    dev_free(g->prim_off, (2 * g->rec_cap + 3) * sizeof(int));
     g->rec = nullptr;
     g->ext = nullptr;
+    g->prim_off = nullptr;
     g->rec_cap = 0;
-    gpf_status st = dev_alloc((void**)&g->rec, (size_t)n * sizeof(PrimRec), "grid records");
-    if (st != GPF_OK) return st;
-    st = dev_alloc((void**)&g->ext, (size_t)n * sizeof(float4), "grid extents");
-    if (st != GPF_OK) {
+    gpf_status st;
+    if ((st = dev_alloc((void**)&g->rec, (size_t)n * sizeof(PrimRec), "grid records")) != GPF_OK ||
+        (st = dev_alloc((void**)&g->ext, (size_t)n * sizeof(float4), "grid extents")) != GPF_OK ||
+        (st = dev_alloc((void**)&g->prim_off, (size_t)(2 * n + 3) * sizeof(int), "grid counts")) !=
+            GPF_OK) {
       dev_free(g->rec, (size_t)n * sizeof(PrimRec));
+      dev_free(g->ext, (size_t)n * sizeof(float4));
       g->rec = nullptr;
+      g->ext = nullptr;
       return st;
     }
     g->rec_cap = n;
   }
-  if (!g->cell_count) {
-    gpf_status st = dev_alloc((void**)&g->cell_count, (size_t)(nc + 1) * sizeof(int), "cell counts");
-    if (st != GPF_OK) return st;
-    st = dev_alloc((void**)&g->cell_start, (size_t)(nc + 1) * sizeof(int), "cell starts");
+  if (!g->cell_start) {
+    gpf_status st = dev_alloc((void**)&g->cell_start, (size_t)(nc + 1) * sizeof(int), "cell starts");
     if (st != GPF_OK) return st;
   }
   Geom geo{qs->origin[0], qs->origin[1], qs->origin[2], qs->cell, qs->dims[0], qs->dims[1],
            qs->dims[2]};
-  // cell_count[nc] doubles as the degenerate-primitive counter during counting
-  GPF_HIP(hipMemsetAsync(g->cell_count, 0, (size_t)(nc + 1) * sizeof(int), s));
-  int nb = (n + 255) / 256;
-  hipLaunchKernelGGL(register_kernel<false>, dim3(nb), dim3(256), 0, s, g->mu, g->quat, g->log_scale,
-                     g->rgb, n, g->cutoff, geo, qs->occ_of_dense, g->rec, g->ext, g->cell_count,
-                     (const int*)nullptr, (int*)nullptr, g->cell_count + nc);
+  const int nb = (n + 255) / 256;
+  // counts: prim_off[0 .. n] (entry n stays 0), degenerate counter at n + 1;
+  // offsets: prim_off[n + 2 .. 2n + 2]
+  int* cnt = g->prim_off;
+  int* off = g->prim_off + n + 2;
+  GPF_HIP(hipMemsetAsync(cnt + n, 0, 2 * sizeof(int), s));
+  hipLaunchKernelGGL(count_kernel, dim3(nb), dim3(256), 0, s, g->mu, g->quat, g->log_scale, g->rgb,
+                     n, g->cutoff, geo, qs->occ_bits, qs->occ_of_dense, g->rec, g->ext, cnt,
+                     cnt + n + 1);
+  size_t scan_bytes = 0;
+  GPF_HIP(rocprim::exclusive_scan(nullptr, scan_bytes, cnt, off, 0, (size_t)(n + 1),
+                                  rocprim::plus<int>(), s));
+  if (g->sort_tmp_bytes < scan_bytes) {
+    dev_free(g->sort_tmp, g->sort_tmp_bytes);
+    g->sort_tmp = nullptr;
+    g->sort_tmp_bytes = 0;
+    gpf_status st = dev_alloc(&g->sort_tmp, scan_bytes, "scan scratch");
+    if (st != GPF_OK) return st;
+    g->sort_tmp_bytes = scan_bytes;
+  }
   int host[2] = {0, 0};
-  GPF_HIP(hipMemcpyAsync(&host[1], g->cell_count + nc, sizeof(int), hipMemcpyDeviceToHost, s));
-  GPF_HIP(hipMemsetAsync(g->cell_count + nc, 0, sizeof(int), s));
-  hipLaunchKernelGGL(scan_exclusive_kernel, dim3(1), dim3(kScanThreads), 0, s, g->cell_count,
-                     g->cell_start, nc);
-  GPF_HIP(hipMemcpyAsync(&host[0], g->cell_start + nc, sizeof(int), hipMemcpyDeviceToHost, s));
+  size_t tb = g->sort_tmp_bytes;
+  GPF_HIP(rocprim::exclusive_scan(g->sort_tmp, tb, cnt, off, 0, (size_t)(n + 1),
+                                  rocprim::plus<int>(), s));
+  GPF_HIP(hipMemcpyAsync(&host[1], cnt + n + 1, sizeof(int), hipMemcpyDeviceToHost, s));
+  GPF_HIP(hipMemcpyAsync(&host[0], off + n, sizeof(int), hipMemcpyDeviceToHost, s));
   GPF_HIP(hipStreamSynchronize(s));
   if (host[1] > 0)
     return set_error(GPF_ERR_INVALID_ARGUMENT,
                      "field has a zero-norm quaternion or a non-finite parameter");
-  int64_t E = host[0];
+  const int64_t E = host[0];
   if (E < 0) return set_error(GPF_ERR_CAPACITY, "more than 2^31-1 cell-primitive entries");
   if (g->cap < E) {
-    dev_free(g->cell_prims, g->cap * sizeof(int));
-    g->cell_prims = nullptr;
+    int** bufs[4] = {&g->keys, &g->vals, &g->keys_sorted, &g->cell_prims};
+    for (auto b : bufs) {
+      dev_free(*b, g->cap * sizeof(int));
+      *b = nullptr;
+    }
     g->cap = 0;
-    int64_t want = E + E / 8 + 1024;
-    gpf_status st = dev_alloc((void**)&g->cell_prims, (size_t)want * sizeof(int), "cell lists");
-    if (st != GPF_OK) return st;
+    const int64_t want = E + E / 8 + 1024;
+    for (auto b : bufs) {
+      gpf_status st = dev_alloc((void**)b, (size_t)want * sizeof(int), "cell lists");
+      if (st != GPF_OK) return st;
+    }
     g->cap = want;
   }
   g->entries = E;
-  GPF_HIP(hipMemsetAsync(g->cell_count, 0, (size_t)nc * sizeof(int), s));
-  hipLaunchKernelGGL(register_kernel<true>, dim3(nb), dim3(256), 0, s, g->mu, g->quat, g->log_scale,
-                     g->rgb, n, g->cutoff, geo, qs->occ_of_dense, g->rec, g->ext, g->cell_count,
-                     g->cell_start, g->cell_prims, (int*)nullptr);
+  hipLaunchKernelGGL(emit_kernel, dim3(nb), dim3(256), 0, s, n, g->cutoff, geo, qs->occ_bits,
+                     qs->occ_of_dense, g->rec, g->ext, off, g->keys, g->vals);
+  // stable sort by cell slot: each cell's primitives end up in ascending order
+  int bits_needed = 1;
+  while ((1 << bits_needed) <= nc) ++bits_needed;
+  size_t sort_bytes = 0;
+  GPF_HIP(rocprim::radix_sort_pairs(nullptr, sort_bytes, g->keys, g->keys_sorted, g->vals,
+                                    g->cell_prims, (size_t)E, 0, bits_needed, s));
+  if (g->sort_tmp_bytes < sort_bytes) {
+    dev_free(g->sort_tmp, g->sort_tmp_bytes);
+    g->sort_tmp = nullptr;
+    g->sort_tmp_bytes = 0;
+    gpf_status st = dev_alloc(&g->sort_tmp, sort_bytes, "sort scratch");
+    if (st != GPF_OK) return st;
+    g->sort_tmp_bytes = sort_bytes;
+  }
+  sort_bytes = g->sort_tmp_bytes;
+  GPF_HIP(rocprim::radix_sort_pairs(g->sort_tmp, sort_bytes, g->keys, g->keys_sorted, g->vals,
+                                    g->cell_prims, (size_t)E, 0, bits_needed, s));
+  hipLaunchKernelGGL(cell_start_kernel, dim3((nc + 256) / 256), dim3(256), 0, s, g->keys_sorted,
+                     (int)E, nc, g->cell_start);
   GPF_HIP(hipGetLastError());
-  g->bytes = g->rec_cap * (sizeof(PrimRec) + sizeof(float4)) + 2 * (size_t)(nc + 1) * sizeof(int) + g->cap * sizeof(int);
+  g->bytes = g->rec_cap * (sizeof(PrimRec) + sizeof(float4) + 2 * sizeof(int)) +
+             (size_t)(nc + 1) * sizeof(int) + 4 * g->cap * sizeof(int) + g->sort_tmp_bytes;
   return GPF_OK;
 }
 
