@@ -47,9 +47,9 @@ typedef struct gpf_queries gpf_queries; /* binned query points (opaque)       */
 typedef struct gpf_grid gpf_grid;       /* per-field cull structure (opaque)  */
 typedef struct gpf_mlp gpf_mlp;         /* learned initialiser (opaque)       */
 
-/* A field of n primitives: mu[n][3], quat[n][4] (w,x,y,z; any non-zero norm,
-   normalised inside), log_scale[n][3] (natural log of the per-axis standard
-   deviation), rgb[n][3] (flux Phi). */
+/* A field of n primitives (1 <= n <= 2^30 - 1): mu[n][3], quat[n][4]
+   (w,x,y,z; any non-zero norm, normalised inside), log_scale[n][3] (natural
+   log of the per-axis standard deviation), rgb[n][3] (flux Phi). */
 typedef struct {
   const float *mu, *quat, *log_scale, *rgb;
   int64_t n;

@@ -65,7 +65,7 @@ void dev_free(void* p, size_t bytes) {
 
 static bool field_ok(const gpf_field* f, std::string* why) {
   if (!f) { *why = "field is NULL"; return false; }
-  if (f->n < 1 || f->n > (int64_t)INT32_MAX) { *why = "field n out of range [1, 2^31-1]"; return false; }
+  if (f->n < 1 || f->n > ((int64_t)1 << 30) - 1) { *why = "field n out of range [1, 2^30-1]"; return false; }
   if (!f->mu || !f->quat || !f->log_scale || !f->rgb) { *why = "field has a NULL array"; return false; }
   return true;
 }

@@ -72,71 +72,84 @@ __device__ __forceinline__ int append_survivor(int* sv, int ns, bool pass, int p
 // ---------------------------------------------------------------------------
 // Forward
 // ---------------------------------------------------------------------------
-constexpr int kQpl = kGroupTiles;  // query points per lane in the forward
+constexpr int kFwdSurvCap = 256;   // staged survivors per wave
 
-// One wave per group of consecutive tiles of one cell (kQpl * 64 points):
-// lane l owns points l, l + 64, ...  The cell's candidates are culled against
-// the group box by lane = candidate into a per-wave LDS index list; every
-// survivor's record is then read once with wave-uniform scalar loads and
-// evaluated against all of the lane's points.
+// One wave per group of two consecutive tiles of one cell: lane l owns point l
+// of the first tile and point l of the second.  Lane = candidate culls the
+// cell's list against both tile boxes; a survivor is staged in LDS as
+// {index | tile mask << 30, b'} with b' = W' (mu - centre), centre = the group
+// box centre.  Every lane then evaluates each survivor for the tiles it may
+// touch (a wave-uniform branch per tile), reading W' and the flux with
+// wave-uniform scalar loads: u' = W' (x - centre) - b'.
 __global__ void __launch_bounds__(kWaves * 64) eval_fwd_kernel(
     const float4* __restrict__ xs, const int* __restrict__ perm,
     const GroupInfo* __restrict__ groups, const float4* __restrict__ glo,
-    const float4* __restrict__ ghi, int ngroups, const int* __restrict__ cell_start,
+    const float4* __restrict__ ghi, int ngroups, const float4* __restrict__ tlo,
+    const float4* __restrict__ thi, const int* __restrict__ cell_start,
     const int* __restrict__ cell_prims, const PrimRec* __restrict__ recs, float c2,
     float* __restrict__ L) {
-  __shared__ int surv[kWaves][kSurvCap];
+  static_assert(kGroupTiles == 2, "the forward pairs the two tiles of a group");
+  __shared__ int4 surv[kWaves][kFwdSurvCap];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int g = xcd_remap(blockIdx.x) * kWaves + wave;
   if (g >= ngroups) return;
   const GroupInfo gi = groups[g];
-  const TileCtx tc = tile_ctx(glo, ghi, g);
-  float px[kQpl], py[kQpl], pz[kQpl], acc[kQpl][3];
+  const TileCtx gc = tile_ctx(glo, ghi, g);
+  const TileCtx ta = tile_ctx(tlo, thi, gi.first_tile);
+  const bool has_b = gi.count > kTile;
+  const TileCtx tb = has_b ? tile_ctx(tlo, thi, gi.first_tile + 1) : ta;
+  float px[2], py[2], pz[2], acc[2][3];
 #pragma unroll
-  for (int i = 0; i < kQpl; ++i) {
+  for (int i = 0; i < 2; ++i) {
     const float4 p = xs[gi.start + min(lane + 64 * i, gi.count - 1)];
-    px[i] = p.x;
-    py[i] = p.y;
-    pz[i] = p.z;
+    px[i] = p.x - gc.cx;
+    py[i] = p.y - gc.cy;
+    pz[i] = p.z - gc.cz;
     acc[i][0] = acc[i][1] = acc[i][2] = 0.f;
   }
   const int cs = cell_start[gi.cell], ce = cell_start[gi.cell + 1];
-  int* sv = surv[wave];
+  int4* sv = surv[wave];
   int ns = 0;
   for (int base = cs; base < ce; base += 64) {
     const int j = base + lane;
-    bool pass = false;
-    int pid = 0;
+    int mask = 0, pid = 0;
+    float b0 = 0.f, b1 = 0.f, b2 = 0.f;
     if (j < ce) {
       pid = cell_prims[j];
-      pass = tile_may_touch(recs[pid], tc, c2);
+      const PrimRec r = recs[pid];
+      mask = (tile_may_touch(r, ta, c2) ? 1 : 0) | ((has_b && tile_may_touch(r, tb, c2)) ? 2 : 0);
+      if (mask) {
+        const float mx = r.r0.x - gc.cx, my = r.r0.y - gc.cy, mz = r.r0.z - gc.cz;
+        b0 = r.r1.x * mx + r.r1.y * my + r.r1.z * mz;
+        b1 = r.r2.x * mx + r.r2.y * my + r.r2.z * mz;
+        b2 = r.r3.x * mx + r.r3.y * my + r.r3.z * mz;
+      }
     }
-    ns = append_survivor(sv, ns, pass, pid, lane);
-    if (ns > kSurvCap - 64 || base + 64 >= ce) {
+    const uint64_t bal = __ballot(mask != 0);
+    if (mask) {
+      const uint64_t below = bal & ((lane == 0) ? 0ull : (~0ull >> (64 - lane)));
+      sv[ns + __popcll(below)] =
+          make_int4(pid | (mask << 30), __float_as_int(b0), __float_as_int(b1), __float_as_int(b2));
+    }
+    ns += __popcll(bal);
+    if (ns > kFwdSurvCap - 64 || base + 64 >= ce) {
       wave_sync_lds();
-      // two survivors per scalar fetch; an odd tail repeats the last record
-      // with its weights masked to zero
-      for (int s = 0; s < ns; s += 2) {
-        const int ida = __builtin_amdgcn_readfirstlane(sv[s]);
-        const int idb = __builtin_amdgcn_readfirstlane(sv[min(s + 1, ns - 1)]);
-        const PrimRec rp[2] = {recs[ida], recs[idb]};
-        const bool has_b = s + 1 < ns;
+      for (int s = 0; s < ns; ++s) {
+        const int4 e = sv[s];
+        const int head = __builtin_amdgcn_readfirstlane(e.x);
+        const PrimRec r = recs[head & 0x3fffffff];
+        const float nb0 = -__int_as_float(e.y), nb1 = -__int_as_float(e.z), nb2 = -__int_as_float(e.w);
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const PrimRec& r = rp[h];
-#pragma unroll
-          for (int i = 0; i < kQpl; ++i) {
-            const float dx = px[i] - r.r0.x, dy = py[i] - r.r0.y, dz = pz[i] - r.r0.z;
-            const float u0 = r.r1.x * dx + r.r1.y * dy + r.r1.z * dz;
-            const float u1 = r.r2.x * dx + r.r2.y * dy + r.r2.z * dz;
-            const float u2 = r.r3.x * dx + r.r3.y * dy + r.r3.z * dz;
-            const float m2 = u0 * u0 + u1 * u1 + u2 * u2;
-            const bool in = (m2 <= c2) && (h == 0 || has_b);
-            const float w = in ? __builtin_amdgcn_exp2f(-m2) : 0.f;
-            acc[i][0] += w * r.r0.w;
-            acc[i][1] += w * r.r1.w;
-            acc[i][2] += w * r.r2.w;
-          }
+        for (int i = 0; i < 2; ++i) {
+          if (!((head >> (30 + i)) & 1)) continue;   // wave-uniform
+          const float u0 = fmaf(r.r1.z, pz[i], fmaf(r.r1.y, py[i], fmaf(r.r1.x, px[i], nb0)));
+          const float u1 = fmaf(r.r2.z, pz[i], fmaf(r.r2.y, py[i], fmaf(r.r2.x, px[i], nb1)));
+          const float u2 = fmaf(r.r3.z, pz[i], fmaf(r.r3.y, py[i], fmaf(r.r3.x, px[i], nb2)));
+          const float m2 = u0 * u0 + u1 * u1 + u2 * u2;
+          const float w = (m2 <= c2) ? __builtin_amdgcn_exp2f(-m2) : 0.f;
+          acc[i][0] += w * r.r0.w;
+          acc[i][1] += w * r.r1.w;
+          acc[i][2] += w * r.r2.w;
         }
       }
       ns = 0;
@@ -144,7 +157,7 @@ __global__ void __launch_bounds__(kWaves * 64) eval_fwd_kernel(
     }
   }
 #pragma unroll
-  for (int i = 0; i < kQpl; ++i) {
+  for (int i = 0; i < 2; ++i) {
     const int k = lane + 64 * i;
     if (k < gi.count) {
       const int o = perm[gi.start + k];
@@ -213,7 +226,7 @@ __global__ void __launch_bounds__(kWaves * 64) count_pairs_kernel(
 constexpr int kBwdThreads = 256;
 constexpr int kBwdWaves = kBwdThreads / 64;
 constexpr int kGroupQ = kTile * kGroupTiles;  // points per group (max, a multiple of 4)
-constexpr int kGSurvCap = 1024;               // group survivor slots
+constexpr int kListCap = 1024;                // survivor slots per list
 constexpr int kRowStride = 14;                // transpose row stride (13 values + flag)
 
 // Maps the per-primitive sums (kappa-scaled whitened frame, u' = kappa u,
@@ -280,21 +293,24 @@ __device__ __forceinline__ void grad_epilogue(const PrimRec& r, const float* __r
   out[12] = GP[2];
 }
 
-// One workgroup per group of consecutive tiles of one cell.  The cell's
-// candidates are culled once against the group's box into an LDS list; each
-// wave then takes 64 survivors at a time (lane = primitive), loops over all of
-// the group's points (broadcast from LDS), and adds the resulting 13-value
-// gradient rows to a padded per-primitive buffer with row-coalesced atomics
-// (16 lanes update one 64-byte row per instruction).
+// One workgroup per group of two consecutive tiles of one cell.  The cell's
+// candidates are culled once against both tile boxes into three LDS lists
+// (first tile only, second tile only, both); each wave takes 64 survivors at a
+// time (lane = primitive) and loops over the points of the tiles they touch
+// (broadcast from LDS, relative to the group centre).  The
+// resulting 13-value gradient rows are added to a padded per-primitive buffer
+// with row-coalesced atomics (16 lanes update one 64-byte row per instruction).
 __global__ void __launch_bounds__(kBwdThreads) eval_bwd_kernel(
     const float4* __restrict__ xs, const int* __restrict__ perm,
     const GroupInfo* __restrict__ groups, const float4* __restrict__ glo,
-    const float4* __restrict__ ghi, int ngroups, const int* __restrict__ cell_start,
+    const float4* __restrict__ ghi, int ngroups, const float4* __restrict__ tlo,
+    const float4* __restrict__ thi, const int* __restrict__ cell_start,
     const int* __restrict__ cell_prims, const PrimRec* __restrict__ recs,
     const float* __restrict__ quat, const float* __restrict__ ls, float c2,
     const float* __restrict__ dL, float* __restrict__ grad_rows) {
-  __shared__ int sv[kGSurvCap];
-  __shared__ int sv_count;
+  static_assert(kGroupTiles == 2, "the backward splits survivors over the two tiles of a group");
+  __shared__ int sv[3][kListCap];
+  __shared__ int sv_count[3];
   __shared__ float4 qx_s[kGroupQ];
   __shared__ float4 qg_s[kGroupQ];
   __shared__ float rows_s[kBwdWaves][64 * kRowStride];
@@ -303,10 +319,12 @@ __global__ void __launch_bounds__(kBwdThreads) eval_bwd_kernel(
   if (gidx >= ngroups) return;  // uniform for the workgroup
   const GroupInfo gi = groups[gidx];
   const TileCtx tc = tile_ctx(glo, ghi, gidx);
-  // points relative to the group centre; the tail up to a multiple of 4 gets
-  // a zero upstream gradient, so its pairs contribute exactly nothing
-  const int nq4 = (gi.count + 3) & ~3;
-  for (int k = tid; k < nq4; k += kBwdThreads) {
+  const TileCtx ta = tile_ctx(tlo, thi, gi.first_tile);
+  const bool has_b = gi.count > kTile;
+  const TileCtx tb = has_b ? tile_ctx(tlo, thi, gi.first_tile + 1) : ta;
+  // points relative to the group centre; slots past the group's points get a
+  // zero upstream gradient, so their pairs contribute exactly nothing
+  for (int k = tid; k < kGroupQ; k += kBwdThreads) {
     if (k < gi.count) {
       const int o = perm[gi.start + k];
       const float4 p = xs[gi.start + k];
@@ -317,36 +335,58 @@ __global__ void __launch_bounds__(kBwdThreads) eval_bwd_kernel(
       qg_s[k] = make_float4(0.f, 0.f, 0.f, 0.f);
     }
   }
-  if (tid == 0) sv_count = 0;
+  if (tid < 3) sv_count[tid] = 0;
   __syncthreads();
+  // point ranges (multiples of 4) of the three lists
+  const int qe_a = (min(gi.count, kTile) + 3) & ~3, qe_all = (gi.count + 3) & ~3;
   const int cs = cell_start[gi.cell], ce = cell_start[gi.cell + 1];
   for (int base = cs; base < ce; base += kBwdThreads) {
     const int j = base + tid;
-    bool pass = false;
-    int pid = 0;
+    int mask = 0, pid = 0;
     if (j < ce) {
       pid = cell_prims[j];
-      pass = tile_may_touch(recs[pid], tc, c2);
+      const PrimRec r = recs[pid];
+      mask = (tile_may_touch(r, ta, c2) ? 1 : 0) | ((has_b && tile_may_touch(r, tb, c2)) ? 2 : 0);
     }
-    const uint64_t b = __ballot(pass);
-    int off = 0;
-    if (lane == 0 && b) off = atomicAdd(&sv_count, (int)__popcll(b));
-    off = __shfl(off, 0, 64);
-    if (pass) {
-      const uint64_t below = b & ((lane == 0) ? 0ull : (~0ull >> (64 - lane)));
-      sv[off + __popcll(below)] = pid;
+#pragma unroll
+    for (int li = 0; li < 3; ++li) {
+      const bool pass = mask == li + 1;
+      const uint64_t b = __ballot(pass);
+      int off = 0;
+      if (lane == 0 && b) off = atomicAdd(&sv_count[li], (int)__popcll(b));
+      off = __shfl(off, 0, 64);
+      if (pass) {
+        const uint64_t below = b & ((lane == 0) ? 0ull : (~0ull >> (64 - lane)));
+        sv[li][off + __popcll(below)] = pid;
+      }
     }
     __syncthreads();
-    const int nsv = sv_count;
-    // every wave must read the count before any wave appends again
+    const int n0 = sv_count[0], n1 = sv_count[1], n2 = sv_count[2];
+    // every wave must read the counts before any wave appends again
     __syncthreads();
     const bool last = base + kBwdThreads >= ce;
-    if (nsv > kGSurvCap - kBwdThreads || (last && nsv > 0)) {
-      for (int chunk = wave * 64; chunk < nsv; chunk += kBwdThreads) {
-        const bool valid = chunk + lane < nsv;
-        const int id = valid ? sv[chunk + lane] : 0;
+    const int total = n0 + n1 + n2;
+    if (total > kListCap - kBwdThreads || (last && total)) {
+      // chunks of 64 over the survivors taken in the order first-tile-only,
+      // both, second-tile-only: all but at most two chunks are pure, and a
+      // chunk loops only over the points of the tiles its survivors touch
+      for (int chunk = 64 * wave; chunk < total; chunk += 64 * kBwdWaves) {
+        const int v = chunk + lane;
+        const bool valid = v < total;
+        int id = 0, cat = 0;
+        if (v < n0) {
+          id = sv[0][v];
+          cat = 1;
+        } else if (v < n0 + n2) {
+          id = sv[2][v - n0];
+          cat = 3;
+        } else if (valid) {
+          id = sv[1][v - n0 - n2];
+          cat = 2;
+        }
+        const bool use_a = __ballot(cat & 1) != 0, use_b = __ballot(cat & 2) != 0;
+        const int qb = use_a ? 0 : kTile, qe = use_b ? qe_all : qe_a;
         const PrimRec r = recs[id];
-        // offsets are taken from the group centre: u' = W' x' - b', b' = W' (mu - centre)
         const float mx = r.r0.x - tc.cx, my = r.r0.y - tc.cy, mz = r.r0.z - tc.cz;
         const float b0 = r.r1.x * mx + r.r1.y * my + r.r1.z * mz;
         const float b1 = r.r2.x * mx + r.r2.y * my + r.r2.z * mz;
@@ -354,7 +394,7 @@ __global__ void __launch_bounds__(kBwdThreads) eval_bwd_kernel(
         float GP[3] = {0.f, 0.f, 0.f}, A[3] = {0.f, 0.f, 0.f};
         float U[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
         bool any = false;
-        for (int k = 0; k < nq4; k += 4) {
+        for (int k = qb; k < qe; k += 4) {
           float4 xq[4], gq[4];
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
@@ -393,22 +433,22 @@ __global__ void __launch_bounds__(kBwdThreads) eval_bwd_kernel(
         float* rw = rows_s[wave];
 #pragma unroll
         for (int e = 0; e < 13; ++e) rw[lane * kRowStride + e] = write ? out[e] : 0.f;
-        rw[lane * kRowStride + 13] = write ? 1.f : 0.f;
+        rw[lane * kRowStride + 13] = __int_as_float(write ? id : -1);
         wave_sync_lds();
         // row-coalesced atomics: instruction r covers rows 4r..4r+3, 16 lanes each
         const int sub = lane >> 4, e = lane & 15;
 #pragma unroll 4
         for (int rr = 0; rr < 16; ++rr) {
           const int row = rr * 4 + sub;
-          if (e < 13 && rw[row * kRowStride + 13] != 0.f) {
-            const int rid = sv[chunk + row];
+          const int rid = __float_as_int(rw[row * kRowStride + 13]);
+          if (e < 13 && rid >= 0) {
             unsafeAtomicAdd(grad_rows + (int64_t)rid * 16 + e, rw[row * kRowStride + e]);
           }
         }
         wave_sync_lds();
       }
       __syncthreads();
-      if (tid == 0) sv_count = 0;
+      if (tid < 3) sv_count[tid] = 0;
       __syncthreads();
     }
   }
@@ -452,7 +492,7 @@ gpf_status launch_eval_fwd(const gpf_grid* g, float* L, hipStream_t s) {
   const float c2 = (float)(kKappa2 * g->cutoff * g->cutoff);
   hipLaunchKernelGGL(eval_fwd_kernel, dim3(xcd_grid(fwd_blocks(qs->ngroups))), dim3(kWaves * 64), 0, s,
                      qs->xs, qs->perm, qs->groups, qs->group_lo, qs->group_hi, (int)qs->ngroups,
-                     g->cell_start, g->cell_prims, g->rec, c2, L);
+                     qs->tile_lo, qs->tile_hi, g->cell_start, g->cell_prims, g->rec, c2, L);
   GPF_HIP(hipGetLastError());
   return GPF_OK;
 }
@@ -475,7 +515,7 @@ gpf_status launch_eval_bwd(const gpf_grid* gc, const float* dL, gpf_field_grad* 
   }
   hipLaunchKernelGGL(eval_bwd_kernel, dim3(xcd_grid(qs->ngroups)), dim3(kBwdThreads), 0, s, qs->xs,
                      qs->perm, qs->groups, qs->group_lo, qs->group_hi, (int)qs->ngroups,
-                     g->cell_start, g->cell_prims, g->rec, g->quat, g->log_scale, c2, dL,
+                     qs->tile_lo, qs->tile_hi, g->cell_start, g->cell_prims, g->rec, g->quat, g->log_scale, c2, dL,
                      (float*)g->grad_rows);
   hipLaunchKernelGGL(grad_finalize_kernel, dim3((unsigned)((g->n + 255) / 256)), dim3(256), 0, s,
                      g->grad_rows, (int)g->n, grad->mu, grad->quat, grad->log_scale, grad->rgb);
