@@ -35,6 +35,24 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def measured_traffic(kernel: str, workload: str, default_shape: bool):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE, each scaled by what the counter reads for a
+    plain copy of known size), or None when the summary was taken on another
+    workload or on a different kernel source."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "counters_caustic1m.json")
+    if workload != "caustic1m" or not default_shape or not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    with open(os.path.join(ROOT, rec["source"]), "rb") as fh:
+        if hashlib.sha256(fh.read()).hexdigest() != rec["source_sha256"]:
+            return None
+    k = rec["kernels"].get(kernel)
+    return None if k is None else float(k["hbm_bytes"])
+
+
 def cpu_baseline(field, x, sample: int, seed: int = 11):
     """The FP64 oracle (brute force over all primitives) forward + backward on
     a bounded random sample of query points, over a process pool."""
@@ -218,7 +236,10 @@ def main():
                          "torch_peak": torch.cuda.max_memory_allocated()},
         "roofline": {"bound": "alu", "kernel": f"eval_{dom}", "achieved": achieved / 1e12,
                      "peak": PEAK_FP32_VALU / 1e12, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_VALU, "traffic": None,
+                     "frac": achieved / PEAK_FP32_VALU,
+                     "traffic": measured_traffic(f"eval_{dom}_kernel", args.workload,
+                                                 not (args.views or args.res) and args.cell == 0.025),
+                     "traffic_unit": "bytes per launch",
                      "frac_of_nonpacked_peak": achieved / PEAK_FP32_NONPACKED,
                      "flops_per_pair": FLOPS_BWD if dom == "bwd" else FLOPS_FWD},
     }

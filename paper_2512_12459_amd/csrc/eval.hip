@@ -223,11 +223,11 @@ __global__ void __launch_bounds__(kWaves * 64) count_pairs_kernel(
 // ---------------------------------------------------------------------------
 // Backward
 // ---------------------------------------------------------------------------
-constexpr int kBwdThreads = 256;
-constexpr int kBwdWaves = kBwdThreads / 64;
+constexpr int kBwdWaves = 4;                  // independent waves per workgroup
+constexpr int kBwdThreads = kBwdWaves * 64;
 constexpr int kGroupQ = kTile * kGroupTiles;  // points per group (max, a multiple of 4)
-constexpr int kListCap = 1024;                // survivor slots per list
-constexpr int kRowStride = 14;                // transpose row stride (13 values + flag)
+constexpr int kListCap = 128;                 // survivor slots per list and wave
+constexpr int kRowStride = 14;                // transpose row stride (12 sums, pad, row id)
 
 // Maps the per-primitive sums (kappa-scaled whitened frame, u' = kappa u,
 // W' = kappa W) to the 13 parameter gradients:
@@ -293,194 +293,210 @@ __device__ __forceinline__ void grad_epilogue(const PrimRec& r, const float* __r
   out[12] = GP[2];
 }
 
-// One workgroup per group of two consecutive tiles of one cell.  The cell's
-// candidates are culled once against both tile boxes into three LDS lists
-// (first tile only, second tile only, both); each wave takes 64 survivors at a
-// time (lane = primitive) and loops over the points of the tiles they touch
-// (broadcast from LDS, relative to the group centre).  The
-// resulting 13-value gradient rows are added to a padded per-primitive buffer
-// with row-coalesced atomics (16 lanes update one 64-byte row per instruction).
+// 64 survivors (lane = primitive) against the points [qb, qe) of the wave's
+// group, held in LDS relative to the group centre (points past the group's
+// count carry a zero upstream gradient).  The 12 per-primitive sums are added
+// to the padded per-primitive buffer with row-coalesced atomics: after an LDS
+// transpose, 16 lanes update one 64-byte row per instruction.
+__device__ __forceinline__ void bwd_chunk(int id, bool valid, int qb, int qe, const TileCtx& tc,
+                                          const PrimRec* __restrict__ recs, float c2,
+                                          const float4* qx, const float4* qg, float* rw,
+                                          float* __restrict__ grad_rows, int lane) {
+  const PrimRec r = recs[id];
+  const float mx = r.r0.x - tc.cx, my = r.r0.y - tc.cy, mz = r.r0.z - tc.cz;
+  const float b0 = r.r1.x * mx + r.r1.y * my + r.r1.z * mz;
+  const float b1 = r.r2.x * mx + r.r2.y * my + r.r2.z * mz;
+  const float b2 = r.r3.x * mx + r.r3.y * my + r.r3.z * mz;
+  float GP[3] = {0.f, 0.f, 0.f}, A[3] = {0.f, 0.f, 0.f};
+  float U[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  bool any = false;
+  for (int k = qb; k < qe; k += 4) {
+    float4 xq[4], gq[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      xq[i] = qx[k + i];
+      gq[i] = qg[k + i];
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const float u0 = fmaf(r.r1.z, xq[i].z, fmaf(r.r1.y, xq[i].y, fmaf(r.r1.x, xq[i].x, -b0)));
+      const float u1 = fmaf(r.r2.z, xq[i].z, fmaf(r.r2.y, xq[i].y, fmaf(r.r2.x, xq[i].x, -b1)));
+      const float u2 = fmaf(r.r3.z, xq[i].z, fmaf(r.r3.y, xq[i].y, fmaf(r.r3.x, xq[i].x, -b2)));
+      const float m2 = u0 * u0 + u1 * u1 + u2 * u2;
+      const bool in = m2 <= c2;
+      const float w = in ? __builtin_amdgcn_exp2f(-m2) : 0.f;
+      any |= in;
+      const float a = gq[i].x * r.r0.w + gq[i].y * r.r1.w + gq[i].z * r.r2.w;
+      const float c = a * w;
+      GP[0] += w * gq[i].x;
+      GP[1] += w * gq[i].y;
+      GP[2] += w * gq[i].z;
+      const float cu0 = c * u0, cu1 = c * u1, cu2 = c * u2;
+      A[0] += cu0;
+      A[1] += cu1;
+      A[2] += cu2;
+      U[0] += cu0 * u0;
+      U[1] += cu0 * u1;
+      U[2] += cu0 * u2;
+      U[3] += cu1 * u1;
+      U[4] += cu1 * u2;
+      U[5] += cu2 * u2;
+    }
+  }
+  // the sums do not depend on the group centre (u' = W'(x - mu)), so they
+  // are added over groups as they are and mapped to parameter gradients once
+  // per primitive by the finalize pass
+  const bool write = valid && any;
+  const float sums[12] = {GP[0], GP[1], GP[2], A[0], A[1], A[2], U[0], U[1], U[2], U[3], U[4], U[5]};
+#pragma unroll
+  for (int e = 0; e < 12; ++e) rw[lane * kRowStride + e] = write ? sums[e] : 0.f;
+  rw[lane * kRowStride + 13] = __int_as_float(write ? id : -1);
+  wave_sync_lds();
+  // instruction rr covers rows 4 rr .. 4 rr + 3, 16 lanes each
+  const int sub = lane >> 4, e = lane & 15;
+#pragma unroll 4
+  for (int rr = 0; rr < 16; ++rr) {
+    const int row = rr * 4 + sub;
+    const int rid = __float_as_int(rw[row * kRowStride + 13]);
+    if (e < 12 && rid >= 0) unsafeAtomicAdd(grad_rows + (int64_t)rid * 16 + e, rw[row * kRowStride + e]);
+  }
+  wave_sync_lds();
+}
+
+// One wave per group of two consecutive tiles of one cell, with no
+// workgroup-wide synchronisation.  Lane = candidate culls the cell's list
+// against both tile boxes and pushes survivors onto three LDS stacks (first
+// tile only, second tile only, both).  A stack that holds 64 entries is
+// drained at once as a pure chunk over the points of its tiles; the
+// remainders (under 64 each) are taken at the end in the order
+// first-tile-only, both, second-tile-only, so a chunk loops over the second
+// tile only if one of its survivors may touch it, and over the first likewise.
 __global__ void __launch_bounds__(kBwdThreads) eval_bwd_kernel(
     const float4* __restrict__ xs, const int* __restrict__ perm,
     const GroupInfo* __restrict__ groups, const float4* __restrict__ glo,
     const float4* __restrict__ ghi, int ngroups, const float4* __restrict__ tlo,
     const float4* __restrict__ thi, const int* __restrict__ cell_start,
-    const int* __restrict__ cell_prims, const PrimRec* __restrict__ recs,
-    const float* __restrict__ quat, const float* __restrict__ ls, float c2,
+    const int* __restrict__ cell_prims, const PrimRec* __restrict__ recs, float c2,
     const float* __restrict__ dL, float* __restrict__ grad_rows) {
   static_assert(kGroupTiles == 2, "the backward splits survivors over the two tiles of a group");
-  __shared__ int sv[3][kListCap];
-  __shared__ int sv_count[3];
-  __shared__ float4 qx_s[kGroupQ];
-  __shared__ float4 qg_s[kGroupQ];
-  __shared__ float rows_s[kBwdWaves][64 * kRowStride];
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int gidx = xcd_remap(blockIdx.x);
-  if (gidx >= ngroups) return;  // uniform for the workgroup
-  const GroupInfo gi = groups[gidx];
-  const TileCtx tc = tile_ctx(glo, ghi, gidx);
+  __shared__ int sv_all[kBwdWaves][3][kListCap];
+  __shared__ float4 qx_all[kBwdWaves][kGroupQ];
+  __shared__ float4 qg_all[kBwdWaves][kGroupQ];
+  __shared__ float rows_all[kBwdWaves][64 * kRowStride];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int g = xcd_remap(blockIdx.x) * kBwdWaves + wave;
+  if (g >= ngroups) return;  // per wave: no workgroup barrier follows
+  const GroupInfo gi = groups[g];
+  const TileCtx tc = tile_ctx(glo, ghi, g);
   const TileCtx ta = tile_ctx(tlo, thi, gi.first_tile);
   const bool has_b = gi.count > kTile;
   const TileCtx tb = has_b ? tile_ctx(tlo, thi, gi.first_tile + 1) : ta;
-  // points relative to the group centre; slots past the group's points get a
-  // zero upstream gradient, so their pairs contribute exactly nothing
-  for (int k = tid; k < kGroupQ; k += kBwdThreads) {
+  float4* qx = qx_all[wave];
+  float4* qg = qg_all[wave];
+  int* sv0 = sv_all[wave][0];
+  int* sv1 = sv_all[wave][1];
+  int* sv2 = sv_all[wave][2];
+  float* rw = rows_all[wave];
+  for (int k = lane; k < kGroupQ; k += 64) {
     if (k < gi.count) {
       const int o = perm[gi.start + k];
       const float4 p = xs[gi.start + k];
-      qx_s[k] = make_float4(p.x - tc.cx, p.y - tc.cy, p.z - tc.cz, 0.f);
-      qg_s[k] = make_float4(dL[(int64_t)o * 3], dL[(int64_t)o * 3 + 1], dL[(int64_t)o * 3 + 2], 0.f);
+      qx[k] = make_float4(p.x - tc.cx, p.y - tc.cy, p.z - tc.cz, 0.f);
+      qg[k] = make_float4(dL[(int64_t)o * 3], dL[(int64_t)o * 3 + 1], dL[(int64_t)o * 3 + 2], 0.f);
     } else {
-      qx_s[k] = make_float4(0.f, 0.f, 0.f, 0.f);
-      qg_s[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+      qx[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+      qg[k] = make_float4(0.f, 0.f, 0.f, 0.f);
     }
   }
-  if (tid < 3) sv_count[tid] = 0;
-  __syncthreads();
-  // point ranges (multiples of 4) of the three lists
+  wave_sync_lds();
   const int qe_a = (min(gi.count, kTile) + 3) & ~3, qe_all = (gi.count + 3) & ~3;
+  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const int cs = cell_start[gi.cell], ce = cell_start[gi.cell + 1];
-  for (int base = cs; base < ce; base += kBwdThreads) {
-    const int j = base + tid;
+  int n0 = 0, n1 = 0, n2 = 0;  // stack heights, each below 64 between batches
+  for (int base = cs; base < ce; base += 64) {
+    const int j = base + lane;
     int mask = 0, pid = 0;
     if (j < ce) {
       pid = cell_prims[j];
       const PrimRec r = recs[pid];
       mask = (tile_may_touch(r, ta, c2) ? 1 : 0) | ((has_b && tile_may_touch(r, tb, c2)) ? 2 : 0);
     }
-#pragma unroll
-    for (int li = 0; li < 3; ++li) {
-      const bool pass = mask == li + 1;
-      const uint64_t b = __ballot(pass);
-      int off = 0;
-      if (lane == 0 && b) off = atomicAdd(&sv_count[li], (int)__popcll(b));
-      off = __shfl(off, 0, 64);
-      if (pass) {
-        const uint64_t below = b & ((lane == 0) ? 0ull : (~0ull >> (64 - lane)));
-        sv[li][off + __popcll(below)] = pid;
-      }
+    const uint64_t m0 = __ballot(mask == 1), m1 = __ballot(mask == 2), m2 = __ballot(mask == 3);
+    if (mask == 1) sv0[n0 + __popcll(m0 & below)] = pid;
+    if (mask == 2) sv1[n1 + __popcll(m1 & below)] = pid;
+    if (mask == 3) sv2[n2 + __popcll(m2 & below)] = pid;
+    n0 += __popcll(m0);
+    n1 += __popcll(m1);
+    n2 += __popcll(m2);
+    wave_sync_lds();
+    if (n0 >= 64) {
+      n0 -= 64;
+      bwd_chunk(sv0[n0 + lane], true, 0, qe_a, tc, recs, c2, qx, qg, rw, grad_rows, lane);
     }
-    __syncthreads();
-    const int n0 = sv_count[0], n1 = sv_count[1], n2 = sv_count[2];
-    // every wave must read the counts before any wave appends again
-    __syncthreads();
-    const bool last = base + kBwdThreads >= ce;
-    const int total = n0 + n1 + n2;
-    if (total > kListCap - kBwdThreads || (last && total)) {
-      // chunks of 64 over the survivors taken in the order first-tile-only,
-      // both, second-tile-only: all but at most two chunks are pure, and a
-      // chunk loops only over the points of the tiles its survivors touch
-      for (int chunk = 64 * wave; chunk < total; chunk += 64 * kBwdWaves) {
-        const int v = chunk + lane;
-        const bool valid = v < total;
-        int id = 0, cat = 0;
-        if (v < n0) {
-          id = sv[0][v];
-          cat = 1;
-        } else if (v < n0 + n2) {
-          id = sv[2][v - n0];
-          cat = 3;
-        } else if (valid) {
-          id = sv[1][v - n0 - n2];
-          cat = 2;
-        }
-        const bool use_a = __ballot(cat & 1) != 0, use_b = __ballot(cat & 2) != 0;
-        const int qb = use_a ? 0 : kTile, qe = use_b ? qe_all : qe_a;
-        const PrimRec r = recs[id];
-        const float mx = r.r0.x - tc.cx, my = r.r0.y - tc.cy, mz = r.r0.z - tc.cz;
-        const float b0 = r.r1.x * mx + r.r1.y * my + r.r1.z * mz;
-        const float b1 = r.r2.x * mx + r.r2.y * my + r.r2.z * mz;
-        const float b2 = r.r3.x * mx + r.r3.y * my + r.r3.z * mz;
-        float GP[3] = {0.f, 0.f, 0.f}, A[3] = {0.f, 0.f, 0.f};
-        float U[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-        bool any = false;
-        for (int k = qb; k < qe; k += 4) {
-          float4 xq[4], gq[4];
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            xq[i] = qx_s[k + i];
-            gq[i] = qg_s[k + i];
-          }
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const float u0 = fmaf(r.r1.z, xq[i].z, fmaf(r.r1.y, xq[i].y, fmaf(r.r1.x, xq[i].x, -b0)));
-            const float u1 = fmaf(r.r2.z, xq[i].z, fmaf(r.r2.y, xq[i].y, fmaf(r.r2.x, xq[i].x, -b1)));
-            const float u2 = fmaf(r.r3.z, xq[i].z, fmaf(r.r3.y, xq[i].y, fmaf(r.r3.x, xq[i].x, -b2)));
-            const float m2 = u0 * u0 + u1 * u1 + u2 * u2;
-            const bool in = m2 <= c2;
-            const float w = in ? __builtin_amdgcn_exp2f(-m2) : 0.f;
-            any |= in;
-            const float a = gq[i].x * r.r0.w + gq[i].y * r.r1.w + gq[i].z * r.r2.w;
-            const float c = a * w;
-            GP[0] += w * gq[i].x;
-            GP[1] += w * gq[i].y;
-            GP[2] += w * gq[i].z;
-            const float cu0 = c * u0, cu1 = c * u1, cu2 = c * u2;
-            A[0] += cu0;
-            A[1] += cu1;
-            A[2] += cu2;
-            U[0] += cu0 * u0;
-            U[1] += cu0 * u1;
-            U[2] += cu0 * u2;
-            U[3] += cu1 * u1;
-            U[4] += cu1 * u2;
-            U[5] += cu2 * u2;
-          }
-        }
-        float out[13];
-        grad_epilogue(r, quat, ls, id, GP, A, U, out);
-        const bool write = valid && any;
-        float* rw = rows_s[wave];
-#pragma unroll
-        for (int e = 0; e < 13; ++e) rw[lane * kRowStride + e] = write ? out[e] : 0.f;
-        rw[lane * kRowStride + 13] = __int_as_float(write ? id : -1);
-        wave_sync_lds();
-        // row-coalesced atomics: instruction r covers rows 4r..4r+3, 16 lanes each
-        const int sub = lane >> 4, e = lane & 15;
-#pragma unroll 4
-        for (int rr = 0; rr < 16; ++rr) {
-          const int row = rr * 4 + sub;
-          const int rid = __float_as_int(rw[row * kRowStride + 13]);
-          if (e < 13 && rid >= 0) {
-            unsafeAtomicAdd(grad_rows + (int64_t)rid * 16 + e, rw[row * kRowStride + e]);
-          }
-        }
-        wave_sync_lds();
-      }
-      __syncthreads();
-      if (tid < 3) sv_count[tid] = 0;
-      __syncthreads();
+    if (n1 >= 64) {
+      n1 -= 64;
+      bwd_chunk(sv1[n1 + lane], true, kTile, qe_all, tc, recs, c2, qx, qg, rw, grad_rows, lane);
     }
+    if (n2 >= 64) {
+      n2 -= 64;
+      bwd_chunk(sv2[n2 + lane], true, 0, qe_all, tc, recs, c2, qx, qg, rw, grad_rows, lane);
+    }
+  }
+  const int total = n0 + n1 + n2;
+  for (int chunk = 0; chunk < total; chunk += 64) {
+    const int v = chunk + lane;
+    int id = 0, cat = 0;
+    if (v < n0) {
+      id = sv0[v];
+      cat = 1;
+    } else if (v < n0 + n2) {
+      id = sv2[v - n0];
+      cat = 3;
+    } else if (v < total) {
+      id = sv1[v - n0 - n2];
+      cat = 2;
+    }
+    const bool use_a = __ballot(cat & 1) != 0, use_b = __ballot(cat & 2) != 0;
+    bwd_chunk(id, cat != 0, use_a ? 0 : kTile, use_b ? qe_all : qe_a, tc, recs, c2, qx, qg,
+              rw, grad_rows, lane);
   }
 }
 
-// grads += rows; rows = 0 (leaves the scratch clean for the next call).
+// Per primitive: the sums (GP, A', U') gathered over every group become the
+// 13 parameter gradients, which are added to the caller's arrays; the rows
+// are cleared for the next call.
 __global__ void __launch_bounds__(256) grad_finalize_kernel(float4* __restrict__ rows, int n,
+                                                            const PrimRec* __restrict__ recs,
+                                                            const float* __restrict__ quat,
+                                                            const float* __restrict__ ls,
                                                             float* __restrict__ gmu,
                                                             float* __restrict__ gq,
                                                             float* __restrict__ gls,
                                                             float* __restrict__ grgb) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  float4 a = rows[i * 4], b = rows[i * 4 + 1], c = rows[i * 4 + 2], d = rows[i * 4 + 3];
+  const float4 a = rows[i * 4], b = rows[i * 4 + 1], c = rows[i * 4 + 2];
   const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
   rows[i * 4] = z;
   rows[i * 4 + 1] = z;
   rows[i * 4 + 2] = z;
-  rows[i * 4 + 3] = z;
-  gmu[i * 3] += a.x;
-  gmu[i * 3 + 1] += a.y;
-  gmu[i * 3 + 2] += a.z;
-  gq[i * 4] += a.w;
-  gq[i * 4 + 1] += b.x;
-  gq[i * 4 + 2] += b.y;
-  gq[i * 4 + 3] += b.z;
-  gls[i * 3] += b.w;
-  gls[i * 3 + 1] += c.x;
-  gls[i * 3 + 2] += c.y;
-  grgb[i * 3] += c.z;
-  grgb[i * 3 + 1] += c.w;
-  grgb[i * 3 + 2] += d.x;
+  const float GP[3] = {a.x, a.y, a.z}, A[3] = {a.w, b.x, b.y};
+  const float U[6] = {b.z, b.w, c.x, c.y, c.z, c.w};
+  float out[13];
+  grad_epilogue(recs[i], quat, ls, i, GP, A, U, out);
+  gmu[i * 3] += out[0];
+  gmu[i * 3 + 1] += out[1];
+  gmu[i * 3 + 2] += out[2];
+  gq[i * 4] += out[3];
+  gq[i * 4 + 1] += out[4];
+  gq[i * 4 + 2] += out[5];
+  gq[i * 4 + 3] += out[6];
+  gls[i * 3] += out[7];
+  gls[i * 3 + 1] += out[8];
+  gls[i * 3 + 2] += out[9];
+  grgb[i * 3] += out[10];
+  grgb[i * 3 + 1] += out[11];
+  grgb[i * 3 + 2] += out[12];
 }
 
 }  // namespace
@@ -513,12 +529,13 @@ gpf_status launch_eval_bwd(const gpf_grid* gc, const float* dL, gpf_field_grad* 
     g->grad_cap = g->n;
     g->bytes += (size_t)g->n * sizeof(float4) * 4;
   }
-  hipLaunchKernelGGL(eval_bwd_kernel, dim3(xcd_grid(qs->ngroups)), dim3(kBwdThreads), 0, s, qs->xs,
+  hipLaunchKernelGGL(eval_bwd_kernel, dim3(xcd_grid((qs->ngroups + kBwdWaves - 1) / kBwdWaves)),
+                     dim3(kBwdThreads), 0, s, qs->xs,
                      qs->perm, qs->groups, qs->group_lo, qs->group_hi, (int)qs->ngroups,
-                     qs->tile_lo, qs->tile_hi, g->cell_start, g->cell_prims, g->rec, g->quat, g->log_scale, c2, dL,
+                     qs->tile_lo, qs->tile_hi, g->cell_start, g->cell_prims, g->rec, c2, dL,
                      (float*)g->grad_rows);
   hipLaunchKernelGGL(grad_finalize_kernel, dim3((unsigned)((g->n + 255) / 256)), dim3(256), 0, s,
-                     g->grad_rows, (int)g->n, grad->mu, grad->quat, grad->log_scale, grad->rgb);
+                     g->grad_rows, (int)g->n, g->rec, g->quat, g->log_scale, grad->mu, grad->quat, grad->log_scale, grad->rgb);
   GPF_HIP(hipGetLastError());
   return GPF_OK;
 }
