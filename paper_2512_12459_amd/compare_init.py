@@ -27,6 +27,9 @@ from . import scenes as S
 from .fit import Field, Fitter
 
 
+THRESHOLDS = (20.0, 25.0, 30.0, 33.0)
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -49,11 +52,19 @@ def compare(net, workload="caustic1m", gt_seed=7, views=32, res=800, target_psnr
         t_init = time.perf_counter() - t0
         fitter = Fitter(f, qs, T, lr=lr)
         p0 = fitter.current_psnr()
+        pairs0 = fitter.grid.build(*f.arrays()).count_pairs()
         res_ = fitter.run(max_steps, target_psnr, check_every, log=lambda s: log(f"[{name}] {s}"))
+        hist = res_["history"]
+        # first check at or above each level (checks every `check_every` steps)
+        levels = {}
+        for lv in sorted(set(THRESHOLDS + (target_psnr,))):
+            hit = next((h for h in hist if h[1] >= lv), None)
+            levels[f"{lv:g}"] = None if hit is None else dict(steps=hit[0], seconds=t_init + hit[2])
         out[name] = dict(init_psnr=p0, steps_to_target=res_["reached"],
                          seconds_to_target=(t_init + res_["seconds"]) if res_["reached"] else None,
-                         init_seconds=t_init, final_psnr=res_["history"][-1][1],
-                         steps_run=res_["history"][-1][0], history=res_["history"])
+                         init_seconds=t_init, final_psnr=hist[-1][1], steps_run=hist[-1][0],
+                         ms_per_step=res_["seconds"] / hist[-1][0] * 1e3,
+                         init_pairs_per_query=pairs0 / x.shape[0], levels=levels, history=hist)
         log(f"{name}: init {p0:.2f} dB, reached {res_['reached']}, final {out[name]['final_psnr']:.2f} dB")
     return dict(workload=workload, n=gt.n, q=int(x.shape[0]), target_psnr=target_psnr, runs=out)
 

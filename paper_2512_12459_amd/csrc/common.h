@@ -111,6 +111,7 @@ gpf_status launch_eval_fwd(const gpf_grid* g, float* L, hipStream_t s);
 gpf_status launch_eval_bwd(const gpf_grid* g, const float* dL, gpf_field_grad* grad,
                            hipStream_t s);
 gpf_status launch_count_pairs(const gpf_grid* g, unsigned long long* d_count, hipStream_t s);
+gpf_status launch_valu_probe(float* out, int blocks, int iters, hipStream_t s);
 gpf_status launch_mse(const float* L, const float* T, int64_t q, double* loss, float* dL,
                       hipStream_t s);
 gpf_status launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr,

@@ -134,7 +134,8 @@ __global__ void __launch_bounds__(kWaves * 64) eval_fwd_kernel(
     ns += __popcll(bal);
     if (ns > kFwdSurvCap - 64 || base + 64 >= ce) {
       wave_sync_lds();
-      for (int s = 0; s < ns; ++s) {
+      const int nsu = __builtin_amdgcn_readfirstlane(ns);  // wave-uniform trip count
+      for (int s = 0; s < nsu; ++s) {
         const int4 e = sv[s];
         const int head = __builtin_amdgcn_readfirstlane(e.x);
         const PrimRec r = recs[head & 0x3fffffff];
@@ -413,14 +414,26 @@ __global__ void __launch_bounds__(kBwdThreads) eval_bwd_kernel(
   const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const int cs = cell_start[gi.cell], ce = cell_start[gi.cell + 1];
   int n0 = 0, n1 = 0, n2 = 0;  // stack heights, each below 64 between batches
+  // Software pipeline over the candidates in batches of 64: the records of
+  // batch b + 1 and the indices of batch b + 2 are requested before batch b is
+  // tested, so their latency overlaps the tests and the draining of full
+  // stacks.  Indices past the end repeat the cell's last entry, keeping every
+  // load unconditional and in bounds.
+  int pid_c = 0, pid_n = 0;
+  PrimRec rec_c{};
+  if (cs < ce) {
+    pid_c = cell_prims[min(cs + lane, ce - 1)];
+    rec_c = recs[pid_c];
+    pid_n = cell_prims[min(cs + 64 + lane, ce - 1)];
+  }
   for (int base = cs; base < ce; base += 64) {
-    const int j = base + lane;
-    int mask = 0, pid = 0;
-    if (j < ce) {
-      pid = cell_prims[j];
-      const PrimRec r = recs[pid];
-      mask = (tile_may_touch(r, ta, c2) ? 1 : 0) | ((has_b && tile_may_touch(r, tb, c2)) ? 2 : 0);
-    }
+    const PrimRec rec_n = recs[pid_n];
+    const int pid_nn = cell_prims[min(base + 128 + lane, ce - 1)];
+    const int pid = pid_c;
+    int mask = 0;
+    if (base + lane < ce)
+      mask = (tile_may_touch(rec_c, ta, c2) ? 1 : 0) |
+             ((has_b && tile_may_touch(rec_c, tb, c2)) ? 2 : 0);
     const uint64_t m0 = __ballot(mask == 1), m1 = __ballot(mask == 2), m2 = __ballot(mask == 3);
     if (mask == 1) sv0[n0 + __popcll(m0 & below)] = pid;
     if (mask == 2) sv1[n1 + __popcll(m1 & below)] = pid;
@@ -441,6 +454,9 @@ __global__ void __launch_bounds__(kBwdThreads) eval_bwd_kernel(
       n2 -= 64;
       bwd_chunk(sv2[n2 + lane], true, 0, qe_all, tc, recs, c2, qx, qg, rw, grad_rows, lane);
     }
+    pid_c = pid_n;
+    rec_c = rec_n;
+    pid_n = pid_nn;
   }
   const int total = n0 + n1 + n2;
   for (int chunk = 0; chunk < total; chunk += 64) {
