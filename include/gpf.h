@@ -123,6 +123,45 @@ gpf_status gpf_eval_radiance_backward(const gpf_grid *grid, const gpf_field *f, 
                                       int64_t q, const float *dL, gpf_field_grad *grad,
                                       void *stream);
 
+/* ---- hybrid query: the paper's own neighbourhood (supplementary Alg. S3;
+ * Sec. 4.2 neighbourhood search and aggregation) ----------------------------
+ * Neighbourhood N(x) of a query point: the Gaussians whose centre lies within
+ * Euclidean distance r of x (ball query); when the ball holds fewer than
+ * k_min centres, the k_min centres nearest to x (which contain the ball).
+ * Membership and nearest order are decided on single-precision squared
+ * distances (dx*dx + dy*dy) + dz*dz, dx = x - mu, without fused multiply-add,
+ * against r*r rounded to FP32; ties go to the lower index.  Weight
+ * w = exp(-m^2/2) psi(|x - mu|) with no 3-sigma cut, psi = 1 within r and
+ * exp(-3 t^2), t = (|x - mu| - r) / max(r, 1e-6), beyond.
+ * L(x) = sum_N w Phi / max(sum_N w, eps).
+ *
+ * gpf_build_grid_hybrid: as gpf_build_grid, but every Gaussian is listed in
+ * each occupied query cell its ball of radius r may reach, and a uniform grid
+ * over the centres is built for the nearest-centre top-up.  r > 0 (finite),
+ * 1 <= k_min <= 8.  Synchronises `stream` (two small readbacks).  A handle
+ * keeps its query mode: rebuilding a truncated handle as hybrid (or the
+ * reverse) is GPF_ERR_INVALID_ARGUMENT. */
+gpf_status gpf_build_grid_hybrid(const gpf_field *f, float r, int k_min, const gpf_queries *qs,
+                                 void *stream, gpf_grid **grid);
+
+/* Forward: L[q][3] (overwritten, normalised), Z[q] = sum of the weights
+ * before clamping, count[q] = number of centres in the ball of each point
+ * (the top-up applies where count < k_min).  eps > 0.  Device pointers. */
+gpf_status gpf_eval_hybrid(const gpf_grid *grid, const gpf_field *f, const float *x, int64_t q,
+                           float eps, float *L, float *Z, int *count, void *stream);
+
+/* Backward: adds to `grad` the gradient of sum_x dL(x) . L(x) with respect to
+ * every Gaussian parameter, given this forward's L, Z and count for the same
+ * grid, field and eps (per-point values, not per pair; weights are
+ * recomputed).  With Zc = max(Z, eps): dPhi += w dL / Zc and, through w,
+ * a = (dL . Phi - [Z >= eps] dL . L) / Zc per pair; changes of the
+ * neighbourhoods contribute nothing.  Accumulation order is not
+ * deterministic (floating-point atomics). */
+gpf_status gpf_eval_hybrid_backward(const gpf_grid *grid, const gpf_field *f, const float *x,
+                                    int64_t q, float eps, const float *L, const float *Z,
+                                    const int *count, const float *dL, gpf_field_grad *grad,
+                                    void *stream);
+
 /* ---- exact pair count (roofline numerator) --------------------------------
  * Writes to *pairs (host) the number of (query, primitive) pairs with
  * m^2 <= cutoff^2.  Synchronises `stream`. */

@@ -81,6 +81,14 @@ def rotation_matrix_grad(qhat):
     return D
 
 
+def quat_error_scale(a_hat, qhat, qnorm):
+    """Error scale of dq = (I - qhat qhat^T) dqhat / |q| per component, given
+    a per-component scale a_hat of dqhat: the projection mixes components, so
+    component c carries a_hat_c + |qhat_c| sum_c' |qhat_c'| a_hat_c'."""
+    mix = np.sum(np.abs(qhat) * a_hat, axis=-1, keepdims=True)
+    return (a_hat + np.abs(qhat) * mix) / qnorm[..., None]
+
+
 def primitive_frames(quat, log_scale):
     """Returns dict(qhat, qnorm, R, s, W) with W = diag(1/s) R^T, so u = W d."""
     qhat, qnorm = quat_normalise(quat)
@@ -292,8 +300,8 @@ def radiance_backward(mu, quat, log_scale, rgb, x, g, cutoff=3.0):
     gqhat = np.einsum("njk,njkc->nc", gR, D)
     proj = gqhat - np.sum(gqhat * qhat, axis=1, keepdims=True) * qhat
     gq_ = proj / qn[:, None]
-    aq = np.einsum("njk,njkc->nc", aR, np.abs(D)) / qn[:, None]
-    cq = np.einsum("njk,njkc->nc", cR, np.abs(D)) / qn[:, None]
+    aq = quat_error_scale(np.einsum("njk,njkc->nc", aR, np.abs(D)), qhat, qn)
+    cq = quat_error_scale(np.einsum("njk,njkc->nc", cR, np.abs(D)), qhat, qn)
     return dict(mu=gm, quat=gq_, log_scale=gs, rgb=gp,
                 mu_abs=am, quat_abs=aq, log_scale_abs=as_, rgb_abs=ap,
                 mu_cond=cm, quat_cond=cq, log_scale_cond=cs, rgb_cond=cp)

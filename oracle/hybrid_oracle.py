@@ -41,10 +41,12 @@ from __future__ import annotations
 
 import numpy as np
 
-from oracle.gpf_oracle import primitive_frames, rotation_matrix_grad
+from oracle.gpf_oracle import primitive_frames, quat_error_scale, rotation_matrix_grad
 
 F64 = np.float64
 F32 = np.float32
+TINY_W = 2.0 ** -120      # weights below this sit at the edge of FP32's normal range
+TINY_TERM = 2.0 ** -100   # per-pair gradient terms below this may pass through sub-normal products
 
 
 # ----------------------------------------------------------------------------
@@ -153,11 +155,11 @@ def _pairs(mu, x, sets):
 
 def radiance(mu, quat, log_scale, rgb, x, r=0.02, k_min=3, eps=1e-6, sets=None, counts=None):
     """Returns dict(L [q,3], Z [q], count [q] = ball count k_r, size [q] =
-    |N(x)|, L_abs, L_cond) in float64.  L_abs = (sum w |Phi| + |L| Z) / Zc is
+    |N(x)|, L_abs, L_cond, Z_cond) in float64.  L_abs = (sum w |Phi| + |L| Z) / Zc is
     the error scale of the two sums; L_cond = sum w |Phi - L| sens / Zc is the
     first-order effect of rounding in each weight's exponent, with sens =
     sum_k |u_k| eta_k (eta_k = sum_j |W_kj d_j|) + [dist > r] 6 t dist /
-    max(r, 1e-6)."""
+    max(r, 1e-6); Z_cond = sum w sens likewise for Z."""
     mu64 = np.asarray(mu, F64)
     x64 = np.asarray(x, F64)
     rgb = np.asarray(rgb, F64)
@@ -185,16 +187,28 @@ def radiance(mu, quat, log_scale, rgb, x, r=0.02, k_min=3, eps=1e-6, sets=None, 
     L = S / Zc[:, None]
     Lc = np.zeros((q, 3))
     np.add.at(Lc, qi, (w * sens)[:, None] * np.abs(rgb[pi] - L[qi]))
+    Zcond = np.zeros(q)
+    np.add.at(Zcond, qi, w * sens)
+    # weights below the single-precision normal range may flush to zero in a
+    # working-precision evaluation: their whole contribution is error scale
+    tiny = w < TINY_W
+    Lt = np.zeros((q, 3))
+    Zt = np.zeros(q)
+    np.add.at(Lt, qi[tiny], w[tiny, None] * np.abs(rgb[pi[tiny]]))
+    np.add.at(Zt, qi[tiny], w[tiny])
     return dict(L=L, Z=Z, count=np.asarray(counts), size=np.array([s.size for s in sets]),
                 L_abs=(A + np.abs(L) * Z[:, None]) / Zc[:, None], L_cond=Lc / Zc[:, None],
+                Z_cond=Zcond, L_tiny=(Lt + np.abs(L) * Zt[:, None]) / Zc[:, None], Z_tiny=Zt,
                 sets=sets)
 
 
 def radiance_backward(mu, quat, log_scale, rgb, x, g, r=0.02, k_min=3, eps=1e-6, sets=None):
     """Gradient of sum_q g_q . L(x_q) with respect to every Gaussian parameter
     (see the module docstring), plus ``_abs`` (sum of |per-pair term|) and
-    ``_cond`` (first-order effect of rounding in the weights' exponents and in
-    the per-query normaliser) error scales, as in the truncated oracle."""
+    ``_cond`` error scales as in the truncated oracle: first-order effects of
+    rounding in the weights' exponents, in the per-query normaliser, and in
+    the cancelling difference a = gp . Phi - gl (per unit roundoff); and
+    ``_tiny``, the terms of pairs whose weight is below FP32's normal range."""
     mu64 = np.asarray(mu, F64)
     x64 = np.asarray(x, F64)
     rgb = np.asarray(rgb, F64)
@@ -237,6 +251,11 @@ def radiance_backward(mu, quat, log_scale, rgb, x, g, r=0.02, k_min=3, eps=1e-6,
     zrel = ind * zrel / Zc
     da = np.sum(np.abs(g) * fwd["L_cond"], axis=1) * ind / Zc      # |delta a| from delta L
     rel = sens + zrel[qi]
+    # a = gp . Phi - gl cancels when L is close to Phi (one Gaussian carries
+    # the point's weight): any working-precision evaluation, whichever way it
+    # groups the difference, carries an absolute error of order one unit
+    # roundoff times |gp| (|Phi| + |L|) in a (L itself is held rounded)
+    aerr = np.sum(np.abs(gp[qi]) * (np.abs(rgb[pi]) + ind[qi, None] * np.abs(L[qi])), axis=1)
     out = {}
     gm = np.zeros((n, 3)); gs = np.zeros((n, 3)); gph = np.zeros((n, 3)); gR = np.zeros((n, 3, 3))
     am = np.zeros((n, 3)); as_ = np.zeros((n, 3)); ap = np.zeros((n, 3)); aR = np.zeros((n, 3, 3))
@@ -249,19 +268,35 @@ def radiance_backward(mu, quat, log_scale, rgb, x, g, r=0.02, k_min=3, eps=1e-6,
     np.add.at(am, pi, np.abs(t_m))
     np.add.at(as_, pi, np.abs(t_s))
     np.add.at(aR, pi, np.abs(t_R))
-    fa = np.where(np.abs(c) > 0, da[qi] * w / np.maximum(np.abs(c), 1e-300), 0.0)  # relative change of c
+    # absolute error of c from the error of a (delta L and the cancellation)
+    cerr = (da[qi] + aerr) * w
+    f_m = np.abs(np.einsum("pkj,pk->pj", W[pi], u) + dpsi[:, None] * d)
+    f_R = np.abs(d)[:, :, None] * (np.abs(u) / s[pi])[:, None, :]
     np.add.at(cp, pi, np.abs(t_p) * rel[:, None])
-    np.add.at(cm, pi, np.abs(t_m) * (rel + fa)[:, None]
+    np.add.at(cm, pi, np.abs(t_m) * rel[:, None] + cerr[:, None] * f_m
               + np.abs(c)[:, None] * np.abs(np.einsum("pkj,pk->pj", np.abs(W[pi]), eta)))
-    np.add.at(cs, pi, np.abs(t_s) * (rel + fa)[:, None] + 2 * np.abs(c)[:, None] * np.abs(u) * eta)
-    np.add.at(cR, pi, np.abs(t_R) * (rel + fa)[:, None, None]
+    np.add.at(cs, pi, np.abs(t_s) * rel[:, None] + cerr[:, None] * u * u
+              + 2 * np.abs(c)[:, None] * np.abs(u) * eta)
+    np.add.at(cR, pi, np.abs(t_R) * rel[:, None, None] + cerr[:, None, None] * f_R
               + (np.abs(c)[:, None, None] * np.abs(d)[:, :, None] * (eta / s[pi])[:, None, :]))
+    # pairs whose weight, or whose terms, sit near the bottom of FP32's normal
+    # range: intermediate products of a single-precision evaluation may flush
+    big = np.maximum.reduce([np.max(np.abs(t_p), axis=1), np.max(np.abs(t_m), axis=1),
+                             np.max(np.abs(t_s), axis=1), np.max(np.abs(t_R), axis=(1, 2))])
+    tiny = (w < TINY_W) | (big < TINY_TERM)
+    tm = np.zeros((n, 3)); ts = np.zeros((n, 3)); tp = np.zeros((n, 3)); tR = np.zeros((n, 3, 3))
+    np.add.at(tp, pi[tiny], np.abs(t_p[tiny]))
+    np.add.at(tm, pi[tiny], np.abs(t_m[tiny]))
+    np.add.at(ts, pi[tiny], np.abs(t_s[tiny]))
+    np.add.at(tR, pi[tiny], np.abs(t_R[tiny]))
     D = rotation_matrix_grad(qhat)
     gqhat = np.einsum("njk,njkc->nc", gR, D)
     proj = gqhat - np.sum(gqhat * qhat, axis=1, keepdims=True) * qhat
     out["quat"] = proj / qn[:, None]
-    out["quat_abs"] = np.einsum("njk,njkc->nc", aR, np.abs(D)) / qn[:, None]
-    out["quat_cond"] = np.einsum("njk,njkc->nc", cR, np.abs(D)) / qn[:, None]
+    out["quat_tiny"] = quat_error_scale(np.einsum("njk,njkc->nc", tR, np.abs(D)), qhat, qn)
+    out.update(mu_tiny=tm, log_scale_tiny=ts, rgb_tiny=tp)
+    out["quat_abs"] = quat_error_scale(np.einsum("njk,njkc->nc", aR, np.abs(D)), qhat, qn)
+    out["quat_cond"] = quat_error_scale(np.einsum("njk,njkc->nc", cR, np.abs(D)), qhat, qn)
     out.update(mu=gm, log_scale=gs, rgb=gph, mu_abs=am, log_scale_abs=as_, rgb_abs=ap,
                mu_cond=cm, log_scale_cond=cs, rgb_cond=cp)
     return out

@@ -20,6 +20,7 @@ FWD_RTOL = 1e-5
 GRAD_RTOL = 1e-4
 EPS32 = 2.0 ** -24
 COND_C = 4.0
+TINY32 = 2.0 ** -126       # smallest normal FP32: values below it may flush to zero
 
 
 def check_forward(L_gpu, ref, rtol=FWD_RTOL):
@@ -50,7 +51,7 @@ def check_grads(gpu, ref, rows=None, rtol=GRAD_RTOL):
         if rows is not None:
             g, r, a, c = g[rows], r[rows], a[rows], c[rows]
         err = np.abs(g - r)
-        tol = rtol * a + COND_C * EPS32 * c + 1e-30
+        tol = rtol * a + COND_C * EPS32 * c + TINY32 + ref.get(name + "_tiny", 0.0)
         bad = np.argwhere(err > tol)
         if bad.size:
             b = tuple(bad[0])
@@ -60,3 +61,28 @@ def check_grads(gpu, ref, rows=None, rtol=GRAD_RTOL):
         ne = np.linalg.norm(g - r)
         if ne > rtol * nr:
             raise AssertionError(f"{name}: group error {ne / nr:.3g} above {rtol}")
+
+
+def check_hybrid_forward(L_gpu, Z_gpu, count_gpu, ref, rtol=FWD_RTOL):
+    """Hybrid query (supplementary Alg. S3): ball counts equal (both sides take
+    the membership decision on the same FP32 squared distances); L and Z within
+    rtol of their sums' error scale plus C eps32 times their conditioning,
+    plus the contribution of weights below FP32's normal range (``_tiny``)."""
+    count_gpu = np.asarray(count_gpu)
+    bad = np.flatnonzero(count_gpu != ref["count"])
+    if bad.size:
+        i = bad[0]
+        raise AssertionError(f"{bad.size} ball counts differ; first q={i} gpu={count_gpu[i]} ref={ref['count'][i]}")
+    Z_gpu = np.asarray(Z_gpu, np.float64)
+    zt = rtol * ref["Z"] + COND_C * EPS32 * ref["Z_cond"] + TINY32 + ref["Z_tiny"]
+    bad = np.flatnonzero(np.abs(Z_gpu - ref["Z"]) > zt)
+    if bad.size:
+        i = bad[0]
+        raise AssertionError(f"{bad.size} weight sums off; first q={i} gpu={Z_gpu[i]!r} ref={ref['Z'][i]!r}")
+    L_gpu = np.asarray(L_gpu, np.float64)
+    lt = rtol * ref["L_abs"] + COND_C * EPS32 * ref["L_cond"] + TINY32 + ref["L_tiny"]
+    bad = np.argwhere(np.abs(L_gpu - ref["L"]) > lt)
+    if bad.size:
+        i, c = bad[0]
+        raise AssertionError(f"{len(bad)} radiance values off; first q={i} c={c} gpu={L_gpu[i, c]!r} "
+                             f"ref={ref['L'][i, c]!r} abs={ref['L_abs'][i, c]!r} count={ref['count'][i]}")

@@ -53,6 +53,11 @@ _SIG = {
     "gpf_eval_radiance_backward": (ctypes.c_int, [_P, ctypes.POINTER(Field), _P, _I64, _P,
                                                   ctypes.POINTER(FieldGrad), _P]),
     "gpf_count_pairs": (ctypes.c_int, [_P, ctypes.POINTER(Field), ctypes.POINTER(_I64), _P]),
+    "gpf_build_grid_hybrid": (ctypes.c_int, [ctypes.POINTER(Field), _F, ctypes.c_int, _P, _P,
+                                             ctypes.POINTER(_P)]),
+    "gpf_eval_hybrid": (ctypes.c_int, [_P, ctypes.POINTER(Field), _P, _I64, _F, _P, _P, _P, _P]),
+    "gpf_eval_hybrid_backward": (ctypes.c_int, [_P, ctypes.POINTER(Field), _P, _I64, _F, _P, _P, _P,
+                                                _P, ctypes.POINTER(FieldGrad), _P]),
     "gpf_valu_probe": (ctypes.c_int, [_P, _I64, ctypes.c_int, ctypes.c_int, _P]),
     "gpf_mse_loss": (ctypes.c_int, [_P, _P, _I64, _P, _P, _P]),
     "gpf_adam_step": (ctypes.c_int, [_P, _P, _P, _P, _I64, _F, _F, _F, _F, _I64, _P]),

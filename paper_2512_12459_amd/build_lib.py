@@ -18,7 +18,7 @@ LIB = os.path.join(HERE, "libgpf.so")
 ARCH = "gfx950"
 
 SOURCES = ["capi.cpp", "capi_init.cpp", "bin_queries.hip", "grid.hip", "eval.hip", "optim.hip",
-           "mlp.hip", "init.hip", "probe.hip"]
+           "mlp.hip", "init.hip", "probe.hip", "hybrid.hip"]
 
 COMMON = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", f"-I{INCLUDE}", f"-I{CSRC}",
@@ -56,7 +56,8 @@ def build(jobs: int | None = None, verbose: bool = False, defines=(), out: str |
     with cf.ThreadPoolExecutor(jobs) as ex:
         objs = list(ex.map(lambda s_: _compile(s_, build_dir, defines), SOURCES))
     tmp = out + ".tmp"
-    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-Wl,--no-undefined", "-o", tmp,
+           *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

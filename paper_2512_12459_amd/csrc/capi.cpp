@@ -1,5 +1,6 @@
 // C ABI entry points: argument validation, handle lifetime, error reporting.
 // Every compute step runs in the HIP kernels of the sibling .hip files.
+#include <cmath>
 #include <cstdlib>
 #include <cstring>
 #include <mutex>
@@ -70,8 +71,12 @@ static bool field_ok(const gpf_field* f, std::string* why) {
   return true;
 }
 
-static gpf_status check_grid_use(const gpf_grid* g, const gpf_field* f, const float* x, int64_t q) {
+static gpf_status check_grid_use(const gpf_grid* g, const gpf_field* f, const float* x, int64_t q,
+                                 bool hybrid = false) {
   if (!g) return set_error(GPF_ERR_INVALID_ARGUMENT, "grid is NULL");
+  if ((g->ball > 0.f) != hybrid)
+    return set_error(GPF_ERR_INVALID_ARGUMENT, hybrid ? "grid was built for the truncated query"
+                                                      : "grid was built for the hybrid query");
   std::string why;
   if (!field_ok(f, &why)) return set_error(GPF_ERR_INVALID_ARGUMENT, why);
   if (!x) return set_error(GPF_ERR_INVALID_ARGUMENT, "x is NULL");
@@ -151,6 +156,8 @@ gpf_status gpf_build_grid(const gpf_field* f, float cutoff, const gpf_queries* q
   bool fresh = (g == nullptr);
   if (!fresh && g->qs != qs)
     return set_error(GPF_ERR_STALE, "grid was built for a different query set");
+  if (!fresh && g->ball > 0.f)
+    return set_error(GPF_ERR_INVALID_ARGUMENT, "grid was built for the hybrid query");
   if (fresh) g = new gpf_grid();
   g->qs = qs;
   g->mu = f->mu;
@@ -182,6 +189,7 @@ void gpf_grid_destroy(gpf_grid* g) {
   dev_free(g->cell_prims, g->cap * sizeof(int));
   dev_free(g->sort_tmp, g->sort_tmp_bytes);
   dev_free(g->grad_rows, g->grad_cap * sizeof(float4) * 4);
+  free_centre_grid(g);
   delete g;
 }
 
@@ -214,6 +222,67 @@ gpf_status gpf_eval_radiance_backward(const gpf_grid* g, const gpf_field* f, con
     for (auto b : gp)
       if (a == b) return set_error(GPF_ERR_INVALID_ARGUMENT, "gradient buffer aliases the field");
   return launch_eval_bwd(g, dL, grad, (hipStream_t)stream);
+}
+
+gpf_status gpf_build_grid_hybrid(const gpf_field* f, float r, int k_min, const gpf_queries* qs,
+                                 void* stream, gpf_grid** grid) {
+  if (!grid) return set_error(GPF_ERR_INVALID_ARGUMENT, "grid out-pointer is NULL");
+  std::string why;
+  if (!field_ok(f, &why)) return set_error(GPF_ERR_INVALID_ARGUMENT, why);
+  if (!qs) return set_error(GPF_ERR_INVALID_ARGUMENT, "query set is NULL");
+  if (!(r > 0.f) || !std::isfinite(r)) return set_error(GPF_ERR_INVALID_ARGUMENT, "r must be positive and finite");
+  if (k_min < 1 || k_min > 8) return set_error(GPF_ERR_INVALID_ARGUMENT, "k_min must lie in [1, 8]");
+  gpf_grid* g = *grid;
+  bool fresh = (g == nullptr);
+  if (!fresh && g->qs != qs)
+    return set_error(GPF_ERR_STALE, "grid was built for a different query set");
+  if (!fresh && !(g->ball > 0.f))
+    return set_error(GPF_ERR_INVALID_ARGUMENT, "grid was built for the truncated query");
+  if (fresh) g = new gpf_grid();
+  g->qs = qs;
+  g->mu = f->mu;
+  g->quat = f->quat;
+  g->log_scale = f->log_scale;
+  g->rgb = f->rgb;
+  g->n = f->n;
+  g->cutoff = 3.f;
+  g->ball = r;
+  g->k_min = k_min;
+  gpf_status st = launch_build_grid(g, (hipStream_t)stream);
+  if (st != GPF_OK) {
+    if (fresh) gpf_grid_destroy(g);
+    else g->n = -1;  // poison: the handle no longer matches any field
+    return st;
+  }
+  *grid = g;
+  return GPF_OK;
+}
+
+gpf_status gpf_eval_hybrid(const gpf_grid* g, const gpf_field* f, const float* x, int64_t q,
+                           float eps, float* L, float* Z, int* count, void* stream) {
+  gpf_status st = check_grid_use(g, f, x, q, true);
+  if (st != GPF_OK) return st;
+  if (!L || !Z || !count) return set_error(GPF_ERR_INVALID_ARGUMENT, "L, Z and count must be non-NULL");
+  if (!(eps > 0.f) || !std::isfinite(eps)) return set_error(GPF_ERR_INVALID_ARGUMENT, "eps must be positive and finite");
+  return launch_hybrid_fwd(g, eps, L, Z, count, (hipStream_t)stream);
+}
+
+gpf_status gpf_eval_hybrid_backward(const gpf_grid* g, const gpf_field* f, const float* x,
+                                    int64_t q, float eps, const float* L, const float* Z,
+                                    const int* count, const float* dL, gpf_field_grad* grad,
+                                    void* stream) {
+  gpf_status st = check_grid_use(g, f, x, q, true);
+  if (st != GPF_OK) return st;
+  if (!L || !Z || !count || !dL) return set_error(GPF_ERR_INVALID_ARGUMENT, "L, Z, count and dL must be non-NULL");
+  if (!(eps > 0.f) || !std::isfinite(eps)) return set_error(GPF_ERR_INVALID_ARGUMENT, "eps must be positive and finite");
+  if (!grad || !grad->mu || !grad->quat || !grad->log_scale || !grad->rgb)
+    return set_error(GPF_ERR_INVALID_ARGUMENT, "gradient buffers must be non-NULL");
+  const void* fp[4] = {f->mu, f->quat, f->log_scale, f->rgb};
+  const void* gp[4] = {grad->mu, grad->quat, grad->log_scale, grad->rgb};
+  for (auto a : fp)
+    for (auto b : gp)
+      if (a == b) return set_error(GPF_ERR_INVALID_ARGUMENT, "gradient buffer aliases the field");
+  return launch_hybrid_bwd(g, eps, L, Z, count, dL, grad, (hipStream_t)stream);
 }
 
 gpf_status gpf_count_pairs(const gpf_grid* g, const gpf_field* f, int64_t* pairs, void* stream) {

@@ -85,6 +85,21 @@ struct gpf_grid {
   int64_t entries = 0;
   float4* grad_rows = nullptr;  // [n][4] backward scratch: one 64-byte row per primitive
   int64_t grad_cap = 0;
+  // Hybrid query (ball > 0): ball radius r, nearest-centre top-up size, and a
+  // uniform grid over the centres for the top-up search.
+  float ball = 0.f;
+  int k_min = 0;
+  float cg_origin[3] = {0.f, 0.f, 0.f};
+  float cg_h = 0.f;
+  int cg_dims[3] = {0, 0, 0};
+  int64_t cg_cells_cap = 0, cg_n_cap = 0;
+  int* cg_start = nullptr;      // [cells + 1]
+  int* cg_fill = nullptr;       // [cells + 1] counts / fill cursors
+  int* cg_sorted = nullptr;     // [n] centre indices by cell
+  float* cg_box = nullptr;      // [64 * 6] partial boxes
+  void* cg_tmp = nullptr;
+  size_t cg_tmp_bytes = 0;
+  size_t cg_bytes = 0;
   size_t bytes = 0;
 };
 
@@ -111,6 +126,15 @@ gpf_status launch_eval_fwd(const gpf_grid* g, float* L, hipStream_t s);
 gpf_status launch_eval_bwd(const gpf_grid* g, const float* dL, gpf_field_grad* grad,
                            hipStream_t s);
 gpf_status launch_count_pairs(const gpf_grid* g, unsigned long long* d_count, hipStream_t s);
+gpf_status ensure_grad_rows(gpf_grid* g, hipStream_t s);
+gpf_status launch_grad_finalize(gpf_grid* g, gpf_field_grad* grad, hipStream_t s);
+gpf_status build_centre_grid(gpf_grid* g, hipStream_t s);
+void free_centre_grid(gpf_grid* g);
+gpf_status launch_hybrid_fwd(const gpf_grid* g, float eps, float* L, float* Z, int* count,
+                             hipStream_t s);
+gpf_status launch_hybrid_bwd(const gpf_grid* g, float eps, const float* L, const float* Z,
+                             const int* count, const float* dL, gpf_field_grad* grad,
+                             hipStream_t s);
 gpf_status launch_valu_probe(float* out, int blocks, int iters, hipStream_t s);
 gpf_status launch_mse(const float* L, const float* T, int64_t q, double* loss, float* dL,
                       hipStream_t s);

@@ -1,42 +1,24 @@
-// Radiance query (forward), its gradient (backward) and the exact pair count.
+// Radiance query (forward), its gradient (backward) and the exact pair count,
+// for the 3-sigma truncated, un-normalised sum.
 //
-// Work decomposition: one wave64 per query tile (<= 64 sorted points in one
-// occupied grid cell).  The wave first culls its cell's primitive list
-// against the tile's tight box with the whitened-frame separating test and
-// compacts the survivors into a per-wave LDS list; then
-//  - forward:  one wave per group of consecutive tiles, lane = query points
-//              (kGroupTiles per lane), loop over survivors read with
-//              wave-uniform scalar loads, accumulate L in registers;
-//  - backward: one workgroup per group of consecutive tiles; lane = survivor,
-//              loop over the group's queries (broadcast from LDS), accumulate
-//              the 18 per-primitive sums in registers, map them to parameter
-//              gradients and add them with row-coalesced atomics.
+// Work decomposition: query points are sorted by cell and cut into tiles of
+// 64; two consecutive tiles of one cell form a group.
+//  - forward:  one wave per group, lane = query point (one per tile); the
+//              cell's candidates are culled against both tile boxes into an
+//              LDS list, then each survivor is read with wave-uniform scalar
+//              loads and evaluated on the tiles it may touch;
+//  - backward: one wave per group, lane = survivor (64 at a time), looping
+//              over the group's points broadcast from LDS; the 12 sums per
+//              primitive are added to padded rows with row-coalesced atomics
+//              and mapped to parameter gradients once per primitive.
 // Weights are recomputed in the backward; nothing per pair is stored.
-#include "common.h"
+#include "radiance_common.h"
 
 namespace gpf {
 namespace {
 
 constexpr int kWaves = 4;        // waves (tiles) per workgroup
 constexpr int kSurvCap = 512;    // survivor slots per wave
-
-struct TileCtx {
-  float cx, cy, cz;   // tile box centre
-  float hx, hy, hz;   // tile box half-extent (padded)
-};
-
-__device__ __forceinline__ TileCtx tile_ctx(const float4* __restrict__ tlo,
-                                            const float4* __restrict__ thi, int t) {
-  float4 lo = tlo[t], hi = thi[t];
-  TileCtx c;
-  c.cx = 0.5f * (lo.x + hi.x);
-  c.cy = 0.5f * (lo.y + hi.y);
-  c.cz = 0.5f * (lo.z + hi.z);
-  c.hx = 0.5f * (hi.x - lo.x) * 1.0001f + 1e-7f;
-  c.hy = 0.5f * (hi.y - lo.y) * 1.0001f + 1e-7f;
-  c.hz = 0.5f * (hi.z - lo.z) * 1.0001f + 1e-7f;
-  return c;
-}
 
 // May the primitive's cutoff ellipsoid reach any point of the tile box?
 // Lower bound of |u'_k| over the box is |u'_k(centre)| - sum_j |W'_kj| h_j.
@@ -52,11 +34,6 @@ __device__ __forceinline__ bool tile_may_touch(const PrimRec& r, const TileCtx& 
     acc += lb * lb;
   }
   return acc <= c2 * 1.0001f;
-}
-
-__device__ __forceinline__ void wave_sync_lds() {
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  __builtin_amdgcn_wave_barrier();
 }
 
 // Appends this lane's candidate (if it survives) to the wave's LDS list.
@@ -229,70 +206,6 @@ constexpr int kBwdThreads = kBwdWaves * 64;
 constexpr int kGroupQ = kTile * kGroupTiles;  // points per group (max, a multiple of 4)
 constexpr int kListCap = 128;                 // survivor slots per list and wave
 constexpr int kRowStride = 14;                // transpose row stride (12 sums, pad, row id)
-
-// Maps the per-primitive sums (kappa-scaled whitened frame, u' = kappa u,
-// W' = kappa W) to the 13 parameter gradients:
-//   GP = sum w g,  A' = sum c u',  U' = sum c u' u'^T   (c = w g.Phi).
-// Since d = W^-1 u = R diag(s) u' / kappa, the sums M[k][j] = sum c u_k d_j
-// follow from U': M[k][j] = sum_l U'[k][l] R[j][l] s_l / kappa^2.  Then
-//   dmu = W^T A = W'^T A' / kappa^2,   dsigma_k = U'[k][k] / kappa^2,
-//   dR[j][k] = -M[k][j] / s_k,
-//   dq = (I - qhat qhat^T) dqhat / |q|,  dqhat = sum_jk dR[j][k] dR[j][k]/dqhat,
-//   dPhi = GP.
-// out: [0..2] mu, [3..6] quat, [7..9] log_scale, [10..12] rgb.
-__device__ __forceinline__ void grad_epilogue(const PrimRec& r, const float* __restrict__ quat,
-                                              const float* __restrict__ ls, int pid,
-                                              const float GP[3], const float A[3],
-                                              const float U[6], float out[13]) {
-  const float ik2 = (float)(1.0 / kKappa2);
-  const float4 wr[3] = {r.r1, r.r2, r.r3};
-  out[0] = (wr[0].x * A[0] + wr[1].x * A[1] + wr[2].x * A[2]) * ik2;
-  out[1] = (wr[0].y * A[0] + wr[1].y * A[1] + wr[2].y * A[2]) * ik2;
-  out[2] = (wr[0].z * A[0] + wr[1].z * A[1] + wr[2].z * A[2]) * ik2;
-  float qw = quat[pid * 4], qx = quat[pid * 4 + 1], qy = quat[pid * 4 + 2], qz = quat[pid * 4 + 3];
-  const float qn = sqrtf(qw * qw + qx * qx + qy * qy + qz * qz);
-  const float iq = 1.f / qn;
-  qw *= iq; qx *= iq; qy *= iq; qz *= iq;
-  float R[3][3];
-  R[0][0] = 1.f - 2.f * (qy * qy + qz * qz);
-  R[0][1] = 2.f * (qx * qy - qw * qz);
-  R[0][2] = 2.f * (qx * qz + qw * qy);
-  R[1][0] = 2.f * (qx * qy + qw * qz);
-  R[1][1] = 1.f - 2.f * (qx * qx + qz * qz);
-  R[1][2] = 2.f * (qy * qz - qw * qx);
-  R[2][0] = 2.f * (qx * qz - qw * qy);
-  R[2][1] = 2.f * (qy * qz + qw * qx);
-  R[2][2] = 1.f - 2.f * (qx * qx + qy * qy);
-  const float sc[3] = {__expf(ls[pid * 3]), __expf(ls[pid * 3 + 1]), __expf(ls[pid * 3 + 2])};
-  const float Uf[3][3] = {{U[0], U[1], U[2]}, {U[1], U[3], U[4]}, {U[2], U[4], U[5]}};
-  float G[3][3];  // G[j][k] = d loss / d R[j][k] = -M[k][j] / s_k
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    const float f = -ik2 / sc[k];
-#pragma unroll
-    for (int j = 0; j < 3; ++j)
-      G[j][k] = f * (Uf[k][0] * R[j][0] * sc[0] + Uf[k][1] * R[j][1] * sc[1] +
-                     Uf[k][2] * R[j][2] * sc[2]);
-  }
-  float gw = 2.f * (qz * (G[1][0] - G[0][1]) + qy * (G[0][2] - G[2][0]) + qx * (G[2][1] - G[1][2]));
-  float gx = 2.f * (qy * (G[0][1] + G[1][0]) + qz * (G[0][2] + G[2][0]) + qw * (G[2][1] - G[1][2]) -
-                    2.f * qx * (G[1][1] + G[2][2]));
-  float gy = 2.f * (qx * (G[0][1] + G[1][0]) + qz * (G[1][2] + G[2][1]) + qw * (G[0][2] - G[2][0]) -
-                    2.f * qy * (G[0][0] + G[2][2]));
-  float gz = 2.f * (qx * (G[0][2] + G[2][0]) + qy * (G[1][2] + G[2][1]) + qw * (G[1][0] - G[0][1]) -
-                    2.f * qz * (G[0][0] + G[1][1]));
-  const float dot = qw * gw + qx * gx + qy * gy + qz * gz;
-  out[3] = (gw - dot * qw) * iq;
-  out[4] = (gx - dot * qx) * iq;
-  out[5] = (gy - dot * qy) * iq;
-  out[6] = (gz - dot * qz) * iq;
-  out[7] = U[0] * ik2;
-  out[8] = U[3] * ik2;
-  out[9] = U[5] * ik2;
-  out[10] = GP[0];
-  out[11] = GP[1];
-  out[12] = GP[2];
-}
 
 // 64 survivors (lane = primitive) against the points [qb, qe) of the wave's
 // group, held in LDS relative to the group centre (points past the group's
@@ -478,42 +391,6 @@ __global__ void __launch_bounds__(kBwdThreads) eval_bwd_kernel(
   }
 }
 
-// Per primitive: the sums (GP, A', U') gathered over every group become the
-// 13 parameter gradients, which are added to the caller's arrays; the rows
-// are cleared for the next call.
-__global__ void __launch_bounds__(256) grad_finalize_kernel(float4* __restrict__ rows, int n,
-                                                            const PrimRec* __restrict__ recs,
-                                                            const float* __restrict__ quat,
-                                                            const float* __restrict__ ls,
-                                                            float* __restrict__ gmu,
-                                                            float* __restrict__ gq,
-                                                            float* __restrict__ gls,
-                                                            float* __restrict__ grgb) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const float4 a = rows[i * 4], b = rows[i * 4 + 1], c = rows[i * 4 + 2];
-  const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
-  rows[i * 4] = z;
-  rows[i * 4 + 1] = z;
-  rows[i * 4 + 2] = z;
-  const float GP[3] = {a.x, a.y, a.z}, A[3] = {a.w, b.x, b.y};
-  const float U[6] = {b.z, b.w, c.x, c.y, c.z, c.w};
-  float out[13];
-  grad_epilogue(recs[i], quat, ls, i, GP, A, U, out);
-  gmu[i * 3] += out[0];
-  gmu[i * 3 + 1] += out[1];
-  gmu[i * 3 + 2] += out[2];
-  gq[i * 4] += out[3];
-  gq[i * 4 + 1] += out[4];
-  gq[i * 4 + 2] += out[5];
-  gq[i * 4 + 3] += out[6];
-  gls[i * 3] += out[7];
-  gls[i * 3 + 1] += out[8];
-  gls[i * 3 + 2] += out[9];
-  grgb[i * 3] += out[10];
-  grgb[i * 3 + 1] += out[11];
-  grgb[i * 3 + 2] += out[12];
-}
 
 }  // namespace
 
@@ -529,11 +406,9 @@ gpf_status launch_eval_fwd(const gpf_grid* g, float* L, hipStream_t s) {
   return GPF_OK;
 }
 
-gpf_status launch_eval_bwd(const gpf_grid* gc, const float* dL, gpf_field_grad* grad,
-                           hipStream_t s) {
-  gpf_grid* g = const_cast<gpf_grid*>(gc);  // scratch rows live in the handle
-  const gpf_queries* qs = g->qs;
-  const float c2 = (float)(kKappa2 * g->cutoff * g->cutoff);
+// The padded per-primitive rows the backward passes gather into (allocated
+// and cleared once per handle; the finalize pass leaves them zeroed).
+gpf_status ensure_grad_rows(gpf_grid* g, hipStream_t s) {
   if (g->grad_cap < g->n) {
     dev_free(g->grad_rows, g->grad_cap * sizeof(float4) * 4);
     g->grad_rows = nullptr;
@@ -545,15 +420,30 @@ gpf_status launch_eval_bwd(const gpf_grid* gc, const float* dL, gpf_field_grad* 
     g->grad_cap = g->n;
     g->bytes += (size_t)g->n * sizeof(float4) * 4;
   }
+  return GPF_OK;
+}
+
+gpf_status launch_grad_finalize(gpf_grid* g, gpf_field_grad* grad, hipStream_t s) {
+  hipLaunchKernelGGL(grad_finalize_kernel, dim3((unsigned)((g->n + 255) / 256)), dim3(256), 0, s,
+                     g->grad_rows, (int)g->n, g->rec, g->quat, g->log_scale, grad->mu,
+                     grad->quat, grad->log_scale, grad->rgb);
+  GPF_HIP(hipGetLastError());
+  return GPF_OK;
+}
+
+gpf_status launch_eval_bwd(const gpf_grid* gc, const float* dL, gpf_field_grad* grad,
+                           hipStream_t s) {
+  gpf_grid* g = const_cast<gpf_grid*>(gc);  // scratch rows live in the handle
+  const gpf_queries* qs = g->qs;
+  const float c2 = (float)(kKappa2 * g->cutoff * g->cutoff);
+  gpf_status st = ensure_grad_rows(g, s);
+  if (st != GPF_OK) return st;
   hipLaunchKernelGGL(eval_bwd_kernel, dim3(xcd_grid((qs->ngroups + kBwdWaves - 1) / kBwdWaves)),
                      dim3(kBwdThreads), 0, s, qs->xs,
                      qs->perm, qs->groups, qs->group_lo, qs->group_hi, (int)qs->ngroups,
                      qs->tile_lo, qs->tile_hi, g->cell_start, g->cell_prims, g->rec, c2, dL,
                      (float*)g->grad_rows);
-  hipLaunchKernelGGL(grad_finalize_kernel, dim3((unsigned)((g->n + 255) / 256)), dim3(256), 0, s,
-                     g->grad_rows, (int)g->n, g->rec, g->quat, g->log_scale, grad->mu, grad->quat, grad->log_scale, grad->rgb);
-  GPF_HIP(hipGetLastError());
-  return GPF_OK;
+  return launch_grad_finalize(g, grad, s);
 }
 
 gpf_status launch_count_pairs(const gpf_grid* g, unsigned long long* d_count, hipStream_t s) {

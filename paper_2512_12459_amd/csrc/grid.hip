@@ -89,16 +89,28 @@ __device__ __forceinline__ bool box_may_touch(const PrimRec& r, float bx, float 
   return acc <= c2 * 1.001f;
 }
 
-// Visits the occupied cells of the primitive's cutoff box that pass the
-// whitened-frame test; counts them, or (kEmit) writes (cell slot, primitive)
+// Conservative test: may a point within distance `ball` of the centre lie in
+// the box with centre b and half-edge hh?  (Hybrid query: ball query of
+// radius r about each query point, Sec. 4.2 neighbourhood search.)
+__device__ __forceinline__ bool ball_may_touch(const PrimRec& r, float bx, float by, float bz,
+                                               float hh, float ball) {
+  const float ex = fmaxf(fabsf(bx - r.r0.x) - hh, 0.f);
+  const float ey = fmaxf(fabsf(by - r.r0.y) - hh, 0.f);
+  const float ez = fmaxf(fabsf(bz - r.r0.z) - hh, 0.f);
+  return ex * ex + ey * ey + ez * ez <= ball * ball * 1.001f + 1e-10f;
+}
+
+// Visits the occupied cells of the primitive's cutoff box (or, with ball > 0,
+// of the box of its ball) that pass the whitened-frame (or ball) test; counts
+// them, or (kEmit) writes (cell slot, primitive)
 // entries from `base` on.  Both passes read the same stored record and
 // extents, so they make identical decisions.
 template <bool kEmit>
 __device__ __forceinline__ int visit_cells(const PrimRec& r, const float ext[3], const Geom& g,
                                            const uint32_t* __restrict__ bits,
-                                           const int* __restrict__ occ_of_dense, float c2, int pid,
-                                           int* __restrict__ keys, int* __restrict__ vals,
-                                           int base, int limit) {
+                                           const int* __restrict__ occ_of_dense, float c2,
+                                           float ball, int pid, int* __restrict__ keys,
+                                           int* __restrict__ vals, int base, int limit) {
   const float inv = 1.f / g.h;
   const float m[3] = {r.r0.x, r.r0.y, r.r0.z};
   const float o[3] = {g.ox, g.oy, g.oz};
@@ -122,7 +134,9 @@ __device__ __forceinline__ int visit_cells(const PrimRec& r, const float ext[3],
         if (!((bits[dc >> 5] >> (dc & 31)) & 1u)) continue;
         const float bx = o[0] + (cx + 0.5f) * g.h, by = o[1] + (cy + 0.5f) * g.h,
                     bz = o[2] + (cz + 0.5f) * g.h;
-        if (!box_may_touch(r, bx, by, bz, hh, c2)) continue;
+        if (ball > 0.f ? !ball_may_touch(r, bx, by, bz, hh, ball)
+                       : !box_may_touch(r, bx, by, bz, hh, c2))
+          continue;
         if (kEmit && cnt < limit) {
           keys[base + cnt] = occ_of_dense[dc];
           vals[base + cnt] = pid;
@@ -137,7 +151,8 @@ __device__ __forceinline__ int visit_cells(const PrimRec& r, const float ext[3],
 // number of cells it registers in; `bad` counts degenerate primitives.
 __global__ void __launch_bounds__(256) count_kernel(
     const float* __restrict__ mu, const float* __restrict__ quat, const float* __restrict__ ls,
-    const float* __restrict__ rgb, int n, float cutoff, Geom g, const uint32_t* __restrict__ bits,
+    const float* __restrict__ rgb, int n, float cutoff, float ball, Geom g,
+    const uint32_t* __restrict__ bits,
     const int* __restrict__ occ_of_dense, PrimRec* __restrict__ recs, float4* __restrict__ exts,
     int* __restrict__ prim_cnt, int* __restrict__ bad) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -145,6 +160,7 @@ __global__ void __launch_bounds__(256) count_kernel(
   PrimRec r;
   float ext[3];
   const bool ok = prim_frame(mu, quat, ls, rgb, i, cutoff, &r, ext);
+  if (ball > 0.f) ext[0] = ext[1] = ext[2] = ball * (1.f + 1e-5f);
   recs[i] = r;
   exts[i] = make_float4(ext[0], ext[1], ext[2], ok ? 1.f : 0.f);
   if (!ok) {
@@ -153,11 +169,12 @@ __global__ void __launch_bounds__(256) count_kernel(
     return;
   }
   const float c2 = (float)(kKappa2 * cutoff * cutoff);
-  prim_cnt[i] = visit_cells<false>(r, ext, g, bits, occ_of_dense, c2, i, nullptr, nullptr, 0, 0);
+  prim_cnt[i] =
+      visit_cells<false>(r, ext, g, bits, occ_of_dense, c2, ball, i, nullptr, nullptr, 0, 0);
 }
 
 // Pass 2: entries in primitive-major order at the scanned offsets.
-__global__ void __launch_bounds__(256) emit_kernel(int n, float cutoff, Geom g,
+__global__ void __launch_bounds__(256) emit_kernel(int n, float cutoff, float ball, Geom g,
                                                    const uint32_t* __restrict__ bits,
                                                    const int* __restrict__ occ_of_dense,
                                                    const PrimRec* __restrict__ recs,
@@ -172,7 +189,7 @@ __global__ void __launch_bounds__(256) emit_kernel(int n, float cutoff, Geom g,
   const float c2 = (float)(kKappa2 * cutoff * cutoff);
   const int base = prim_off[i];
   // never write past this primitive's range, whatever the visit decides
-  visit_cells<true>(recs[i], ext, g, bits, occ_of_dense, c2, i, keys, vals, base,
+  visit_cells<true>(recs[i], ext, g, bits, occ_of_dense, c2, ball, i, keys, vals, base,
                     prim_off[i + 1] - base);
 }
 
@@ -230,7 +247,7 @@ gpf_status launch_build_grid(gpf_grid* g, hipStream_t s) {
   int* off = g->prim_off + n + 2;
   GPF_HIP(hipMemsetAsync(cnt + n, 0, 2 * sizeof(int), s));
   hipLaunchKernelGGL(count_kernel, dim3(nb), dim3(256), 0, s, g->mu, g->quat, g->log_scale, g->rgb,
-                     n, g->cutoff, geo, qs->occ_bits, qs->occ_of_dense, g->rec, g->ext, cnt,
+                     n, g->cutoff, g->ball, geo, qs->occ_bits, qs->occ_of_dense, g->rec, g->ext, cnt,
                      cnt + n + 1);
   size_t scan_bytes = 0;
   GPF_HIP(rocprim::exclusive_scan(nullptr, scan_bytes, cnt, off, 0, (size_t)(n + 1),
@@ -270,7 +287,7 @@ gpf_status launch_build_grid(gpf_grid* g, hipStream_t s) {
     g->cap = want;
   }
   g->entries = E;
-  hipLaunchKernelGGL(emit_kernel, dim3(nb), dim3(256), 0, s, n, g->cutoff, geo, qs->occ_bits,
+  hipLaunchKernelGGL(emit_kernel, dim3(nb), dim3(256), 0, s, n, g->cutoff, g->ball, geo, qs->occ_bits,
                      qs->occ_of_dense, g->rec, g->ext, off, g->keys, g->vals);
   // stable sort by cell slot: each cell's primitives end up in ascending order
   int bits_needed = 1;
@@ -294,6 +311,11 @@ gpf_status launch_build_grid(gpf_grid* g, hipStream_t s) {
   GPF_HIP(hipGetLastError());
   g->bytes = g->rec_cap * (sizeof(PrimRec) + sizeof(float4) + 2 * sizeof(int)) +
              (size_t)(nc + 1) * sizeof(int) + 4 * g->cap * sizeof(int) + g->sort_tmp_bytes;
+  if (g->ball > 0.f) {
+    gpf_status st = build_centre_grid(g, s);
+    if (st != GPF_OK) return st;
+    g->bytes += g->cg_bytes;
+  }
   return GPF_OK;
 }
 

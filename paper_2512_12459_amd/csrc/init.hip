@@ -6,86 +6,13 @@
 
 #include "common.h"
 #include "mlp.h"
+#include "pointgrid.h"
 
 namespace gpf {
 namespace {
 
 constexpr int kMaxK = 32;
 constexpr int kPhotonDim = 256;  // cells per axis (max)
-
-struct PGrid {
-  float ox, oy, oz, h;
-  int dx, dy, dz;
-};
-
-__device__ __forceinline__ int3 pcell(const PGrid& g, float x, float y, float z) {
-  int3 c;
-  c.x = min(max((int)floorf((x - g.ox) / g.h), 0), g.dx - 1);
-  c.y = min(max((int)floorf((y - g.oy) / g.h), 0), g.dy - 1);
-  c.z = min(max((int)floorf((z - g.oz) / g.h), 0), g.dz - 1);
-  return c;
-}
-
-__global__ void pbox_kernel(const float* __restrict__ pos, int64_t n, float* part) {
-  float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x)
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      lo[a] = fminf(lo[a], pos[i * 3 + a]);
-      hi[a] = fmaxf(hi[a], pos[i * 3 + a]);
-    }
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1)
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      lo[a] = fminf(lo[a], __shfl_xor(lo[a], off, 64));
-      hi[a] = fmaxf(hi[a], __shfl_xor(hi[a], off, 64));
-    }
-  __shared__ float s[4][6];
-  const int w = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0)
-    for (int a = 0; a < 3; ++a) {
-      s[w][a] = lo[a];
-      s[w][3 + a] = hi[a];
-    }
-  __syncthreads();
-  if (threadIdx.x < 6) {
-    float v = s[0][threadIdx.x];
-    for (int k = 1; k < 4; ++k) v = threadIdx.x < 3 ? fminf(v, s[k][threadIdx.x]) : fmaxf(v, s[k][threadIdx.x]);
-    part[blockIdx.x * 6 + threadIdx.x] = v;
-  }
-}
-
-__global__ void pcount_kernel(const float* __restrict__ pos, int64_t n, PGrid g,
-                              int* __restrict__ cnt) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int3 c = pcell(g, pos[i * 3], pos[i * 3 + 1], pos[i * 3 + 2]);
-  atomicAdd(&cnt[(c.z * g.dy + c.y) * g.dx + c.x], 1);
-}
-
-__global__ void pscatter_kernel(const float* __restrict__ pos, int64_t n, PGrid g,
-                                const int* __restrict__ start, int* __restrict__ fill,
-                                int* __restrict__ sorted) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int3 c = pcell(g, pos[i * 3], pos[i * 3 + 1], pos[i * 3 + 2]);
-  const int cell = (c.z * g.dy + c.y) * g.dx + c.x;
-  const int slot = atomicAdd(&fill[cell], 1);
-  sorted[start[cell] + slot] = (int)i;
-}
-
-// (d2, index) order; FP32 squared distance without fused multiply-add
-__device__ __forceinline__ float sqd(float ax, float ay, float az, float bx, float by, float bz) {
-#pragma clang fp contract(off)
-  const float dx = bx - ax, dy = by - ay, dz = bz - az;
-  return (dx * dx + dy * dy) + dz * dz;
-}
-
-__device__ __forceinline__ bool before(float da, int ia, float db, int ib) {
-  return da < db || (da == db && ia < ib);
-}
 
 // One thread per photon: rings of cells around its own cell until the k-th
 // best distance is below the distance to any unvisited cell.
@@ -251,7 +178,7 @@ __global__ void __launch_bounds__(256) targets_kernel(const float* __restrict__ 
 
 gpf_status photon_knn(const float* pos, int64_t n, int k, int* idx, float* d2, hipStream_t s) {
   // bounding box -> cubic cells holding about one photon per cell in volume
-  const int nb = 64;
+  const int nb = kPointBoxBlocks;
   float* part = nullptr;
   gpf_status st = dev_alloc((void**)&part, nb * 6 * sizeof(float), "photon box");
   if (st != GPF_OK) return st;
@@ -261,26 +188,9 @@ gpf_status photon_knn(const float* pos, int64_t n, int k, int* idx, float* d2, h
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   dev_free(part, nb * 6 * sizeof(float));
   if (e != hipSuccess) return hip_fail(e, "photon box");
-  float lo[3], hi[3];
-  for (int a = 0; a < 3; ++a) {
-    lo[a] = hp[a];
-    hi[a] = hp[3 + a];
-    for (int b = 1; b < nb; ++b) {
-      lo[a] = std::fmin(lo[a], hp[b * 6 + a]);
-      hi[a] = std::fmax(hi[a], hp[b * 6 + 3 + a]);
-    }
-    if (!std::isfinite(lo[a]) || !std::isfinite(hi[a]))
-      return set_error(GPF_ERR_INVALID_ARGUMENT, "photon positions contain NaN or Inf");
-  }
-  double ext = 0;
-  for (int a = 0; a < 3; ++a) ext = std::fmax(ext, (double)hi[a] - lo[a]);
-  double vol = 1;
-  for (int a = 0; a < 3; ++a) vol *= std::fmax((double)hi[a] - lo[a], ext * 1e-3 + 1e-12);
-  double h = std::cbrt(vol / (double)n);
-  h = std::fmax(h, ext / kPhotonDim + 1e-12);
-  PGrid g{lo[0], lo[1], lo[2], (float)h, 1, 1, 1};
-  int* dims[3] = {&g.dx, &g.dy, &g.dz};
-  for (int a = 0; a < 3; ++a) *dims[a] = std::min(kPhotonDim, (int)std::floor(((double)hi[a] - lo[a]) / h) + 1);
+  PGrid g;
+  st = point_grid_geometry(hp, n, kPhotonDim, &g);
+  if (st != GPF_OK) return st;
   const int64_t cells = (int64_t)g.dx * g.dy * g.dz;
   int *cnt = nullptr, *start = nullptr, *sorted = nullptr;
   void* tmp = nullptr;

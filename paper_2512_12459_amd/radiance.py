@@ -161,6 +161,84 @@ class GPFRadiance(torch.autograd.Function):
         return g["mu"], g["quat"], g["log_scale"], g["rgb"], None
 
 
+class HybridGrid(Grid):
+    """Cull structure of the hybrid query (the paper's ball + nearest-centre
+    neighbourhood, supplementary Alg. S3) over one query set; rebuild after
+    every parameter change (``build``)."""
+
+    def __init__(self, queries: QuerySet, r: float = 0.02, k_min: int = 3, eps: float = 1e-6):
+        super().__init__(queries)
+        self.r = float(r)
+        self.k_min = int(k_min)
+        self.eps = float(eps)
+
+    def build(self, mu, quat, log_scale, rgb) -> "HybridGrid":
+        fs = field_struct(mu, quat, log_scale, rgb)
+        C.check(C.lib().gpf_build_grid_hybrid(ctypes.byref(fs), self.r, self.k_min,
+                                              self.queries.handle, _stream(),
+                                              ctypes.byref(self.handle)))
+        self._field = (mu, quat, log_scale, rgb)
+        return self
+
+    def count_pairs(self) -> int:
+        raise NotImplementedError("the hybrid query's pair count is sum(max(count, k_min)) "
+                                  "over eval_hybrid's count output")
+
+
+def eval_hybrid(grid: HybridGrid, mu, quat, log_scale, rgb):
+    """(L [q,3], Z [q], count [q] int32) at the grid's query points."""
+    fs = field_struct(mu, quat, log_scale, rgb)
+    x = grid.queries.x
+    q = x.shape[0]
+    L = torch.empty((q, 3), device=x.device, dtype=torch.float32)
+    Z = torch.empty(q, device=x.device, dtype=torch.float32)
+    count = torch.empty(q, device=x.device, dtype=torch.int32)
+    C.check(C.lib().gpf_eval_hybrid(grid.handle, ctypes.byref(fs), C.ptr(x), q, grid.eps,
+                                    C.ptr(L), C.ptr(Z), C.ptr(count), _stream()))
+    return L, Z, count
+
+
+def eval_hybrid_backward(grid: HybridGrid, mu, quat, log_scale, rgb, L, Z, count, dL, grads=None):
+    """Adds d(loss)/d(params) for upstream dL [q,3] into ``grads``, given the
+    forward's L, Z and count."""
+    fs = field_struct(mu, quat, log_scale, rgb)
+    x = grid.queries.x
+    _need(dL, "dL", 3)
+    _need(L, "L", 3)
+    for t, name, dt in ((Z, "Z", torch.float32), (count, "count", torch.int32)):
+        if t.dtype != dt or not t.is_contiguous() or t.shape != (x.shape[0],):
+            raise ValueError(f"{name} must be a contiguous [q] {dt} tensor")
+    if grads is None:
+        grads = dict(mu=torch.zeros_like(mu), quat=torch.zeros_like(quat),
+                     log_scale=torch.zeros_like(log_scale), rgb=torch.zeros_like(rgb))
+    gs = C.FieldGrad(C.ptr(grads["mu"]), C.ptr(grads["quat"]), C.ptr(grads["log_scale"]),
+                     C.ptr(grads["rgb"]))
+    C.check(C.lib().gpf_eval_hybrid_backward(grid.handle, ctypes.byref(fs), C.ptr(x), x.shape[0],
+                                             grid.eps, C.ptr(L), C.ptr(Z), C.ptr(count), C.ptr(dL),
+                                             ctypes.byref(gs), _stream()))
+    return grads
+
+
+class GPFHybridRadiance(torch.autograd.Function):
+    """L = GPFHybridRadiance.apply(mu, quat, log_scale, rgb, grid).
+
+    The context keeps the parameter tensors and the per-point normaliser and
+    ball count (nothing per pair); the backward recomputes every weight."""
+
+    @staticmethod
+    def forward(ctx, mu, quat, log_scale, rgb, grid):
+        L, Z, count = eval_hybrid(grid, mu, quat, log_scale, rgb)
+        ctx.save_for_backward(mu, quat, log_scale, rgb, L, Z, count)
+        ctx.grid = grid
+        return L
+
+    @staticmethod
+    def backward(ctx, dL):
+        mu, quat, log_scale, rgb, L, Z, count = ctx.saved_tensors
+        g = eval_hybrid_backward(ctx.grid, mu, quat, log_scale, rgb, L, Z, count, dL.contiguous())
+        return g["mu"], g["quat"], g["log_scale"], g["rgb"], None
+
+
 def mse_loss(L: torch.Tensor, T: torch.Tensor, dL: torch.Tensor | None = None,
              loss_sum: torch.Tensor | None = None):
     """Returns (loss_sum [1] float64 device tensor, dL); MSE = loss_sum / q."""

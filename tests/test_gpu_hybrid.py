@@ -1,0 +1,188 @@
+"""GPU parity of the hybrid query (supplementary Alg. S3; Sec. 4.2: ball of
+radius r, nearest-centre top-up to k_min, distance falloff, normalised sum)
+against the FP64 oracle, through the C ABI: ball counts bit-exact, L and Z
+within the conditioning-aware bars, gradients within 1e-4 of their error
+scale and against central differences of the FP64 loss, plus edge cases."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import hybrid_oracle as H
+from oracle.tolerances import check_grads, check_hybrid_forward
+from paper_2512_12459_amd import scenes as S
+from tests.gpu_helpers import say, to_dev
+
+pytestmark = pytest.mark.gpu
+R_Q = 0.02
+
+
+@pytest.fixture(scope="module")
+def rad():
+    from paper_2512_12459_amd import radiance
+    radiance.C.lib()
+    return radiance
+
+
+def _field(seed, n, spread, scale=0.01, aniso=0.3):
+    rng = np.random.default_rng(seed)
+    mu = rng.random((n, 3)) * spread
+    q = rng.normal(size=(n, 4))
+    ls = math.log(scale) + rng.normal(0, aniso, (n, 3))
+    ls[:, 2] += math.log(0.3)
+    rgb = np.exp(rng.normal(0, 1, (n, 3)))
+    return [a.astype(np.float32) for a in (mu, q, ls, rgb)]
+
+
+def _points(seed, nq, spread, planes=8):
+    rng = np.random.default_rng(seed)
+    x = rng.random((nq, 3)) * spread * 1.1 - 0.05 * spread
+    x[:, 1] = np.round(x[:, 1] * planes / spread) / planes * spread   # points on a few planes
+    return x.astype(np.float32)
+
+
+def _run(rad, f, x, r=R_Q, k_min=3, eps=1e-6, cell=0.025, dL=None):
+    dev = to_dev(*f)
+    (xd,) = to_dev(x)
+    qs = rad.QuerySet(xd, cell)
+    g = rad.HybridGrid(qs, r, k_min, eps).build(*dev)
+    L, Z, cnt = rad.eval_hybrid(g, *dev)
+    grads = None
+    if dL is not None:
+        (dLd,) = to_dev(dL)
+        grads = rad.eval_hybrid_backward(g, *dev, L, Z, cnt, dLd)
+        grads = {k: v.cpu().numpy() for k, v in grads.items()}
+    torch.cuda.synchronize()
+    return L.cpu().numpy(), Z.cpu().numpy(), cnt.cpu().numpy(), grads
+
+
+def _check(rad, f, x, r=R_Q, k_min=3, eps=1e-6, cell=0.025, backward=True, seed=0):
+    ref = H.radiance(*f, x, r, k_min, eps)
+    dL = np.random.default_rng(seed).normal(size=(len(x), 3)).astype(np.float32) if backward else None
+    L, Z, cnt, grads = _run(rad, f, x, r, k_min, eps, cell, dL)
+    check_hybrid_forward(L, Z, cnt, ref)
+    if backward:
+        gref = H.radiance_backward(*f, x, dL, r, k_min, eps, sets=ref["sets"])
+        check_grads(grads, gref)
+    return ref
+
+
+def test_plain4k_forward_and_backward(rad):
+    f, x = S.workload("plain4k")
+    say(f"case: hybrid plain4k, n={f.n} q={len(x)}")
+    ref = _check(rad, f.arrays(), x)
+    top = ref["count"] < 3
+    say(f"top-up points {top.sum()} of {len(x)}, mean ball count {ref['count'].mean():.2f}")
+    assert top.any() and (~top).any()
+
+
+def test_dense_volume_forward_and_backward(rad):
+    f = _field(1, 3000, 0.15)
+    x = _points(2, 4000, 0.15)
+    say("case: hybrid dense volume, n=3000 q=4000")
+    ref = _check(rad, f, x, seed=3)
+    assert ref["count"].mean() > 10
+
+
+@pytest.mark.parametrize("cell", [0.0125, 0.05])
+def test_grid_invariance(rad, cell):
+    f = _field(4, 800, 0.1)
+    x = _points(5, 1500, 0.1)
+    say(f"case: hybrid grid cell {cell}")
+    _check(rad, f, x, cell=cell, seed=6)
+
+
+@pytest.mark.parametrize("k_min", [1, 5, 8])
+def test_top_up_sizes(rad, k_min):
+    f = _field(7, 300, 0.2)
+    x = _points(8, 1200, 0.2)
+    say(f"case: hybrid k_min={k_min}")
+    ref = _check(rad, f, x, k_min=k_min, seed=9)
+    assert np.any(ref["count"] < k_min)
+
+
+def test_edge_cases(rad):
+    # fewer Gaussians than k_min; points far from every centre (weights below
+    # eps: L = sum / eps); a single point; a large radius
+    f = _field(10, 2, 0.02)
+    x = np.concatenate([_points(11, 64, 0.03), np.array([[3.0, 3.0, 3.0], [0.01, 0.01, 0.01]],
+                                                          np.float32)])
+    say("case: hybrid n=2 < k_min, far points")
+    ref = _check(rad, f, x, seed=12)
+    assert ref["Z"][-2] < 1e-6
+    say("case: hybrid q=1")
+    _check(rad, f, x[-1:], seed=13)
+    f3 = _field(14, 200, 0.1, scale=0.05)
+    say("case: hybrid r=0.2")
+    _check(rad, f3, _points(15, 500, 0.1), r=0.2, seed=16)
+
+
+def test_gradient_vs_finite_differences(rad):
+    f = _field(17, 60, 0.06, scale=0.012)
+    x = _points(18, 500, 0.06)
+    x[:40] += np.float32(0.07)                       # sparse points use the top-up
+    T = np.random.default_rng(19).random((len(x), 3)).astype(np.float32)
+    ref = H.radiance(*f, x, R_Q, 3)
+    dL = (2 * (ref["L"] - T) / len(x)).astype(np.float32)
+    say("case: hybrid backward vs finite differences")
+    _, _, _, gg = _run(rad, f, x, dL=dL)
+    sets = ref["sets"]
+    keys = ("mu", "quat", "log_scale", "rgb")
+    base = {k: a.astype(np.float64) for k, a in zip(keys, f)}
+    sizes = np.bincount(np.concatenate(sets), minlength=len(f[0]))
+    idx = [int(i) for i in np.argsort(-sizes)[:5]]
+    checked = 0
+    for name in keys:
+        for i in idx:
+            for c in range(base[name].shape[1]):
+                h = 1e-6 * (abs(base[name][i, c]) if name == "rgb" else 1.0)
+                vals = []
+                for sgn in (1, -1):
+                    p = {k: v.copy() for k, v in base.items()}
+                    p[name][i, c] += sgn * h
+                    vals.append(H.loss_of_params(*(p[k] for k in keys), x, T, R_Q, 3, sets=sets))
+                fd = (vals[0] - vals[1]) / (2 * h)
+                scale = max(abs(fd), 1e-2 * np.max(np.abs(gg[name][idx])))
+                assert abs(gg[name][i, c] - fd) <= 1e-4 * scale + 1e-9, (name, i, c, gg[name][i, c], fd)
+                checked += 1
+    assert checked >= 40
+
+
+def test_autograd_function(rad):
+    f = _field(20, 400, 0.1)
+    x = _points(21, 800, 0.1)
+    dev = [t.clone().requires_grad_(True) for t in to_dev(*f)]
+    (xd,) = to_dev(x)
+    qs = rad.QuerySet(xd, 0.025)
+    g = rad.HybridGrid(qs).build(*dev)
+    say("case: hybrid autograd function")
+    L = rad.GPFHybridRadiance.apply(*dev, g)
+    w = torch.randn_like(L)
+    (L * w).sum().backward()
+    det = [t.detach() for t in dev]
+    L2, Z, cnt = rad.eval_hybrid(g, *det)
+    direct = rad.eval_hybrid_backward(g, *det, L2, Z, cnt, w.contiguous())
+    for t, k in zip(dev, ("mu", "quat", "log_scale", "rgb")):
+        scale = direct[k].abs().max().item()
+        assert torch.allclose(t.grad, direct[k], rtol=1e-5, atol=1e-6 * scale), k
+
+
+def test_mode_errors(rad):
+    from paper_2512_12459_amd._lib import GPFError
+    f = _field(22, 50, 0.05)
+    dev = to_dev(*f)
+    (xd,) = to_dev(_points(23, 100, 0.05))
+    qs = rad.QuerySet(xd, 0.025)
+    hg = rad.HybridGrid(qs).build(*dev)
+    with pytest.raises(GPFError) as e:
+        rad.eval_radiance(hg, *dev)
+    assert e.value.status == 1
+    tg = rad.Grid(qs).build(*dev)
+    with pytest.raises(GPFError) as e:
+        rad.eval_hybrid(tg, *dev)
+    assert e.value.status == 1
+    for r, k in ((0.0, 3), (0.02, 0), (0.02, 9)):
+        with pytest.raises(GPFError) as e:
+            rad.HybridGrid(qs, r, k).build(*dev)
+        assert e.value.status == 1
