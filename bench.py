@@ -27,6 +27,12 @@ if ROOT not in sys.path:
 # counts 2), backward 64 (recompute 28, a and c 6, accumulators 30).
 FLOPS_FWD = 34
 FLOPS_BWD = 64
+# Hybrid query (ball + nearest-centre top-up, falloff, normalised), per
+# neighbourhood pair: forward 36 (offset 3, squared distance 5, whitening 15,
+# m^2 5, exp 1, accumulate L and Z 7), backward 60 (recompute 29, a 6, c 1,
+# accumulators 24).
+FLOPS_FWD_HYBRID = 36
+FLOPS_BWD_HYBRID = 60
 PEAK_FP32_VALU = 157.3e12      # published FP32 vector peak
 
 
@@ -52,7 +58,7 @@ def measured_traffic(kernel: str, workload: str, default_shape: bool):
     return None if k is None else float(k["hbm_bytes"])
 
 
-def cpu_baseline(field, x, sample: int, seed: int = 11):
+def cpu_baseline(field, x, sample: int, seed: int = 11, hybrid: bool = False):
     """The FP64 oracle (brute force over all primitives) forward + backward on
     a bounded random sample of query points, over a process pool."""
     import concurrent.futures as cf
@@ -69,14 +75,17 @@ def cpu_baseline(field, x, sample: int, seed: int = 11):
     t0 = time.perf_counter()
     ctx = mp.get_context("spawn")
     with cf.ProcessPoolExecutor(cores, mp_context=ctx) as ex:
-        futs = [ex.submit(cpu_timing.fwd_bwd_chunk, field.mu, field.quat, field.log_scale,
-                          field.rgb, xs[c]) for c in chunks if len(c)]
+        fn = cpu_timing.hybrid_fwd_bwd_chunk if hybrid else cpu_timing.fwd_bwd_chunk
+        futs = [ex.submit(fn, field.mu, field.quat, field.log_scale, field.rgb, xs[c])
+                for c in chunks if len(c)]
         pairs = sum(f.result() for f in futs)
     dt = time.perf_counter() - t0
     return dict(value=sample / dt, unit="queries/s", cores=cores, kind="oracle",
                 sample=f"{sample} random query points of the same workload, FP64 brute force "
-                       f"over all {field.n} primitives, forward + backward, {cores} processes; "
-                       f"{pairs} contributing pairs; {dt:.1f} s wall")
+                       f"over all {field.n} primitives"
+                       + (" (hybrid query: ball r=0.02, top-up to 3 nearest)" if hybrid else "")
+                       + f", forward + backward, {cores} processes; {pairs} "
+                       + ("neighbourhood" if hybrid else "contributing") + f" pairs; {dt:.1f} s wall")
 
 
 def main():
@@ -90,6 +99,10 @@ def main():
     ap.add_argument("--cell", type=float, default=0.025)
     ap.add_argument("--lr", type=float, default=5e-4)
     ap.add_argument("--cpu-sample", type=int, default=1024)
+    ap.add_argument("--query", choices=("truncated", "hybrid"), default="truncated",
+                    help="truncated: 3-sigma un-normalised sum; hybrid: the paper's ball + "
+                         "nearest-centre neighbourhood with falloff and normalisation")
+    ap.add_argument("--radius", type=float, default=0.02, help="hybrid ball radius r")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MB",
                     help="only run a plain device-to-device copy of MB megabytes (5 times), "
@@ -151,14 +164,20 @@ def main():
     log(f"binned: {qinfo} in {t_bin:.2f} s")
 
     # targets: radiance of a second field, rendered once
+    hybrid = args.query == "hybrid"
     gt_dev = [torch.from_numpy(a).to(dev) for a in gt.arrays()]
-    gt_grid = R.Grid(qs).build(*gt_dev)
-    T = R.eval_radiance(gt_grid, *gt_dev)
+    if hybrid:
+        gt_grid = R.HybridGrid(qs, args.radius).build(*gt_dev)
+        T = R.eval_hybrid(gt_grid, *gt_dev)[0]
+    else:
+        gt_grid = R.Grid(qs).build(*gt_dev)
+        T = R.eval_radiance(gt_grid, *gt_dev)
     gt_grid.close()
     del gt_dev
     torch.cuda.synchronize()
 
-    grid = R.Grid(qs)
+    grid = R.HybridGrid(qs, args.radius) if hybrid else R.Grid(qs)
+    fwd_out = {}
     L = torch.empty((q, 3), device=dev)
     dL = torch.empty((q, 3), device=dev)
     loss = torch.zeros(1, dtype=torch.float64, device=dev)
@@ -173,13 +192,21 @@ def main():
         e0 = mark() if timed else None
         grid.build(mu, quat, ls, rgb)
         e1 = mark() if timed else None
-        R.eval_radiance(grid, mu, quat, ls, rgb, out=L)
+        if hybrid:
+            fwd_out["L"], fwd_out["Z"], fwd_out["count"] = R.eval_hybrid(grid, mu, quat, ls, rgb)
+            Lh = fwd_out["L"]
+        else:
+            Lh = R.eval_radiance(grid, mu, quat, ls, rgb, out=L)
         e2 = mark() if timed else None
         loss.zero_()
-        R.mse_loss(L, T, dL=dL, loss_sum=loss)
+        R.mse_loss(Lh, T, dL=dL, loss_sum=loss)
         G.zero_()
         e3 = mark() if timed else None
-        R.eval_radiance_backward(grid, mu, quat, ls, rgb, dL, grads)
+        if hybrid:
+            R.eval_hybrid_backward(grid, mu, quat, ls, rgb, Lh, fwd_out["Z"], fwd_out["count"],
+                                   dL, grads)
+        else:
+            R.eval_radiance_backward(grid, mu, quat, ls, rgb, dL, grads)
         e4 = mark() if timed else None
         R.adam_step(P, G, M, V, t, args.lr)
         e5 = mark() if timed else None
@@ -190,7 +217,11 @@ def main():
     for t in range(1, args.warmup + 1):
         step(t, False)
     torch.cuda.synchronize()
-    pairs = grid.count_pairs()
+    if hybrid:   # neighbourhood pairs: the ball, or min(3, n) nearest centres
+        c = fwd_out["count"].to(torch.int64)
+        pairs = int(torch.where(c >= 3, c, torch.full_like(c, min(3, n))).sum().item())
+    else:
+        pairs = grid.count_pairs()
     valu_tflops = R.valu_probe()   # measured FP32 FMA ceiling of this device
     log(f"measured FP32 FMA rate {valu_tflops:.1f} TFLOP/s")
     ginfo = grid.info()
@@ -209,10 +240,12 @@ def main():
     value = q / (step_ms * 1e-3)
     fb_ms = ms["fwd"] + ms["bwd"]
     dom = "bwd" if ms["bwd"] >= ms["fwd"] else "fwd"
-    flops = pairs * (FLOPS_BWD if dom == "bwd" else FLOPS_FWD)
+    fl_fwd, fl_bwd = (FLOPS_FWD_HYBRID, FLOPS_BWD_HYBRID) if hybrid else (FLOPS_FWD, FLOPS_BWD)
+    flops = pairs * (fl_bwd if dom == "bwd" else fl_fwd)
     achieved = flops / (ms[dom] * 1e-3)
     result = {
-        "metric": "fwd+bwd radiance queries/s @1M Gaussians",
+        "metric": "fwd+bwd radiance queries/s @1M Gaussians"
+                  + (", hybrid query (ball r, top-up to 3 nearest, normalised)" if hybrid else ""),
         "value": value,
         "unit": "queries/s",
         "n_gpus": 1,
@@ -224,7 +257,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: {n} Gaussians, {q} query points "
+        "config": {"query": args.query if not hybrid else f"hybrid r={args.radius} k_min=3 eps=1e-6",
+                   "workload": f"{args.workload}: {n} Gaussians, {q} query points "
                                f"({args.views or 'default'} views, res {args.res or 'default'})",
                    "step": "grid build + forward + MSE + backward + Adam",
                    "cell": args.cell},
@@ -235,19 +269,20 @@ def main():
         "loss": loss_v,
         "device_bytes": {"queries": qinfo["device_bytes"], "grid": ginfo["device_bytes"],
                          "torch_peak": torch.cuda.max_memory_allocated()},
-        "roofline": {"bound": "alu", "kernel": f"eval_{dom}", "achieved": achieved / 1e12,
+        "roofline": {"bound": "alu", "kernel": (f"hybrid_{dom}" if hybrid else f"eval_{dom}"),
+                     "achieved": achieved / 1e12,
                      "peak": PEAK_FP32_VALU / 1e12, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_VALU,
-                     "traffic": measured_traffic(f"eval_{dom}_kernel", args.workload,
+                     "traffic": None if hybrid else measured_traffic(f"eval_{dom}_kernel", args.workload,
                                                  not (args.views or args.res) and args.cell == 0.025),
                      "traffic_unit": "bytes per launch",
                      "measured_valu_ceiling": valu_tflops,
                      "frac_of_measured_ceiling": achieved / 1e12 / valu_tflops,
-                     "flops_per_pair": FLOPS_BWD if dom == "bwd" else FLOPS_FWD},
+                     "flops_per_pair": fl_bwd if dom == "bwd" else fl_fwd},
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
-        result["cpu_baseline"] = cpu_baseline(field, x, args.cpu_sample)
+        result["cpu_baseline"] = cpu_baseline(field, x, args.cpu_sample, hybrid=hybrid)
     print(json.dumps(result), flush=True)
 
 

@@ -20,6 +20,10 @@
 //  - points whose ball holds fewer than k_min centres are finished by a
 //    thread-per-point pass that searches a uniform grid over the centres in
 //    rings of cells for the k_min nearest, with the falloff and its gradient.
+//    Beyond D = r + 7 max(r, 1e-6) the falloff is below 2^-212, so a
+//    single-precision weight is exactly zero there whatever the Gaussian: the
+//    search only looks within D (cells of edge just over D/2, two rings), and
+//    nearest centres beyond D, which would add exact zeros, are left out.
 #include <rocprim/device/device_scan.hpp>
 
 #include "pointgrid.h"
@@ -155,20 +159,22 @@ __global__ void __launch_bounds__(kHWaves * 64) hybrid_fwd_kernel(
 // ---------------------------------------------------------------------------
 // Nearest centres (top-up): rings of centre-grid cells around the point's
 // cell until the k-th best squared distance is below the distance to every
-// unvisited cell.  bd/bi hold the k_min nearest in (d2, index) order; unused
-// slots keep index 0x7fffffff.
+// unvisited cell, or until every cell within the reach has been visited.
+// bd/bi hold the k nearest within squared distance reach2 in (d2, index)
+// order; unused slots keep index 0x7fffffff.
 // ---------------------------------------------------------------------------
 template <int K>
 __device__ void nearest_centres(float px, float py, float pz, const PGrid& cg,
                                 const int* __restrict__ cstart, const int* __restrict__ csorted,
-                                const PrimRec* __restrict__ recs, int k, float bd[K], int bi[K]) {
+                                const PrimRec* __restrict__ recs, int k, float reach2, int max_rings,
+                                float bd[K], int bi[K]) {
 #pragma unroll
   for (int a = 0; a < K; ++a) {
     bd[a] = INFINITY;
     bi[a] = 0x7fffffff;
   }
   const int3 c = pcell(cg, px, py, pz);
-  const int maxr = max(cg.dx, max(cg.dy, cg.dz));
+  const int maxr = min(max_rings, max(cg.dx, max(cg.dy, cg.dz)));
   for (int rr = 0; rr <= maxr; ++rr) {
     for (int zc = c.z - rr; zc <= c.z + rr; ++zc) {
       if (zc < 0 || zc >= cg.dz) continue;
@@ -182,7 +188,7 @@ __device__ void nearest_centres(float px, float py, float pz, const PGrid& cg,
             const int j = csorted[s];
             const float4 m = recs[j].r0;
             const float d = sq_len(px - m.x, py - m.y, pz - m.z);
-            if (!nearer(d, j, bd[K - 1], bi[K - 1])) continue;
+            if (d > reach2 || !nearer(d, j, bd[K - 1], bi[K - 1])) continue;
             bd[K - 1] = d;
             bi[K - 1] = j;
 #pragma unroll
@@ -230,13 +236,14 @@ template <int K>
 __global__ void __launch_bounds__(256) hybrid_topup_fwd_kernel(
     const float* __restrict__ x, int64_t q, PGrid cg, const int* __restrict__ cstart,
     const int* __restrict__ csorted, const PrimRec* __restrict__ recs, int k_min, float rb,
-    float eps, float* __restrict__ L, float* __restrict__ Zout, const int* __restrict__ count) {
+    float reach2, int max_rings, float eps, float* __restrict__ L, float* __restrict__ Zout,
+    const int* __restrict__ count) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= q || count[i] >= k_min) return;
   const float px = x[i * 3], py = x[i * 3 + 1], pz = x[i * 3 + 2];
   float bd[K];
   int bi[K];
-  nearest_centres<K>(px, py, pz, cg, cstart, csorted, recs, k_min, bd, bi);
+  nearest_centres<K>(px, py, pz, cg, cstart, csorted, recs, k_min, reach2, max_rings, bd, bi);
   float s0 = 0.f, s1 = 0.f, s2 = 0.f, z = 0.f;
 #pragma unroll
   for (int a = 0; a < K; ++a) {
@@ -427,8 +434,9 @@ template <int K>
 __global__ void __launch_bounds__(256) hybrid_topup_bwd_kernel(
     const float* __restrict__ x, int64_t q, PGrid cg, const int* __restrict__ cstart,
     const int* __restrict__ csorted, const PrimRec* __restrict__ recs, int k_min, float rb,
-    float eps, const float* __restrict__ Lf, const float* __restrict__ Zf,
-    const int* __restrict__ count, const float* __restrict__ dL, float* __restrict__ grad_rows) {
+    float reach2, int max_rings, float eps, const float* __restrict__ Lf,
+    const float* __restrict__ Zf, const int* __restrict__ count, const float* __restrict__ dL,
+    float* __restrict__ grad_rows) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= q || count[i] >= k_min) return;
   const float px = x[i * 3], py = x[i * 3 + 1], pz = x[i * 3 + 2];
@@ -438,7 +446,7 @@ __global__ void __launch_bounds__(256) hybrid_topup_bwd_kernel(
   const float gl = z >= eps ? g0 * Lf[i * 3] + g1 * Lf[i * 3 + 1] + g2 * Lf[i * 3 + 2] : 0.f;
   float bd[K];
   int bi[K];
-  nearest_centres<K>(px, py, pz, cg, cstart, csorted, recs, k_min, bd, bi);
+  nearest_centres<K>(px, py, pz, cg, cstart, csorted, recs, k_min, reach2, max_rings, bd, bi);
   const float slope = 6.f / fmaxf(rb, 1e-6f);
 #pragma unroll
   for (int a = 0; a < K; ++a) {
@@ -469,6 +477,20 @@ __global__ void __launch_bounds__(256) hybrid_topup_bwd_kernel(
   }
 }
 
+// Distance beyond which a single-precision weight is exactly zero (falloff
+// below 2^-212), and the rings of centre-grid cells that cover it.
+double topup_reach(float rb) { return (double)rb + 7.0 * std::fmax((double)rb, 1e-6); }
+// Cells have edge at least (1 + 1e-4) D / 2, so a centre within D of a point
+// lies at most ceil(D / h) cells away along each axis, with room for the
+// single-precision rounding of cell indices.
+int topup_rings(const gpf_grid* g) {
+  return (int)std::ceil(topup_reach(g->ball) / (double)g->cg_h);
+}
+float topup_reach2(float rb) {
+  const double d = topup_reach(rb);
+  return (float)(d * d * (1.0 + 1e-6));
+}
+
 PGrid centre_geom(const gpf_grid* g) {
   return PGrid{g->cg_origin[0], g->cg_origin[1], g->cg_origin[2], g->cg_h,
                g->cg_dims[0],   g->cg_dims[1],   g->cg_dims[2]};
@@ -490,9 +512,9 @@ void free_centre_grid(gpf_grid* g) {
   g->cg_bytes = 0;
 }
 
-// Uniform grid over the Gaussian centres (about one per cell in the centres'
-// box, at most kCentreDim per axis), rebuilt with the field.  Reads back the
-// centres' box once.
+// Uniform grid over the Gaussian centres (cells of edge just over half the
+// top-up reach, at most kCentreDim per axis), rebuilt with the field.  Reads back
+// the centres' box once.
 gpf_status build_centre_grid(gpf_grid* g, hipStream_t s) {
   const int64_t n = g->n;
   if (!g->cg_box) {
@@ -504,7 +526,8 @@ gpf_status build_centre_grid(gpf_grid* g, hipStream_t s) {
   GPF_HIP(hipMemcpyAsync(hp, g->cg_box, sizeof(hp), hipMemcpyDeviceToHost, s));
   GPF_HIP(hipStreamSynchronize(s));
   PGrid pg;
-  gpf_status st = point_grid_geometry(hp, n, kCentreDim, &pg);
+  gpf_status st =
+      point_grid_geometry(hp, n, kCentreDim, &pg, 0.5 * (1.0 + 1e-4) * topup_reach(g->ball));
   if (st != GPF_OK) return st;
   const int64_t cells = (int64_t)pg.dx * pg.dy * pg.dz;
   if (g->cg_cells_cap < cells || g->cg_n_cap < n) {
@@ -556,7 +579,7 @@ gpf_status launch_hybrid_fwd(const gpf_grid* g, float eps, float* L, float* Z, i
   const unsigned blocks = (unsigned)((qs->q + 255) / 256);
   hipLaunchKernelGGL(hybrid_topup_fwd_kernel<kTopUpMax>, dim3(blocks), dim3(256), 0, s,
                      qs->x_user, qs->q, centre_geom(g), g->cg_start, g->cg_sorted, g->rec,
-                     g->k_min, g->ball, eps, L, Z, count);
+                     g->k_min, g->ball, topup_reach2(g->ball), topup_rings(g), eps, L, Z, count);
   GPF_HIP(hipGetLastError());
   return GPF_OK;
 }
@@ -577,7 +600,8 @@ gpf_status launch_hybrid_bwd(const gpf_grid* gc, float eps, const float* L, cons
   const unsigned blocks = (unsigned)((qs->q + 255) / 256);
   hipLaunchKernelGGL(hybrid_topup_bwd_kernel<kTopUpMax>, dim3(blocks), dim3(256), 0, s,
                      qs->x_user, qs->q, centre_geom(g), g->cg_start, g->cg_sorted, g->rec,
-                     g->k_min, g->ball, eps, L, Z, count, dL, (float*)g->grad_rows);
+                     g->k_min, g->ball, topup_reach2(g->ball), topup_rings(g), eps, L, Z, count, dL,
+                     (float*)g->grad_rows);
   GPF_HIP(hipGetLastError());
   return launch_grad_finalize(g, grad, s);
 }

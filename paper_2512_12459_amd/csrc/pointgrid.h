@@ -88,9 +88,10 @@ __device__ __forceinline__ bool before(float da, int ia, float db, int ib) {
 constexpr int kPointBoxBlocks = 64;  // blocks of pbox_kernel (partial boxes)
 
 // Geometry of a point grid from the partial boxes pbox_kernel wrote: cubic
-// cells holding about one point each in the box's volume, at most maxdim per
-// axis.  Fails on non-finite coordinates.
-inline gpf_status point_grid_geometry(const float* hp, int64_t n, int maxdim, PGrid* g) {
+// cells holding about one point each in the box's volume (or of edge `cell`
+// when cell > 0), at most maxdim per axis.  Fails on non-finite coordinates.
+inline gpf_status point_grid_geometry(const float* hp, int64_t n, int maxdim, PGrid* g,
+                                      double cell = 0.0) {
   float lo[3], hi[3];
   for (int a = 0; a < 3; ++a) {
     lo[a] = hp[a];
@@ -106,7 +107,7 @@ inline gpf_status point_grid_geometry(const float* hp, int64_t n, int maxdim, PG
   for (int a = 0; a < 3; ++a) ext = std::fmax(ext, (double)hi[a] - lo[a]);
   double vol = 1;
   for (int a = 0; a < 3; ++a) vol *= std::fmax((double)hi[a] - lo[a], ext * 1e-3 + 1e-12);
-  double h = std::cbrt(vol / (double)n);
+  double h = cell > 0.0 ? cell : std::cbrt(vol / (double)n);
   h = std::fmax(h, ext / maxdim + 1e-12);
   *g = PGrid{lo[0], lo[1], lo[2], (float)h, 1, 1, 1};
   int* dims[3] = {&g->dx, &g->dy, &g->dz};

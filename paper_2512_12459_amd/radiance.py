@@ -193,7 +193,8 @@ def eval_hybrid(grid: HybridGrid, mu, quat, log_scale, rgb):
     L = torch.empty((q, 3), device=x.device, dtype=torch.float32)
     Z = torch.empty(q, device=x.device, dtype=torch.float32)
     count = torch.empty(q, device=x.device, dtype=torch.int32)
-    C.check(C.lib().gpf_eval_hybrid(grid.handle, ctypes.byref(fs), C.ptr(x), q, grid.eps,
+    eps = getattr(grid, "eps", 1e-6)   # a truncated grid is refused by the library
+    C.check(C.lib().gpf_eval_hybrid(grid.handle, ctypes.byref(fs), C.ptr(x), q, eps,
                                     C.ptr(L), C.ptr(Z), C.ptr(count), _stream()))
     return L, Z, count
 
@@ -214,7 +215,8 @@ def eval_hybrid_backward(grid: HybridGrid, mu, quat, log_scale, rgb, L, Z, count
     gs = C.FieldGrad(C.ptr(grads["mu"]), C.ptr(grads["quat"]), C.ptr(grads["log_scale"]),
                      C.ptr(grads["rgb"]))
     C.check(C.lib().gpf_eval_hybrid_backward(grid.handle, ctypes.byref(fs), C.ptr(x), x.shape[0],
-                                             grid.eps, C.ptr(L), C.ptr(Z), C.ptr(count), C.ptr(dL),
+                                             getattr(grid, "eps", 1e-6), C.ptr(L), C.ptr(Z),
+                                             C.ptr(count), C.ptr(dL),
                                              ctypes.byref(gs), _stream()))
     return grads
 

@@ -183,3 +183,35 @@ def test_stress4m_full_size_forward(R):
     ref = E.radiance(*f.arrays(), x[sel])
     check_forward(L.cpu().numpy()[sel], ref)
     assert ref["count"].mean() > 1000
+
+
+def test_caustic1m_hybrid_query_full_size(R):
+    """The hybrid query (ball r = 0.02, top-up to 3 nearest, falloff,
+    normalised) on the 1M-Gaussian caustic field at 32 x 800x800: ball counts
+    and L, Z on 20,000 sampled points; the full backward with the upstream
+    gradient nonzero on 20,000 sampled points, against the oracle's gradient
+    of every Gaussian."""
+    from oracle import hybrid_oracle as H
+    from oracle.tolerances import check_hybrid_forward
+    f, x = S.workload("caustic1m")
+    q = x.shape[0]
+    say(f"case: caustic1m hybrid, n={f.n} q={q}")
+    dev = [torch.from_numpy(a).cuda() for a in f.arrays()]
+    qs = R.QuerySet(torch.from_numpy(x).cuda(), CELL)
+    g = R.HybridGrid(qs, 0.02, 3).build(*dev)
+    L, Z, cnt = R.eval_hybrid(g, *dev)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(30)
+    sel = np.sort(rng.choice(q, 20000, replace=False))
+    sets, counts = H.select_tree(f.mu, x[sel], 0.02, 3)
+    ref = H.radiance(*f.arrays(), x[sel], 0.02, 3, sets=sets, counts=counts)
+    check_hybrid_forward(L.cpu().numpy()[sel], Z.cpu().numpy()[sel], cnt.cpu().numpy()[sel], ref)
+    assert (counts < 3).any() and (counts >= 3).any()
+    dL = np.zeros((q, 3), np.float32)
+    dL[sel] = rng.normal(size=(len(sel), 3))
+    say("case: caustic1m hybrid backward, 20000 points carry the upstream gradient")
+    grads = R.eval_hybrid_backward(g, *dev, L, Z, cnt, torch.from_numpy(dL).cuda())
+    torch.cuda.synchronize()
+    gg = {k: v.cpu().numpy() for k, v in grads.items()}
+    gref = H.radiance_backward(*f.arrays(), x[sel], dL[sel], 0.02, 3, sets=sets)
+    check_grads(gg, gref)
