@@ -40,20 +40,26 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def measured_traffic(kernel: str, workload: str, default_shape: bool):
+def measured_traffic(kernel: str, workload: str, default_shape: bool, hybrid: bool = False):
     """HBM bytes per launch of `kernel` from the committed counter summary
     (FETCH_SIZE and WRITE_SIZE, each scaled by what the counter reads for a
     plain copy of known size), or None when the summary was taken on another
-    workload or on a different kernel source."""
+    workload or on different kernel sources."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "counters_caustic1m.json")
+    name = "counters_hybrid_caustic1m.json" if hybrid else "counters_caustic1m.json"
+    path = os.path.join(ROOT, "profiles", name)
     if workload != "caustic1m" or not default_shape or not os.path.exists(path):
         return None
     with open(path) as fh:
         rec = json.load(fh)
-    with open(os.path.join(ROOT, rec["source"]), "rb") as fh:
-        if hashlib.sha256(fh.read()).hexdigest() != rec["source_sha256"]:
-            return None
+    if "sources" not in rec:
+        return None
+    h = hashlib.sha256()
+    for src in rec["sources"]:
+        with open(os.path.join(ROOT, src), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != rec["sources_sha256"]:
+        return None
     k = rec["kernels"].get(kernel)
     return None if k is None else float(k["hbm_bytes"])
 
@@ -273,8 +279,10 @@ def main():
                      "achieved": achieved / 1e12,
                      "peak": PEAK_FP32_VALU / 1e12, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_VALU,
-                     "traffic": None if hybrid else measured_traffic(f"eval_{dom}_kernel", args.workload,
-                                                 not (args.views or args.res) and args.cell == 0.025),
+                     "traffic": measured_traffic(f"{'hybrid' if hybrid else 'eval'}_{dom}_kernel",
+                                                 args.workload,
+                                                 not (args.views or args.res) and args.cell == 0.025
+                                                 and (not hybrid or args.radius == 0.02), hybrid),
                      "traffic_unit": "bytes per launch",
                      "measured_valu_ceiling": valu_tflops,
                      "frac_of_measured_ceiling": achieved / 1e12 / valu_tflops,
