@@ -35,12 +35,12 @@ def log(*a):
 
 
 def compare(net, workload="caustic1m", gt_seed=7, views=32, res=800, target_psnr=35.0,
-            max_steps=1500, check_every=10, cell=0.025, lr=None):
+            max_steps=1500, check_every=10, cell=0.025, lr=None, query="truncated"):
     gt, x = S.workload(workload, views=views, res=res, seed=gt_seed)
     pos, power = S.photons_from_field(gt, gt_seed + 1)
     dev = "cuda"
     qs = R.QuerySet(torch.from_numpy(x).to(dev), cell)
-    T = LI.render(qs, gt.arrays())
+    T = LI.render(qs, gt.arrays(), query=query)
     pd = torch.from_numpy(pos).to(dev)
     wd = torch.from_numpy(power).to(dev)
     out = {}
@@ -50,9 +50,13 @@ def compare(net, workload="caustic1m", gt_seed=7, views=32, res=800, target_psnr
         f = Field(*PH.init_from_photons(pd, wd, k=16, mlp=mlp))
         torch.cuda.synchronize()
         t_init = time.perf_counter() - t0
-        fitter = Fitter(f, qs, T, lr=lr)
+        fitter = Fitter(f, qs, T, lr=lr, query=query)
         p0 = fitter.current_psnr()
-        pairs0 = fitter.grid.build(*f.arrays()).count_pairs()
+        if query == "hybrid":
+            c = fitter.count.to(torch.int64)
+            pairs0 = int(torch.where(c >= 3, c, torch.full_like(c, min(3, f.n))).sum().item())
+        else:
+            pairs0 = fitter.grid.build(*f.arrays()).count_pairs()
         res_ = fitter.run(max_steps, target_psnr, check_every, log=lambda s: log(f"[{name}] {s}"))
         hist = res_["history"]
         # first check at or above each level (checks every `check_every` steps)
@@ -66,7 +70,8 @@ def compare(net, workload="caustic1m", gt_seed=7, views=32, res=800, target_psnr
                          ms_per_step=res_["seconds"] / hist[-1][0] * 1e3,
                          init_pairs_per_query=pairs0 / x.shape[0], levels=levels, history=hist)
         log(f"{name}: init {p0:.2f} dB, reached {res_['reached']}, final {out[name]['final_psnr']:.2f} dB")
-    return dict(workload=workload, n=gt.n, q=int(x.shape[0]), target_psnr=target_psnr, runs=out)
+    return dict(workload=workload, query=query, n=gt.n, q=int(x.shape[0]), target_psnr=target_psnr,
+                runs=out)
 
 
 def main():
@@ -83,6 +88,9 @@ def main():
     ap.add_argument("--target", type=float, default=35.0)
     ap.add_argument("--max-steps", type=int, default=1500)
     ap.add_argument("--weights", default=None, help="load trained parameters (.npy) instead of training")
+    ap.add_argument("--query", choices=("truncated", "hybrid"), default="truncated",
+                    help="query used for the targets and both fits (the training data always "
+                         "uses the truncated fits)")
     ap.add_argument("--save-weights", default=None)
     a = ap.parse_args()
     torch.cuda.set_device(0)
@@ -104,7 +112,7 @@ def main():
         if a.save_weights:
             LI.save(net, a.save_weights)
     res = compare(net, a.workload, views=a.views, res=a.res, target_psnr=a.target,
-                  max_steps=a.max_steps)
+                  max_steps=a.max_steps, query=a.query)
     res["training"] = train_info
     print(json.dumps(res))
 

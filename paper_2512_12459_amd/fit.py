@@ -61,30 +61,46 @@ def psnr_from_mse(mse: float, peak: float) -> float:
 
 
 class Fitter:
-    """Fits ``field`` to targets T [q,3] at the points of ``queries``."""
+    """Fits ``field`` to targets T [q,3] at the points of ``queries``, with the
+    truncated query (3-sigma, un-normalised) or, with ``query="hybrid"``, the
+    paper's hybrid query (ball of radius ``r``, top-up to ``k_min`` nearest,
+    falloff, normalised)."""
 
     def __init__(self, field: Field, queries: R.QuerySet, T: torch.Tensor, lr=None,
-                 cutoff: float = 3.0):
+                 cutoff: float = 3.0, query: str = "truncated", r: float = 0.02, k_min: int = 3):
         self.f = field
         self.qs = queries
         self.T = T
         self.q = T.shape[0]
         self.lr = dict(DEFAULT_LR if lr is None else lr)
-        self.grid = R.Grid(queries, cutoff)
+        if query not in ("truncated", "hybrid"):
+            raise ValueError(f"unknown query {query!r}")
+        self.hybrid = query == "hybrid"
+        self.grid = R.HybridGrid(queries, r, k_min) if self.hybrid else R.Grid(queries, cutoff)
         self.L = torch.empty_like(T)
         self.dL = torch.empty_like(T)
         self.loss = torch.zeros(1, dtype=torch.float64, device=T.device)
         self.t = 0
         self.peak = float(T.max().item())
 
-    def step(self):
+    def _forward(self):
         f = self.f
         self.grid.build(*f.arrays())
-        R.eval_radiance(self.grid, *f.arrays(), out=self.L)
+        if self.hybrid:
+            self.L, self.Z, self.count = R.eval_hybrid(self.grid, *f.arrays())
+        else:
+            R.eval_radiance(self.grid, *f.arrays(), out=self.L)
         self.loss.zero_()
         R.mse_loss(self.L, self.T, dL=self.dL, loss_sum=self.loss)
+
+    def step(self):
+        f = self.f
+        self._forward()
         f.G.zero_()
-        R.eval_radiance_backward(self.grid, *f.arrays(), self.dL, f.g)
+        if self.hybrid:
+            R.eval_hybrid_backward(self.grid, *f.arrays(), self.L, self.Z, self.count, self.dL, f.g)
+        else:
+            R.eval_radiance_backward(self.grid, *f.arrays(), self.dL, f.g)
         self.t += 1
         for k, _ in Field.GROUPS:
             R.adam_step(f.p[k], f.g[k], f.m[k], f.v[k], self.t, self.lr[k])
@@ -95,10 +111,7 @@ class Fitter:
 
     def current_psnr(self) -> float:
         """PSNR of the current parameters (one extra forward)."""
-        self.grid.build(*self.f.arrays())
-        R.eval_radiance(self.grid, *self.f.arrays(), out=self.L)
-        self.loss.zero_()
-        R.mse_loss(self.L, self.T, dL=self.dL, loss_sum=self.loss)
+        self._forward()
         return psnr_from_mse(self.mse(), self.peak)
 
     def run(self, max_steps: int, target_psnr: float | None = None, check_every: int = 10,

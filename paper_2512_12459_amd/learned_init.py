@@ -35,11 +35,16 @@ def default_params(seed: int = 0) -> np.ndarray:
     return np.concatenate(parts).astype(np.float32)
 
 
-def render(qs: R.QuerySet, field_arrays, device="cuda") -> torch.Tensor:
-    """Radiance of a field at the query set's points (library forward)."""
+def render(qs: R.QuerySet, field_arrays, device="cuda", query: str = "truncated") -> torch.Tensor:
+    """Radiance of a field at the query set's points (library forward, with
+    the truncated or the hybrid query)."""
     t = [torch.as_tensor(a).to(device).contiguous() for a in field_arrays]
-    g = R.Grid(qs).build(*t)
-    L = R.eval_radiance(g, *t)
+    if query == "hybrid":
+        g = R.HybridGrid(qs).build(*t)
+        L = R.eval_hybrid(g, *t)[0]
+    else:
+        g = R.Grid(qs).build(*t)
+        L = R.eval_radiance(g, *t)
     torch.cuda.synchronize()
     g.close()
     return L

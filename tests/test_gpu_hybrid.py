@@ -186,3 +186,23 @@ def test_mode_errors(rad):
         with pytest.raises(GPFError) as e:
             rad.HybridGrid(qs, r, k).build(*dev)
         assert e.value.status == 1
+
+
+def test_fitting_with_the_hybrid_query_raises_psnr(rad):
+    """The fitting loop with the hybrid query: targets from a ground-truth
+    field, a perturbed start, Adam over the library's backward; PSNR rises."""
+    from paper_2512_12459_amd.fit import Field, Fitter
+    gt, x = S.workload("plain4k")
+    start = S.perturb_field(gt, 2)
+    (xd,) = to_dev(x)
+    qs = rad.QuerySet(xd, 0.025)
+    gdev = to_dev(*gt.arrays())
+    T = rad.eval_hybrid(rad.HybridGrid(qs).build(*gdev), *gdev)[0]
+    f = Field(*start.arrays())
+    fit = Fitter(f, qs, T, query="hybrid")
+    p0 = fit.current_psnr()
+    say(f"case: hybrid fitting, start {p0:.2f} dB")
+    res = fit.run(60, check_every=20)
+    p1 = res["history"][-1][1]
+    say(f"after 60 steps {p1:.2f} dB")
+    assert p1 > p0 + 3.0
