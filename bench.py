@@ -8,6 +8,11 @@ Default workload: 1,000,000 Gaussians (20% in one caustic cluster under the
 sphere, the rest on the five walls), 32 views at 800x800 = 20,480,000 query
 points, FP32.  Targets are the radiance of a second field (seed 1) rendered
 once before timing.  Prints one JSON line.
+
+``--workload sppm`` instead times one progressive photon-mapping iteration per
+step: trace 100,000 photon paths, compact the stored photons, bin them, and
+gather the density estimate (r = 0.02) at the diffuse first hits of the same
+32 ring views at 800x800.
 """
 from __future__ import annotations
 
@@ -34,6 +39,9 @@ FLOPS_BWD = 64
 FLOPS_FWD_HYBRID = 36
 FLOPS_BWD_HYBRID = 60
 PEAK_FP32_VALU = 157.3e12      # published FP32 vector peak
+# Photon density estimate, per gathered (point, photon) pair: squared distance
+# 8 (3 sub, 3 mul, 2 add), power accumulation 3.
+FLOPS_KDE_PAIR = 11
 
 
 def log(*a):
@@ -94,6 +102,121 @@ def cpu_baseline(field, x, sample: int, seed: int = 11, hybrid: bool = False):
                        + ("neighbourhood" if hybrid else "contributing") + f" pairs; {dt:.1f} s wall")
 
 
+def cpu_sppm_baseline(x, xs, n_paths, r, seed, sample: int):
+    """The FP64 oracle's photon tracing (all n_paths paths) and density
+    estimate at a bounded random sample of the points, single process."""
+    import numpy as np
+
+    from oracle import photon_oracle as PO
+    rng = np.random.default_rng(seed)
+    sel = np.sort(rng.choice(x.shape[0], min(sample, x.shape[0]), replace=False))
+    t0 = time.perf_counter()
+    pos, pw, surf = PO.stored_photons(PO.trace(n_paths, seed, 8))
+    t1 = time.perf_counter()
+    PO.kde_radiance(x[sel], xs[sel], pos, pw, surf, r)
+    t2 = time.perf_counter()
+    # one iteration over all points: the trace once plus the gather per point
+    per_iter = (t1 - t0) + (t2 - t1) / len(sel) * x.shape[0]
+    return dict(value=x.shape[0] / per_iter, unit="points/s", cores=1, kind="oracle",
+                sample=f"FP64 trace of all {n_paths} paths ({t1 - t0:.1f} s) and the density "
+                       f"estimate at {len(sel)} random points of the same set "
+                       f"({t2 - t1:.1f} s, scaled to {x.shape[0]} points), one process")
+
+
+def bench_sppm(args):
+    """One progressive photon-mapping iteration per step (Sec. 3 photon pass
+    and radiance estimation; Sec. 4.3 reference equation): trace n_paths
+    photon paths, compact the stored photons, bin them, and gather the density
+    estimate at every diffuse first hit of the camera ring."""
+    import numpy as np
+    import torch
+
+    from paper_2512_12459_amd import photons as PH
+    from paper_2512_12459_amd import scenes as S
+
+    torch.cuda.set_device(0)
+    views, res = args.views or 32, args.res or 800
+    t0 = time.perf_counter()
+    x, sid = S.hit_points(S.camera_ring(views, res), return_surface=True)
+    keep = sid <= 4
+    x = np.ascontiguousarray(x[keep])
+    xs = sid[keep].astype(np.int32)
+    q = x.shape[0]
+    log(f"sppm: {q} diffuse points of {views} views at {res}^2 ({time.perf_counter() - t0:.1f} s)")
+    dev = torch.device("cuda:0")
+    xd = torch.from_numpy(x).to(dev)
+    xsd = torch.from_numpy(xs).to(dev)
+    L = torch.zeros((q, 3), device=dev)
+    cnt = torch.empty(q, dtype=torch.int32, device=dev)
+    E = 8
+    n_iter = args.warmup + args.steps          # L ends as the mean estimate over all iterations
+    stream = torch.cuda.current_stream()
+    ev = {k: [] for k in ("trace", "compact", "map", "gather")}
+    info = {}
+
+    def step(t, timed):
+        def mark():
+            e = torch.cuda.Event(enable_timing=True)
+            e.record(stream)
+            return e
+        e0 = mark() if timed else None
+        rec = PH.trace_photons(args.paths, 1000 + t, E, device=dev)
+        e1 = mark() if timed else None
+        ppos, ppw, psurf = PH.compact_photons(*rec)
+        e2 = mark() if timed else None
+        pm = PH.PhotonMap(ppos, ppw, psurf, args.radius)
+        e3 = mark() if timed else None
+        pm.gather(xd, xsd, 1.0 / n_iter, out=L, accumulate=True, count=cnt)
+        e4 = mark() if timed else None
+        info["photons"] = ppos.shape[0]
+        if timed:
+            for k, (a, b) in zip(ev, ((e0, e1), (e1, e2), (e2, e3), (e3, e4))):
+                ev[k].append((a, b))
+        return pm
+
+    for t in range(1, args.warmup + 1):
+        step(t, False).close()
+    torch.cuda.synchronize()
+    maps = []
+    t_start = time.perf_counter()
+    for t in range(args.warmup + 1, args.warmup + args.steps + 1):
+        maps.append(step(t, True))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    for m in maps:
+        m.close()
+    ms = {k: float(np.mean([a.elapsed_time(b) for a, b in v])) for k, v in ev.items()}
+    pairs = int(cnt.to(torch.int64).sum().item())      # gathered pairs of the last iteration
+    step_ms = wall / args.steps * 1e3
+    achieved = pairs * FLOPS_KDE_PAIR / (ms["gather"] * 1e-3)
+    result = {
+        "metric": "progressive photon-mapping iteration: diffuse points estimated per second",
+        "value": q / (step_ms * 1e-3),
+        "unit": "points/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": step_ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"sppm: {args.paths} photon paths (max 8 events) per iteration, "
+                               f"{q} diffuse first hits of {views} ring views at {res}x{res}, "
+                               f"r={args.radius}",
+                   "step": "trace + compact + photon map build + gather"},
+        "kernel_ms": ms,
+        "photons_per_iteration": info["photons"],
+        "pairs": pairs,
+        "pairs_per_point": pairs / q,
+        "paths_per_s": args.paths / (ms["trace"] * 1e-3),
+        "roofline": {"bound": "alu", "kernel": "kde_kernel", "achieved": achieved / 1e12,
+                     "peak": PEAK_FP32_VALU / 1e12, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32_VALU, "traffic": None,
+                     "flops_per_pair": FLOPS_KDE_PAIR},
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        result["cpu_baseline"] = cpu_sppm_baseline(x, xs, args.paths, args.radius, 11,
+                                                   20 * args.cpu_sample)
+    print(json.dumps(result), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -108,7 +231,10 @@ def main():
     ap.add_argument("--query", choices=("truncated", "hybrid"), default="truncated",
                     help="truncated: 3-sigma un-normalised sum; hybrid: the paper's ball + "
                          "nearest-centre neighbourhood with falloff and normalisation")
-    ap.add_argument("--radius", type=float, default=0.02, help="hybrid ball radius r")
+    ap.add_argument("--radius", type=float, default=0.02,
+                    help="hybrid ball radius r; gather radius of the sppm workload")
+    ap.add_argument("--paths", type=int, default=100_000,
+                    help="photon paths per iteration of the sppm workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MB",
                     help="only run a plain device-to-device copy of MB megabytes (5 times), "
@@ -131,6 +257,10 @@ def main():
             a.copy_(b)
         torch.cuda.synchronize()
         print(json.dumps({"calibrate_copy_bytes": nbytes, "copies": 5}))
+        return
+
+    if args.workload == "sppm":
+        bench_sppm(args)
         return
 
     from paper_2512_12459_amd import radiance as R

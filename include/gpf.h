@@ -46,6 +46,7 @@ typedef enum {
 typedef struct gpf_queries gpf_queries; /* binned query points (opaque)       */
 typedef struct gpf_grid gpf_grid;       /* per-field cull structure (opaque)  */
 typedef struct gpf_mlp gpf_mlp;         /* learned initialiser (opaque)       */
+typedef struct gpf_photon_map gpf_photon_map; /* gridded photon map (opaque) */
 
 /* A field of n primitives (1 <= n <= 2^30 - 1): mu[n][3], quat[n][4]
    (w,x,y,z; any non-zero norm, normalised inside), log_scale[n][3] (natural
@@ -161,6 +162,68 @@ gpf_status gpf_eval_hybrid_backward(const gpf_grid *grid, const gpf_field *f, co
                                     int64_t q, float eps, const float *L, const float *Z,
                                     const int *count, const float *dL, gpf_field_grad *grad,
                                     void *stream);
+
+/* ---- photon tracing (Sec. 3 photon pass) and density estimate (Sec. 3
+ * radiance estimation, Sec. 4.3 reference equation) ----------------------
+ * Scene: the box [0,1]^3 with diffuse faces floor y=0 (0), ceiling y=1 (1),
+ * x=0 (2), x=1 (3), back z=0 (4), open at z=1; optionally a glass sphere
+ * (index 1.5, radius 0.2, centre (0.5,0.5,0.5)).  Albedos: white 0.73 for
+ * 0, 1, 4; red (0.63, 0.06, 0.05) for 2; green (0.14, 0.45, 0.09) for 3.
+ * Light: the ceiling square [light_lo, light_hi]^2 in x and z (a point when
+ * equal), cosine distribution downwards, total power (12, 10, 8).
+ *
+ * gpf_trace_photons: n_paths photon paths, each with power (12,10,8)/n_paths
+ * and uniforms from Philox4x64-10 (key (seed, 0), counter (path, event, 0,
+ * 0), word -> (w >> 40) * 2^-24).  Event 0 emits; events 1..max_events
+ * intersect sphere and box: the sphere reflects when u0 < F (exact Fresnel)
+ * and refracts otherwise; a diffuse face stores a photon in slot
+ * [path][event - 1] and continues when u0 < q = max(albedo) with power
+ * * albedo / q in a cosine direction.  Outputs (device, caller-owned, written
+ * whole): pos[n_paths][max_events][3], power[..][3], surface[..] (-1 where
+ * nothing was stored).  1 <= n_paths < 2^31, 1 <= max_events <= 16,
+ * 0 <= light_lo <= light_hi <= 1. */
+gpf_status gpf_trace_photons(int64_t n_paths, uint64_t seed, int max_events, float light_lo,
+                             float light_hi, int sphere, float *pos, float *power, int *surface,
+                             void *stream);
+
+/* Order-preserving compaction of m photon records (surface >= 0 kept):
+ * out_pos[count][3], out_power[count][3], out_surface[count], out_slot[count]
+ * (record index; may be NULL).  *count (host) receives the number kept;
+ * GPF_ERR_CAPACITY when it exceeds `capacity`.  m < 2^31.  Synchronises. */
+gpf_status gpf_compact_photons(const float *pos, const float *power, const int *surface, int64_t m,
+                               float *out_pos, float *out_power, int *out_surface, int64_t *out_slot,
+                               int64_t capacity, int64_t *count, void *stream);
+
+/* Photon map for the density estimate: the photons ppos[np][3],
+ * ppower[np][3], psurface[np] (device; copied, so the caller may free them
+ * afterwards) binned into a uniform grid of cells of edge >= r in cell order.
+ * 1 <= np < 2^31; r > 0 finite; non-finite positions are
+ * GPF_ERR_INVALID_ARGUMENT.  Synchronises.  Release with
+ * gpf_photon_map_destroy. */
+gpf_status gpf_photon_map_build(const float *ppos, const float *ppower, const int *psurface,
+                                int64_t np, float r, void *stream, gpf_photon_map **map);
+void gpf_photon_map_destroy(gpf_photon_map *map);
+
+/* Density estimate (Sec. 3 radiance estimation; the inner sum of the Sec. 4.3
+ * reference equation with a Lambertian BSDF) at q points x[q][3] lying on
+ * faces x_surface[q] (a point on the sphere, or any value outside 0..4, gets
+ * 0): E = albedo / pi / (pi r^2) * sum of the powers of the photons of the
+ * same face within the map's r, membership decided on FP32 squared distances
+ * (dx*dx + dy*dy) + dz*dz without fused multiply-add.  L[q][3] = weight * E,
+ * or L + weight * E when `accumulate` is non-zero (the progressive average of
+ * the reference equation is a sum of such calls with weight 1/N_iter).  When
+ * `count` is not NULL, count[q] (int32) receives the number of photons
+ * gathered at each point.  All arrays are device memory; 1 <= q < 2^31.  One
+ * kernel launch on `stream`; does not synchronise. */
+gpf_status gpf_photon_map_gather(const gpf_photon_map *map, const float *x, const int *x_surface,
+                                 int64_t q, float weight, int accumulate, float *L, int *count,
+                                 void *stream);
+
+/* gpf_photon_map_build + gpf_photon_map_gather + destroy in one call.
+ * Synchronises. */
+gpf_status gpf_photon_density(const float *x, const int *x_surface, int64_t q, const float *ppos,
+                              const float *ppower, const int *psurface, int64_t np, float r,
+                              float weight, int accumulate, float *L, int *count, void *stream);
 
 /* ---- exact pair count (roofline numerator) --------------------------------
  * Writes to *pairs (host) the number of (query, primitive) pairs with

@@ -170,20 +170,35 @@ def fresnel(cos_i, eta_i, eta_t):
     return F, cos_t, sin2_t
 
 
-def trace(n_paths, seed, max_events=10, margin=1e-6, sphere=True, light=(LIGHT_LO, LIGHT_HI)):
+def trace(n_paths, seed, max_events=10, margin=1e-6, sphere=True, light=(LIGHT_LO, LIGHT_HI),
+          paths=None, jitter=0.0, jitter_seed=0):
     """Returns dict(pos [n, E, 3], power [n, E, 3], surface [n, E] (-1 for
     none), ambiguous [n] (first event index whose decision was within the
     margin, E if none)); E = max_events, slot j-1 holds the photon stored at
-    event j."""
+    event j.  `paths` selects a subset of the n_paths path indices (each path
+    depends only on its own index, the seed and n_paths).
+
+    jitter > 0 perturbs the origin and direction of every segment by
+    independent uniform offsets in [-jitter, jitter] per coordinate (direction
+    renormalised): a second run with jitter of the order of single-precision
+    rounding measures how strongly each stored position reacts to such
+    rounding (its conditioning)."""
+    jrng = np.random.default_rng(jitter_seed) if jitter > 0 else None
     E = max_events
-    idx = np.arange(n_paths, dtype=np.uint64)
+    idx = np.arange(n_paths, dtype=np.uint64) if paths is None else np.asarray(paths, np.uint64)
+    power0 = PHI_LIGHT / n_paths
+    n_paths = idx.shape[0]
     u = uniforms(idx, 0, seed)
     lo, hi = light
     o = np.stack([lo + (hi - lo) * u[0], np.ones(n_paths), lo + (hi - lo) * u[1]], 1)
     phi = 2 * math.pi * u[2]
     r = np.sqrt(u[3])
     d = np.stack([r * np.cos(phi), -np.sqrt(1.0 - u[3]), r * np.sin(phi)], 1)
-    power = np.tile(PHI_LIGHT / n_paths, (n_paths, 1))
+    power = np.tile(power0, (n_paths, 1))
+    if jrng is not None:
+        o = o + jitter * jrng.uniform(-1, 1, o.shape)
+        d = d + jitter * jrng.uniform(-1, 1, d.shape)
+        d = d / np.linalg.norm(d, axis=1, keepdims=True)
     alive = np.ones(n_paths, bool)
     pos = np.zeros((n_paths, E, 3))
     pw = np.zeros((n_paths, E, 3))
@@ -238,8 +253,11 @@ def trace(n_paths, seed, max_events=10, margin=1e-6, sphere=True, light=(LIGHT_L
         amb[newly_amb] = j - 1
         power = np.where((store & cont)[:, None], power * alb / q[:, None], power)
         d = np.where(hit_s[:, None], d_s, d_f)
-        d = d / np.linalg.norm(d, axis=1, keepdims=True)
         o = x
+        if jrng is not None:
+            o = o + jitter * jrng.uniform(-1, 1, o.shape)
+            d = d + jitter * jrng.uniform(-1, 1, d.shape)
+        d = d / np.linalg.norm(d, axis=1, keepdims=True)
         alive = alive & ~esc & (hit_s | cont)
     return dict(pos=pos, power=pw, surface=surf, ambiguous=amb)
 
@@ -247,6 +265,36 @@ def trace(n_paths, seed, max_events=10, margin=1e-6, sphere=True, light=(LIGHT_L
 # ----------------------------------------------------------------------------
 # Density estimate
 # ----------------------------------------------------------------------------
+def stored_photons(out):
+    """The stored photons of a trace() result in record order (path, slot):
+    (pos [m, 3], power [m, 3], surface [m])."""
+    keep = out["surface"].reshape(-1) >= 0
+    return (out["pos"].reshape(-1, 3)[keep], out["power"].reshape(-1, 3)[keep],
+            out["surface"].reshape(-1)[keep])
+
+
+def sppm_radii(T, r0, alpha=0.7):
+    """Progressive radii (Sec. 4.3 implementation details): r_1 = r0 and
+    r_{t+1} = r_t sqrt((t + alpha) / (t + 1))."""
+    r = [float(r0)]
+    for t in range(1, T):
+        r.append(r[-1] * math.sqrt((t + alpha) / (t + 1)))
+    return r
+
+
+def sppm_reference(x, x_surface, T, n_paths, seed, r0=0.02, alpha=0.7, max_events=8,
+                   sphere=True, light=(LIGHT_LO, LIGHT_HI)):
+    """Sec. 4.3 reference equation: the mean over T iterations of the density
+    estimate, iteration t tracing a fresh photon map with key seed + t - 1 and
+    gathering within r_t."""
+    acc = np.zeros((np.asarray(x).shape[0], 3))
+    for t, r in enumerate(sppm_radii(T, r0, alpha), start=1):
+        pos, pw, surf = stored_photons(trace(n_paths, seed + t - 1, max_events, sphere=sphere,
+                                             light=light))
+        acc += kde_radiance(x, x_surface, pos, pw, surf, r)
+    return acc / T
+
+
 def kde_radiance(x, x_surface, ppos, ppower, psurface, r):
     """Radiance estimate [q, 3] at points x of the given faces (a point on the
     sphere or outside 0..4 gets 0)."""

@@ -59,6 +59,15 @@ _SIG = {
     "gpf_eval_hybrid_backward": (ctypes.c_int, [_P, ctypes.POINTER(Field), _P, _I64, _F, _P, _P, _P,
                                                 _P, ctypes.POINTER(FieldGrad), _P]),
     "gpf_valu_probe": (ctypes.c_int, [_P, _I64, ctypes.c_int, ctypes.c_int, _P]),
+    "gpf_trace_photons": (ctypes.c_int, [_I64, ctypes.c_uint64, ctypes.c_int, _F, _F, ctypes.c_int,
+                                         _P, _P, _P, _P]),
+    "gpf_compact_photons": (ctypes.c_int, [_P, _P, _P, _I64, _P, _P, _P, _P, _I64,
+                                           ctypes.POINTER(_I64), _P]),
+    "gpf_photon_map_build": (ctypes.c_int, [_P, _P, _P, _I64, _F, _P, ctypes.POINTER(_P)]),
+    "gpf_photon_map_destroy": (None, [_P]),
+    "gpf_photon_map_gather": (ctypes.c_int, [_P, _P, _P, _I64, _F, ctypes.c_int, _P, _P, _P]),
+    "gpf_photon_density": (ctypes.c_int, [_P, _P, _I64, _P, _P, _P, _I64, _F, _F, ctypes.c_int,
+                                            _P, _P, _P]),
     "gpf_mse_loss": (ctypes.c_int, [_P, _P, _I64, _P, _P, _P]),
     "gpf_adam_step": (ctypes.c_int, [_P, _P, _P, _P, _I64, _F, _F, _F, _F, _I64, _P]),
     "gpf_photon_knn": (ctypes.c_int, [_P, _I64, ctypes.c_int, _P, _P, _P]),

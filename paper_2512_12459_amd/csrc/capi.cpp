@@ -306,6 +306,72 @@ gpf_status gpf_count_pairs(const gpf_grid* g, const gpf_field* f, int64_t* pairs
   return st;
 }
 
+gpf_status gpf_trace_photons(int64_t n_paths, uint64_t seed, int max_events, float light_lo,
+                             float light_hi, int sphere, float* pos, float* power, int* surface,
+                             void* stream) {
+  if (n_paths < 1 || n_paths >= ((int64_t)1 << 31))
+    return set_error(GPF_ERR_INVALID_ARGUMENT, "n_paths must lie in [1, 2^31 - 1]");
+  if (max_events < 1 || max_events > 16)
+    return set_error(GPF_ERR_INVALID_ARGUMENT, "max_events must lie in [1, 16]");
+  if (!(light_lo >= 0.f) || !(light_hi <= 1.f) || !(light_lo <= light_hi))
+    return set_error(GPF_ERR_INVALID_ARGUMENT, "light square must satisfy 0 <= lo <= hi <= 1");
+  if (!pos || !power || !surface) return set_error(GPF_ERR_INVALID_ARGUMENT, "NULL output");
+  return launch_trace_photons(n_paths, seed, max_events, light_lo, light_hi, sphere ? 1 : 0, pos,
+                              power, surface, (hipStream_t)stream);
+}
+
+gpf_status gpf_compact_photons(const float* pos, const float* power, const int* surface, int64_t m,
+                               float* out_pos, float* out_power, int* out_surface, int64_t* out_slot,
+                               int64_t capacity, int64_t* count, void* stream) {
+  if (!pos || !power || !surface || !out_pos || !out_power || !out_surface || !count)
+    return set_error(GPF_ERR_INVALID_ARGUMENT, "NULL argument");
+  if (m < 1 || m >= ((int64_t)1 << 31) - 1)
+    return set_error(GPF_ERR_INVALID_ARGUMENT, "m must lie in [1, 2^31 - 2]");
+  if (capacity < 0) return set_error(GPF_ERR_INVALID_ARGUMENT, "capacity must be >= 0");
+  return compact_photons(pos, power, surface, m, out_pos, out_power, out_surface, out_slot,
+                         capacity, count, (hipStream_t)stream);
+}
+
+gpf_status gpf_photon_map_build(const float* ppos, const float* ppower, const int* psurface,
+                                int64_t np, float r, void* stream, gpf_photon_map** map) {
+  if (!ppos || !ppower || !psurface || !map) return set_error(GPF_ERR_INVALID_ARGUMENT, "NULL argument");
+  *map = nullptr;
+  if (np < 1 || np >= ((int64_t)1 << 31))
+    return set_error(GPF_ERR_INVALID_ARGUMENT, "np must lie in [1, 2^31 - 1]");
+  if (!(r > 0.f) || !std::isfinite(r)) return set_error(GPF_ERR_INVALID_ARGUMENT, "r must be positive and finite");
+  return photon_map_build(ppos, ppower, psurface, np, r, map, (hipStream_t)stream);
+}
+
+void gpf_photon_map_destroy(gpf_photon_map* map) { photon_map_free(map); }
+
+gpf_status gpf_photon_map_gather(const gpf_photon_map* map, const float* x, const int* x_surface,
+                                 int64_t q, float weight, int accumulate, float* L, int* count,
+                                 void* stream) {
+  if (!map || !x || !x_surface || !L) return set_error(GPF_ERR_INVALID_ARGUMENT, "NULL argument");
+  if (q < 1 || q >= ((int64_t)1 << 31))
+    return set_error(GPF_ERR_INVALID_ARGUMENT, "q must lie in [1, 2^31 - 1]");
+  if (!std::isfinite(weight)) return set_error(GPF_ERR_INVALID_ARGUMENT, "weight must be finite");
+  return photon_map_gather(map, x, x_surface, q, weight, accumulate != 0, L, count,
+                           (hipStream_t)stream);
+}
+
+gpf_status gpf_photon_density(const float* x, const int* x_surface, int64_t q, const float* ppos,
+                              const float* ppower, const int* psurface, int64_t np, float r,
+                              float weight, int accumulate, float* L, int* count, void* stream) {
+  if (!x || !x_surface || !L) return set_error(GPF_ERR_INVALID_ARGUMENT, "NULL argument");
+  if (q < 1 || q >= ((int64_t)1 << 31))
+    return set_error(GPF_ERR_INVALID_ARGUMENT, "q must lie in [1, 2^31 - 1]");
+  if (!std::isfinite(weight)) return set_error(GPF_ERR_INVALID_ARGUMENT, "weight must be finite");
+  gpf_photon_map* m = nullptr;
+  gpf_status st = gpf_photon_map_build(ppos, ppower, psurface, np, r, stream, &m);
+  if (st != GPF_OK) return st;
+  st = photon_map_gather(m, x, x_surface, q, weight, accumulate != 0, L, count, (hipStream_t)stream);
+  hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+  photon_map_free(m);
+  if (st == GPF_OK && e != hipSuccess) st = hip_fail(e, "density estimate");
+  return st;
+}
+
 gpf_status gpf_valu_probe(float* out, int64_t out_len, int blocks, int iters, void* stream) {
   if (!out) return set_error(GPF_ERR_INVALID_ARGUMENT, "out is NULL");
   if (blocks < 1 || iters < 1) return set_error(GPF_ERR_INVALID_ARGUMENT, "blocks and iters must be >= 1");

@@ -135,6 +135,16 @@ gpf_status launch_hybrid_fwd(const gpf_grid* g, float eps, float* L, float* Z, i
 gpf_status launch_hybrid_bwd(const gpf_grid* g, float eps, const float* L, const float* Z,
                              const int* count, const float* dL, gpf_field_grad* grad,
                              hipStream_t s);
+gpf_status launch_trace_photons(int64_t n, uint64_t seed, int E, float lo, float hi, int sphere,
+                                float* pos, float* pw, int* surf, hipStream_t s);
+gpf_status compact_photons(const float* pos, const float* pw, const int* surf, int64_t m,
+                           float* opos, float* opw, int* osurf, int64_t* oslot, int64_t cap,
+                           int64_t* count, hipStream_t s);
+gpf_status photon_map_build(const float* ppos, const float* ppw, const int* psurf, int64_t np,
+                            float r, gpf_photon_map** out, hipStream_t s);
+gpf_status photon_map_gather(const gpf_photon_map* m, const float* x, const int* xs, int64_t q,
+                             float weight, bool accumulate, float* L, int* count, hipStream_t s);
+void photon_map_free(gpf_photon_map* m);
 gpf_status launch_valu_probe(float* out, int blocks, int iters, hipStream_t s);
 gpf_status launch_mse(const float* L, const float* T, int64_t q, double* loss, float* dL,
                       hipStream_t s);

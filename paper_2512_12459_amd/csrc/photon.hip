@@ -1,0 +1,435 @@
+// Photon tracing (Sec. 3 photon pass: photons traced from the light and
+// stored at every diffuse hit) and the photon density estimate (Sec. 3
+// radiance estimation; Sec. 4.3 reference equation), for the box scene with a
+// glass sphere that the caustic workloads use.
+//
+// Scene: the box [0,1]^3 with diffuse faces floor y=0 (0), ceiling y=1 (1),
+// x=0 (2), x=1 (3), back z=0 (4), the side z=1 open; a glass sphere (index
+// 1.5, radius 0.2, centre (0.5, 0.5, 0.5)).  Lambertian albedos: white
+// (0.73, 0.73, 0.73) for 0, 1, 4, red (0.63, 0.06, 0.05) for 2, green
+// (0.14, 0.45, 0.09) for 3.  Light: a square [lo, hi]^2 of the ceiling
+// emitting a cosine distribution downwards with total power (12, 10, 8).
+//
+// One thread per photon path; uniforms from Philox4x64-10 (Salmon et al.,
+// SC'11), key (seed, 0), counter (path, event, 0, 0), each word mapped to
+// (w >> 40) * 2^-24.  Event 0 emits; events 1..E intersect the sphere and the
+// box (the open side ends the path): the sphere reflects when u0 < F (exact
+// unpolarised Fresnel, total internal reflection F = 1) and refracts
+// otherwise; a face stores (position, power, face) in slot event-1, then
+// continues when u0 < q = max(albedo) with power * albedo / q and a cosine
+// direction about the normal (azimuth 2 pi u1, sin^2 of the polar angle u2).
+#include <rocprim/device/device_scan.hpp>
+
+#include "common.h"
+#include "pointgrid.h"
+
+namespace gpf {
+namespace {
+
+constexpr float kTEps = 1e-4f;
+constexpr float kIor = 1.5f;
+constexpr float kSphR = 0.2f;
+constexpr float kPi = 3.14159265358979323846f;
+constexpr int kPhotonGridDim = 256;
+
+__constant__ float kAlbedo[5][3] = {{0.73f, 0.73f, 0.73f}, {0.73f, 0.73f, 0.73f},
+                                     {0.63f, 0.06f, 0.05f}, {0.14f, 0.45f, 0.09f},
+                                     {0.73f, 0.73f, 0.73f}};
+__constant__ float kNormal[5][3] = {{0, 1, 0}, {0, -1, 0}, {1, 0, 0}, {-1, 0, 0}, {0, 0, 1}};
+__constant__ float kTangT[5][3] = {{0, 0, 1}, {1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {1, 0, 0}};
+__constant__ float kTangB[5][3] = {{1, 0, 0}, {0, 0, 1}, {0, 0, 1}, {0, 1, 0}, {0, 1, 0}};
+
+// Philox4x64-10.
+__device__ __forceinline__ void philox(uint64_t c[4], uint64_t k0, uint64_t k1) {
+  const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += 0x9E3779B97F4A7C15ull;
+      k1 += 0xBB67AE8584CAA73Bull;
+    }
+    const uint64_t hi0 = __umul64hi(M0, c[0]), lo0 = M0 * c[0];
+    const uint64_t hi1 = __umul64hi(M1, c[2]), lo1 = M1 * c[2];
+    const uint64_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0;
+    c[1] = lo1;
+    c[2] = n2;
+    c[3] = lo0;
+  }
+}
+
+__device__ __forceinline__ void uniforms(uint64_t path, uint64_t event, uint64_t seed, float u[4]) {
+  uint64_t c[4] = {path, event, 0ull, 0ull};
+  philox(c, seed, 0ull);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) u[i] = (float)(c[i] >> 40) * (1.0f / 16777216.0f);
+}
+
+__device__ __forceinline__ float dot3(const float a[3], const float b[3]) {
+  return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+
+__global__ void __launch_bounds__(256) trace_kernel(int64_t n, uint64_t seed, int E, float lo,
+                                                    float hi, int sphere, float3 power0,
+                                                    float* __restrict__ pos,
+                                                    float* __restrict__ pw,
+                                                    int* __restrict__ surf) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int j = 0; j < E; ++j) surf[i * E + j] = -1;
+  float u[4];
+  uniforms((uint64_t)i, 0, seed, u);
+  float o[3] = {lo + (hi - lo) * u[0], 1.f, lo + (hi - lo) * u[1]};
+  const float phi = 2.f * kPi * u[2];
+  const float r = sqrtf(u[3]);
+  float d[3] = {r * cosf(phi), -sqrtf(1.f - u[3]), r * sinf(phi)};
+  float p[3] = {power0.x, power0.y, power0.z};
+  const float c[3] = {0.5f, 0.5f, 0.5f};
+  for (int j = 1; j <= E; ++j) {
+    uniforms((uint64_t)i, (uint64_t)j, seed, u);
+    // box: nearest crossing ahead (face 5 = the open side z = 1)
+    float tb = INFINITY;
+    int face = -1;
+    const float tf[6] = {d[1] < 0.f ? (0.f - o[1]) / d[1] : INFINITY,
+                         d[1] > 0.f ? (1.f - o[1]) / d[1] : INFINITY,
+                         d[0] < 0.f ? (0.f - o[0]) / d[0] : INFINITY,
+                         d[0] > 0.f ? (1.f - o[0]) / d[0] : INFINITY,
+                         d[2] < 0.f ? (0.f - o[2]) / d[2] : INFINITY,
+                         d[2] > 0.f ? (1.f - o[2]) / d[2] : INFINITY};
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+      if (tf[k] > kTEps && tf[k] < tb) {
+        tb = tf[k];
+        face = k;
+      }
+    float ts = INFINITY;
+    if (sphere) {
+      const float oc[3] = {o[0] - c[0], o[1] - c[1], o[2] - c[2]};
+      const float b = dot3(oc, d);
+      const float cc = dot3(oc, oc) - kSphR * kSphR;
+      const float disc = b * b - cc;
+      if (disc > 0.f) {
+        const float sq = sqrtf(disc);
+        const float t0 = -b - sq, t1 = -b + sq;
+        ts = t0 > kTEps ? t0 : (t1 > kTEps ? t1 : INFINITY);
+      }
+    }
+    const bool hit_s = ts < tb;
+    if (!hit_s && (face < 0 || face == 5)) break;  // escaped through the open side
+    const float t = hit_s ? ts : tb;
+    const float x[3] = {o[0] + t * d[0], o[1] + t * d[1], o[2] + t * d[2]};
+    if (hit_s) {
+      float ns[3] = {(x[0] - c[0]) / kSphR, (x[1] - c[1]) / kSphR, (x[2] - c[2]) / kSphR};
+      const float cos_o = -dot3(d, ns);
+      const bool inside = cos_o < 0.f;
+      if (inside) ns[0] = -ns[0], ns[1] = -ns[1], ns[2] = -ns[2];
+      const float cos_i = fabsf(cos_o);
+      const float ei = inside ? kIor : 1.f, et = inside ? 1.f : kIor;
+      const float eta = ei / et;
+      const float sin2_t = eta * eta * fmaxf(0.f, 1.f - cos_i * cos_i);
+      float F = 1.f, cos_t = 0.f;
+      if (sin2_t < 1.f) {
+        cos_t = sqrtf(fmaxf(0.f, 1.f - sin2_t));
+        const float rs = (ei * cos_i - et * cos_t) / (ei * cos_i + et * cos_t);
+        const float rp = (ei * cos_t - et * cos_i) / (ei * cos_t + et * cos_i);
+        F = 0.5f * (rs * rs + rp * rp);
+      }
+      float nd[3];
+      if (u[0] < F) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) nd[a] = d[a] + 2.f * cos_i * ns[a];
+      } else {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) nd[a] = eta * d[a] + (eta * cos_i - cos_t) * ns[a];
+      }
+      const float inv = 1.f / sqrtf(dot3(nd, nd));
+#pragma unroll
+      for (int a = 0; a < 3; ++a) d[a] = nd[a] * inv;
+    } else {
+      const int64_t slot = i * E + (j - 1);
+      pos[slot * 3] = x[0];
+      pos[slot * 3 + 1] = x[1];
+      pos[slot * 3 + 2] = x[2];
+      pw[slot * 3] = p[0];
+      pw[slot * 3 + 1] = p[1];
+      pw[slot * 3 + 2] = p[2];
+      surf[slot] = face;
+      const float q = fmaxf(kAlbedo[face][0], fmaxf(kAlbedo[face][1], kAlbedo[face][2]));
+      if (!(u[0] < q)) break;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) p[a] = p[a] * kAlbedo[face][a] / q;
+      const float ph = 2.f * kPi * u[1];
+      const float sr = sqrtf(u[2]), nz = sqrtf(1.f - u[2]);
+      const float ct = sr * cosf(ph), st = sr * sinf(ph);
+      float nd[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) nd[a] = ct * kTangT[face][a] + st * kTangB[face][a] + nz * kNormal[face][a];
+      const float inv = 1.f / sqrtf(dot3(nd, nd));
+#pragma unroll
+      for (int a = 0; a < 3; ++a) d[a] = nd[a] * inv;
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) o[a] = x[a];
+  }
+}
+
+__global__ void __launch_bounds__(256) photon_flags_kernel(const int* __restrict__ surf, int64_t m,
+                                                           int* __restrict__ flags) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < m) flags[i] = surf[i] >= 0 ? 1 : 0;
+  else if (i == m) flags[m] = 0;
+}
+
+__global__ void __launch_bounds__(256) photon_scatter_kernel(
+    const float* __restrict__ pos, const float* __restrict__ pw, const int* __restrict__ surf,
+    int64_t m, const int* __restrict__ off, float* __restrict__ opos, float* __restrict__ opw,
+    int* __restrict__ osurf, int64_t* __restrict__ oslot) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= m || surf[i] < 0) return;
+  const int64_t k = off[i];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    opos[k * 3 + a] = pos[i * 3 + a];
+    opw[k * 3 + a] = pw[i * 3 + a];
+  }
+  osurf[k] = surf[i];
+  if (oslot) oslot[k] = i;
+}
+
+// Photon records gathered into cell order: (x, y, z, face) and (power, 0),
+// so the gather below reads each cell's photons as one contiguous run.
+__global__ void __launch_bounds__(256) photon_gather_kernel(
+    const int* __restrict__ sorted, int64_t np, const float* __restrict__ ppos,
+    const float* __restrict__ ppw, const int* __restrict__ psurf, float4* __restrict__ spos,
+    float4* __restrict__ spw) {
+  const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (s >= np) return;
+  const int64_t j = sorted[s];
+  spos[s] = make_float4(ppos[j * 3], ppos[j * 3 + 1], ppos[j * 3 + 2], __int_as_float(psurf[j]));
+  spw[s] = make_float4(ppw[j * 3], ppw[j * 3 + 1], ppw[j * 3 + 2], 0.f);
+}
+
+// Density estimate at point i on face k: sum over the photons of face k
+// within r (FP32 squared distance in the fixed order), times
+// weight * albedo_k / pi / (pi r^2), stored or added.  Cells have edge >= r,
+// so the 27 cells around the point's cell cover the disc.
+__global__ void __launch_bounds__(256) kde_kernel(const float* __restrict__ x,
+                                                  const int* __restrict__ xs, int64_t q, PGrid g,
+                                                  const int* __restrict__ start,
+                                                  const float4* __restrict__ spos,
+                                                  const float4* __restrict__ spw, float r2,
+                                                  float scale, int accumulate,
+                                                  float* __restrict__ L, int* __restrict__ count) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= q) return;
+  const int k = xs[i];
+  float s0 = 0.f, s1 = 0.f, s2 = 0.f;
+  int cnt = 0;
+  if (k >= 0 && k <= 4) {
+    const float px = x[i * 3], py = x[i * 3 + 1], pz = x[i * 3 + 2];
+    const int3 c = pcell(g, px, py, pz);
+    for (int zc = max(c.z - 1, 0); zc <= min(c.z + 1, g.dz - 1); ++zc)
+      for (int yc = max(c.y - 1, 0); yc <= min(c.y + 1, g.dy - 1); ++yc) {
+        // the x-neighbours of a row are adjacent cells: one contiguous run
+        const int row = (zc * g.dy + yc) * g.dx;
+        const int e = start[row + min(c.x + 1, g.dx - 1) + 1];
+        for (int s = start[row + max(c.x - 1, 0)]; s < e; ++s) {
+          const float4 p = spos[s];
+          if (__float_as_int(p.w) != k) continue;
+          float d2;
+          {
+#pragma clang fp contract(off)
+            const float dx = px - p.x, dy = py - p.y, dz = pz - p.z;
+            d2 = (dx * dx + dy * dy) + dz * dz;
+          }
+          if (d2 <= r2) {
+            const float4 w = spw[s];
+            s0 += w.x;
+            s1 += w.y;
+            s2 += w.z;
+            ++cnt;
+          }
+        }
+      }
+    s0 *= kAlbedo[k][0] * scale;
+    s1 *= kAlbedo[k][1] * scale;
+    s2 *= kAlbedo[k][2] * scale;
+  }
+  if (accumulate) {
+    L[i * 3] += s0;
+    L[i * 3 + 1] += s1;
+    L[i * 3 + 2] += s2;
+  } else {
+    L[i * 3] = s0;
+    L[i * 3 + 1] = s1;
+    L[i * 3 + 2] = s2;
+  }
+  if (count) count[i] = cnt;
+}
+
+}  // namespace
+
+gpf_status launch_trace_photons(int64_t n, uint64_t seed, int E, float lo, float hi, int sphere,
+                                float* pos, float* pw, int* surf, hipStream_t s) {
+  const float3 p0 = make_float3((float)(12.0 / (double)n), (float)(10.0 / (double)n),
+                                (float)(8.0 / (double)n));
+  hipLaunchKernelGGL(trace_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, seed, E,
+                     lo, hi, sphere, p0, pos, pw, surf);
+  GPF_HIP(hipGetLastError());
+  return GPF_OK;
+}
+
+gpf_status compact_photons(const float* pos, const float* pw, const int* surf, int64_t m,
+                           float* opos, float* opw, int* osurf, int64_t* oslot, int64_t cap,
+                           int64_t* count, hipStream_t s) {
+  int *flags = nullptr, *off = nullptr;
+  void* tmp = nullptr;
+  size_t tb = 0;
+  gpf_status st;
+  if ((st = dev_alloc((void**)&flags, (m + 1) * sizeof(int), "photon flags")) != GPF_OK) return st;
+  if ((st = dev_alloc((void**)&off, (m + 1) * sizeof(int), "photon offsets")) != GPF_OK) {
+    dev_free(flags, (m + 1) * sizeof(int));
+    return st;
+  }
+  auto cleanup = [&]() {
+    dev_free(flags, (m + 1) * sizeof(int));
+    dev_free(off, (m + 1) * sizeof(int));
+    dev_free(tmp, tb);
+  };
+  const unsigned blocks = (unsigned)((m + 256) / 256);
+  hipLaunchKernelGGL(photon_flags_kernel, dim3(blocks), dim3(256), 0, s, surf, m, flags);
+  hipError_t e = rocprim::exclusive_scan(nullptr, tb, flags, off, 0, (size_t)(m + 1),
+                                         rocprim::plus<int>(), s);
+  if (e == hipSuccess && (st = dev_alloc(&tmp, tb, "photon scan")) != GPF_OK) {
+    cleanup();
+    return st;
+  }
+  if (e == hipSuccess)
+    e = rocprim::exclusive_scan(tmp, tb, flags, off, 0, (size_t)(m + 1), rocprim::plus<int>(), s);
+  int total = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&total, off + m, sizeof(int), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    cleanup();
+    return hip_fail(e, "photon compaction");
+  }
+  if (total > cap) {
+    cleanup();
+    return set_error(GPF_ERR_CAPACITY, "more stored photons than the output capacity");
+  }
+  hipLaunchKernelGGL(photon_scatter_kernel, dim3(blocks), dim3(256), 0, s, pos, pw, surf, m, off,
+                     opos, opw, osurf, oslot);
+  e = hipGetLastError();
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  cleanup();
+  if (e != hipSuccess) return hip_fail(e, "photon compaction");
+  *count = total;
+  return GPF_OK;
+}
+
+}  // namespace gpf
+
+// Photon map: the stored photons gathered into the cells of a uniform grid of
+// edge >= r (records in cell order), built once and gathered any number of
+// times.
+struct gpf_photon_map {
+  gpf::PGrid g;
+  int64_t np = 0, cells = 0;
+  float r = 0.f;
+  int* start = nullptr;      // [cells + 1] exclusive prefix of photons per cell
+  float4* spos = nullptr;    // [np] (x, y, z, face bits) in cell order
+  float4* spw = nullptr;     // [np] (power, 0) in cell order
+};
+
+namespace gpf {
+
+void photon_map_free(gpf_photon_map* m) {
+  if (!m) return;
+  dev_free(m->start, (m->cells + 1) * 4);
+  dev_free(m->spos, m->np * sizeof(float4));
+  dev_free(m->spw, m->np * sizeof(float4));
+  delete m;
+}
+
+gpf_status photon_map_build(const float* ppos, const float* ppw, const int* psurf, int64_t np,
+                            float r, gpf_photon_map** out, hipStream_t s) {
+  float* part = nullptr;
+  gpf_status st = dev_alloc((void**)&part, kPointBoxBlocks * 6 * sizeof(float), "photon box");
+  if (st != GPF_OK) return st;
+  hipLaunchKernelGGL(pbox_kernel, dim3(kPointBoxBlocks), dim3(256), 0, s, ppos, np, part);
+  float hp[kPointBoxBlocks * 6];
+  hipError_t e = hipMemcpyAsync(hp, part, sizeof(hp), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  dev_free(part, kPointBoxBlocks * 6 * sizeof(float));
+  if (e != hipSuccess) return hip_fail(e, "photon box");
+  auto* m = new gpf_photon_map;
+  m->np = np;
+  m->r = r;
+  if ((st = point_grid_geometry(hp, np, kPhotonGridDim, &m->g, (double)r * (1.0 + 1e-4))) !=
+      GPF_OK) {
+    delete m;
+    return st;
+  }
+  m->cells = (int64_t)m->g.dx * m->g.dy * m->g.dz;
+  const int64_t cells = m->cells;
+  int *cnt = nullptr, *sorted = nullptr;
+  void* tmp = nullptr;
+  size_t tb = 0;
+  auto cleanup = [&]() {
+    dev_free(cnt, (cells + 1) * 4);
+    dev_free(sorted, np * 4);
+    dev_free(tmp, tb);
+  };
+  if ((st = dev_alloc((void**)&m->start, (cells + 1) * 4, "photon cells")) != GPF_OK ||
+      (st = dev_alloc((void**)&m->spos, np * sizeof(float4), "photon records")) != GPF_OK ||
+      (st = dev_alloc((void**)&m->spw, np * sizeof(float4), "photon records")) != GPF_OK ||
+      (st = dev_alloc((void**)&cnt, (cells + 1) * 4, "photon cells")) != GPF_OK ||
+      (st = dev_alloc((void**)&sorted, np * 4, "photon order")) != GPF_OK) {
+    cleanup();
+    photon_map_free(m);
+    return st;
+  }
+  e = hipMemsetAsync(cnt, 0, (cells + 1) * 4, s);
+  const unsigned pb = (unsigned)((np + 255) / 256);
+  hipLaunchKernelGGL(pcount_kernel, dim3(pb), dim3(256), 0, s, ppos, np, m->g, cnt);
+  if (e == hipSuccess)
+    e = rocprim::exclusive_scan(nullptr, tb, cnt, m->start, 0, (size_t)(cells + 1),
+                                rocprim::plus<int>(), s);
+  if (e == hipSuccess && (st = dev_alloc(&tmp, tb, "photon scan")) != GPF_OK) {
+    cleanup();
+    photon_map_free(m);
+    return st;
+  }
+  if (e == hipSuccess)
+    e = rocprim::exclusive_scan(tmp, tb, cnt, m->start, 0, (size_t)(cells + 1),
+                                rocprim::plus<int>(), s);
+  if (e == hipSuccess) e = hipMemsetAsync(cnt, 0, (cells + 1) * 4, s);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(pscatter_kernel, dim3(pb), dim3(256), 0, s, ppos, np, m->g, m->start, cnt,
+                       sorted);
+    hipLaunchKernelGGL(photon_gather_kernel, dim3(pb), dim3(256), 0, s, sorted, np, ppos, ppw,
+                       psurf, m->spos, m->spw);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  cleanup();
+  if (e != hipSuccess) {
+    photon_map_free(m);
+    return hip_fail(e, "photon map");
+  }
+  *out = m;
+  return GPF_OK;
+}
+
+gpf_status photon_map_gather(const gpf_photon_map* m, const float* x, const int* xs, int64_t q,
+                             float weight, bool accumulate, float* L, int* count, hipStream_t s) {
+  const float r = m->r;
+  const float r2 = r * r;
+  const float scale = (float)((double)weight / (M_PI * M_PI * (double)r * (double)r));
+  hipLaunchKernelGGL(kde_kernel, dim3((unsigned)((q + 255) / 256)), dim3(256), 0, s, x, xs, q, m->g,
+                     m->start, m->spos, m->spw, r2, scale, accumulate ? 1 : 0, L, count);
+  GPF_HIP(hipGetLastError());
+  return GPF_OK;
+}
+
+}  // namespace gpf

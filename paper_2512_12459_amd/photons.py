@@ -4,6 +4,7 @@ marshalling only; every step runs in libgpf.so."""
 from __future__ import annotations
 
 import ctypes
+import math
 
 import numpy as np
 import torch
@@ -126,3 +127,160 @@ def mlp_targets(power, d2, mu, quat, log_scale, rgb) -> torch.Tensor:
     C.check(C.lib().gpf_mlp_targets(C.ptr(power), p, C.ptr(d2), d2.shape[1], ctypes.byref(fs),
                                     C.ptr(T), _stream()))
     return T
+
+
+# ----------------------------------------------------------------------------
+# Photon tracing and the photon density estimate (Sec. 3 photon pass and
+# radiance estimation; Sec. 4.3 reference equation)
+# ----------------------------------------------------------------------------
+LIGHT = (0.4, 0.6)
+
+
+def trace_photons(n_paths: int, seed: int, max_events: int = 8, light=LIGHT,
+                  sphere: bool = True, device="cuda"):
+    """Per-path photon records: (pos [n,E,3], power [n,E,3], surface [n,E]
+    int32, -1 where nothing was stored); slot j-1 holds the photon stored at
+    event j of the path."""
+    E = int(max_events)
+    n = int(n_paths)
+    pos = torch.empty((n, E, 3), dtype=torch.float32, device=device)
+    pw = torch.empty((n, E, 3), dtype=torch.float32, device=device)
+    surf = torch.empty((n, E), dtype=torch.int32, device=device)
+    C.check(C.lib().gpf_trace_photons(n, int(seed), E, float(light[0]), float(light[1]),
+                                      1 if sphere else 0, C.ptr(pos), C.ptr(pw), C.ptr(surf),
+                                      _stream()))
+    return pos, pw, surf
+
+
+def compact_photons(pos: torch.Tensor, power: torch.Tensor, surface: torch.Tensor,
+                    capacity: int | None = None, with_slot: bool = False):
+    """The stored photons in record order: (pos [m,3], power [m,3], surface
+    [m] int32[, slot [m] int64 record index])."""
+    m = surface.numel()
+    if pos.numel() != 3 * m or power.numel() != 3 * m:
+        raise ValueError("pos and power must hold 3 floats per record")
+    for t, name in ((pos, "pos"), (power, "power")):
+        if t.dtype != torch.float32 or not t.is_contiguous() or t.device.type != "cuda":
+            raise ValueError(f"{name} must be contiguous float32 on the GPU")
+    if surface.dtype != torch.int32 or not surface.is_contiguous():
+        raise ValueError("surface must be contiguous int32")
+    cap = m if capacity is None else int(capacity)
+    dev = pos.device
+    opos = torch.empty((max(cap, 1), 3), dtype=torch.float32, device=dev)
+    opw = torch.empty((max(cap, 1), 3), dtype=torch.float32, device=dev)
+    osurf = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+    oslot = torch.empty(max(cap, 1), dtype=torch.int64, device=dev) if with_slot else None
+    cnt = ctypes.c_int64()
+    C.check(C.lib().gpf_compact_photons(C.ptr(pos), C.ptr(power), C.ptr(surface), m, C.ptr(opos),
+                                        C.ptr(opw), C.ptr(osurf),
+                                        C.ptr(oslot) if with_slot else None, cap,
+                                        ctypes.byref(cnt), _stream()))
+    k = cnt.value
+    out = (opos[:k], opw[:k], osurf[:k])
+    return out + (oslot[:k],) if with_slot else out
+
+
+def _check_points(x, x_surface, out, accumulate, count):
+    _need(x, "x", 3)
+    q = x.shape[0]
+    if x_surface.dtype != torch.int32 or not x_surface.is_contiguous() or x_surface.numel() != q:
+        raise ValueError("x_surface must be contiguous int32 with one entry per point")
+    if out is None:
+        if accumulate:
+            raise ValueError("accumulate needs an output tensor")
+        out = torch.empty((q, 3), dtype=torch.float32, device=x.device)
+    else:
+        _need(out, "out", 3)
+        if out.shape[0] != q:
+            raise ValueError("out must have one row per point")
+    if count is not None and (count.dtype != torch.int32 or not count.is_contiguous()
+                              or count.numel() != q or count.device != x.device):
+        raise ValueError("count must be contiguous int32 [q] on the points' device")
+    return out
+
+
+def _check_photons(ppos, ppower, psurface):
+    _need(ppos, "ppos", 3)
+    _need(ppower, "ppower", 3)
+    n = ppos.shape[0]
+    if psurface.dtype != torch.int32 or not psurface.is_contiguous() or psurface.numel() != n:
+        raise ValueError("psurface must be contiguous int32 with one entry per photon")
+    if ppower.shape[0] != n:
+        raise ValueError("ppower must have one row per photon")
+
+
+class PhotonMap:
+    """Photons binned for the density estimate at radius r (built once,
+    gathered any number of times; the library keeps its own copy)."""
+
+    def __init__(self, ppos, ppower, psurface, r: float):
+        _check_photons(ppos, ppower, psurface)
+        h = ctypes.c_void_p()
+        C.check(C.lib().gpf_photon_map_build(C.ptr(ppos), C.ptr(ppower), C.ptr(psurface),
+                                             ppos.shape[0], float(r), _stream(), ctypes.byref(h)))
+        self.handle = h
+        self.r = float(r)
+        self.n = ppos.shape[0]
+
+    def gather(self, x, x_surface, weight: float = 1.0, out=None, accumulate: bool = False,
+               count=None):
+        """weight * density estimate at x (added into `out` when accumulate);
+        asynchronous on the current stream."""
+        out = _check_points(x, x_surface, out, accumulate, count)
+        C.check(C.lib().gpf_photon_map_gather(self.handle, C.ptr(x), C.ptr(x_surface), x.shape[0],
+                                              float(weight), 1 if accumulate else 0, C.ptr(out),
+                                              C.ptr(count), _stream()))
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            C.lib().gpf_photon_map_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def photon_density(x: torch.Tensor, x_surface: torch.Tensor, ppos: torch.Tensor,
+                   ppower: torch.Tensor, psurface: torch.Tensor, r: float,
+                   weight: float = 1.0, out: torch.Tensor | None = None,
+                   accumulate: bool = False, count: torch.Tensor | None = None) -> torch.Tensor:
+    """Radiance estimate [q,3] at points x on faces x_surface from the photon
+    map (ppos, ppower, psurface): weight * albedo / pi / (pi r^2) * the power
+    of the same-face photons within r; added into `out` when accumulate.
+    `count` (int32 [q], optional) receives the photons gathered per point."""
+    out = _check_points(x, x_surface, out, accumulate, count)
+    _check_photons(ppos, ppower, psurface)
+    C.check(C.lib().gpf_photon_density(C.ptr(x), C.ptr(x_surface), x.shape[0], C.ptr(ppos),
+                                       C.ptr(ppower), C.ptr(psurface), ppos.shape[0], float(r),
+                                       float(weight), 1 if accumulate else 0, C.ptr(out),
+                                       C.ptr(count), _stream()))
+    return out
+
+
+def sppm_radii(T: int, r0: float, alpha: float = 0.7):
+    """Radius of each progressive iteration: r_1 = r0, r_{t+1} = r_t *
+    sqrt((t + alpha) / (t + 1)) (Sec. 4.3 implementation details)."""
+    r = [float(r0)]
+    for t in range(1, int(T)):
+        r.append(r[-1] * math.sqrt((t + alpha) / (t + 1)))
+    return r
+
+
+def sppm_reference(x: torch.Tensor, x_surface: torch.Tensor, iters: int, n_paths: int,
+                   seed: int, r0: float = 0.02, alpha: float = 0.7, max_events: int = 8,
+                   light=LIGHT, sphere: bool = True) -> torch.Tensor:
+    """Progressive reference radiance (Sec. 4.3 reference equation): the mean
+    over `iters` iterations of the density estimate from a fresh photon map
+    (key seed + t - 1) with the shrinking radius of sppm_radii."""
+    out = torch.zeros((x.shape[0], 3), dtype=torch.float32, device=x.device)
+    for t, r in enumerate(sppm_radii(iters, r0, alpha), start=1):
+        rec = trace_photons(n_paths, seed + t - 1, max_events, light, sphere, x.device)
+        ppos, ppw, psurf = compact_photons(*rec)
+        if ppos.shape[0] == 0:
+            continue
+        photon_density(x, x_surface, ppos, ppw, psurf, r, 1.0 / iters, out, accumulate=True)
+    return out

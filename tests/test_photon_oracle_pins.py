@@ -149,8 +149,53 @@ def test_density_estimate_on_a_photon_lattice():
     assert np.all(L2 == 0)
 
 
+def _rect_view_factor(px, pz, lo, hi, c=1.0):
+    """View factor from a differential floor area at (px, 0, pz) to the
+    parallel square [lo, hi]^2 at height c, by superposing corner rectangles."""
+    def G(a, b):
+        return math.copysign(1, a) * math.copysign(1, b) * _corner_view_factor(abs(a), abs(b), c)
+    x1, x2, z1, z2 = lo - px, hi - px, lo - pz, hi - pz
+    return G(x2, z2) - G(x1, z2) - G(x2, z1) + G(x1, z1)
+
+
+def test_traced_density_matches_direct_irradiance_of_the_light():
+    # without the sphere and with one event, the photons on the floor are the
+    # direct light: a Lambertian square of total power Phi and area A gives
+    # irradiance Phi / A * F at a floor point (F the view factor to the
+    # square), and the density estimate is albedo / pi times that (up to the
+    # photon noise of the disc and a curvature bias far below it)
+    n, r = 1_000_000, 0.05
+    phi = np.array([12.0, 10.0, 8.0])
+    pos, pw, surf = P.stored_photons(P.trace(n, 21, max_events=1, sphere=False))
+    xs = np.array([[0.5, 0.0, 0.5], [0.2, 0.0, 0.7], [0.8, 0.0, 0.15]])
+    L = P.kde_radiance(xs, np.zeros(3, np.int64), pos, pw, surf, r)
+    for i, x in enumerate(xs):
+        expect = 0.73 / math.pi * phi / 0.04 * _rect_view_factor(x[0], x[2], 0.4, 0.6)
+        cnt = np.sum(np.sum((pos - x) ** 2, axis=1) <= r * r)
+        assert cnt > 1000
+        np.testing.assert_allclose(L[i], expect, rtol=5 / math.sqrt(cnt))
+
+
+def test_progressive_radii_follow_the_closed_form():
+    # r_T^2 = r0^2 prod_{t<T} (t + a) / (t + 1) = r0^2 Gamma(T + a) / (Gamma(1 + a) Gamma(T + 1))
+    r0, a = 0.02, 0.7
+    radii = P.sppm_radii(1000, r0, a)
+    for T in (1, 2, 10, 1000):
+        closed = r0 * math.exp(0.5 * (math.lgamma(T + a) - math.lgamma(1 + a) - math.lgamma(T + 1)))
+        assert radii[T - 1] == pytest.approx(closed, rel=1e-12)
+    assert all(b < c for b, c in zip(radii[1:], radii[:-1]))
+
+
+def test_progressive_reference_of_one_iteration_is_one_density_estimate():
+    x = np.array([[0.5, 0.0, 0.5], [0.3, 0.4, 0.0], [0.0, 0.3, 0.6], [0.5, 0.5, 0.3]])
+    xs = np.array([0, 4, 2, 5])
+    ref = P.sppm_reference(x, xs, 1, 20000, 4, r0=0.1, max_events=4)
+    one = P.kde_radiance(x, xs, *P.stored_photons(P.trace(20000, 4, 4)), 0.1)
+    assert np.array_equal(ref, one) and np.all(ref[3] == 0) and np.all(ref[:3] > 0)
+
+
 @pytest.mark.parametrize("mutation", ["fresnel_swap", "wrong_index", "no_cosine", "rr_biased",
-                                      "philox_round"])
+                                      "philox_round", "light_power"])
 def test_planted_mistakes_are_caught(monkeypatch, mutation):
     if mutation == "fresnel_swap":
         orig = P.fresnel
@@ -176,6 +221,10 @@ def test_planted_mistakes_are_caught(monkeypatch, mutation):
         monkeypatch.setattr(P, "ALBEDO", P.ALBEDO * np.float32(1.2))
         with pytest.raises(AssertionError):
             test_russian_roulette_is_unbiased()
+    elif mutation == "light_power":
+        monkeypatch.setattr(P, "PHI_LIGHT", P.PHI_LIGHT * 1.25)
+        with pytest.raises(AssertionError):
+            test_traced_density_matches_direct_irradiance_of_the_light()
     elif mutation == "philox_round":
         orig = P.philox4x64
         monkeypatch.setattr(P, "philox4x64", lambda *a, rounds=10: orig(*a, rounds=9))
