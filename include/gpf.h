@@ -166,8 +166,9 @@ gpf_status gpf_eval_hybrid_backward(const gpf_grid *grid, const gpf_field *f, co
 /* ---- photon tracing (Sec. 3 photon pass) and density estimate (Sec. 3
  * radiance estimation, Sec. 4.3 reference equation) ----------------------
  * Scene: the box [0,1]^3 with diffuse faces floor y=0 (0), ceiling y=1 (1),
- * x=0 (2), x=1 (3), back z=0 (4), open at z=1; optionally a glass sphere
- * (index 1.5, radius 0.2, centre (0.5,0.5,0.5)).  Albedos: white 0.73 for
+ * x=0 (2), x=1 (3), back z=0 (4), open at z=1; a sphere of radius 0.2 at
+ * (0.5,0.5,0.5) chosen by `sphere`: 0 none, 1 glass of index 1.5, 2 a mirror
+ * of reflectance (0.95, 0.64, 0.54).  Albedos: white 0.73 for
  * 0, 1, 4; red (0.63, 0.06, 0.05) for 2; green (0.14, 0.45, 0.09) for 3.
  * Light: the ceiling square [light_lo, light_hi]^2 in x and z (a point when
  * equal), cosine distribution downwards, total power (12, 10, 8).
@@ -175,13 +176,14 @@ gpf_status gpf_eval_hybrid_backward(const gpf_grid *grid, const gpf_field *f, co
  * gpf_trace_photons: n_paths photon paths, each with power (12,10,8)/n_paths
  * and uniforms from Philox4x64-10 (key (seed, 0), counter (path, event, 0,
  * 0), word -> (w >> 40) * 2^-24).  Event 0 emits; events 1..max_events
- * intersect sphere and box: the sphere reflects when u0 < F (exact Fresnel)
- * and refracts otherwise; a diffuse face stores a photon in slot
+ * intersect sphere and box: the glass sphere reflects when u0 < F (exact
+ * Fresnel) and refracts otherwise, the mirror reflects and scales the power
+ * by its reflectance; a diffuse face stores a photon in slot
  * [path][event - 1] and continues when u0 < q = max(albedo) with power
  * * albedo / q in a cosine direction.  Outputs (device, caller-owned, written
  * whole): pos[n_paths][max_events][3], power[..][3], surface[..] (-1 where
  * nothing was stored).  1 <= n_paths < 2^31, 1 <= max_events <= 16,
- * 0 <= light_lo <= light_hi <= 1. */
+ * 0 <= light_lo <= light_hi <= 1, sphere in {0, 1, 2}. */
 gpf_status gpf_trace_photons(int64_t n_paths, uint64_t seed, int max_events, float light_lo,
                              float light_hi, int sphere, float *pos, float *power, int *surface,
                              void *stream);
@@ -224,6 +226,52 @@ gpf_status gpf_photon_map_gather(const gpf_photon_map *map, const float *x, cons
 gpf_status gpf_photon_density(const float *x, const int *x_surface, int64_t q, const float *ppos,
                               const float *ppower, const int *psurface, int64_t np, float r,
                               float weight, int accumulate, float *L, int *count, void *stream);
+
+/* ---- hybrid camera integrator (Sec. 4.2 rendering with the field;
+ * supplementary Alg. S2) ----------------------------------------------------
+ * Pinhole camera: rays from `eye` through the pixel centres of a width x
+ * height image (row 0 at the top) spanning vertical field of view vfov_deg
+ * about the direction to `target`, `up` fixing the roll. */
+typedef struct {
+  float eye[3], target[3], up[3];
+  float vfov_deg;
+  int width, height;
+} gpf_camera;
+
+/* Camera paths in the scene of gpf_trace_photons, `samples` per pixel, path
+ * k = pixel * samples + s.  Each follows the sphere's specular interactions
+ * (glass: reflect when u0 < F, u0 from Philox counter (k, depth, 1, 0) with
+ * key (seed, 0), throughput unchanged; refract otherwise with throughput *=
+ * (eta_i / eta_t)^2; mirror: throughput *= reflectance) for at most
+ * max_depth intersections and ends
+ *  - on a diffuse face: x[k][3] = hit, face[k] = 0..4, beta[k][3] = throughput;
+ *  - on the ceiling inside the light square: Le[k][3] = throughput * the
+ *    light's radiance (12, 10, 8) / (pi * area), face[k] = -1;
+ *  - through the open side or at max_depth: face[k] = -1.
+ * Unused outputs are 0.  Outputs are device arrays of width*height*samples
+ * rows, which must stay below 2^31; 1 <= samples <= 1024, 1 <= max_depth
+ * <= 64, sphere in {0, 1, 2}; 0 <= light_lo <= light_hi <= 1; 0 < vfov_deg <
+ * 180; eye != target and up not parallel to the view direction. */
+gpf_status gpf_camera_trace(const gpf_camera *cam, int samples, uint64_t seed, int max_depth,
+                            float light_lo, float light_hi, int sphere, float *x, float *beta,
+                            int *face, float *Le, void *stream);
+
+/* Pixel radiance L_pix[n_pix][3] = (1/samples) * sum over the pixel's paths
+ * of Le + beta * L(x), from the diffuse hits compacted in path order
+ * (gpf_compact_photons on (x, beta, face) gives them with slot = path index):
+ * slot[m] ascending path indices, beta_c[m][3], and the field's radiance
+ * Lq[m][3] at those hits.  Le[n_pix * samples][3].  Device arrays; m may be
+ * 0.  Does not synchronise. */
+gpf_status gpf_camera_compose(const float *Le, int64_t n_pix, int samples, const int64_t *slot,
+                              const float *beta_c, const float *Lq, int64_t m, float *L_pix,
+                              void *stream);
+
+/* Gradient of a loss with respect to Lq from its gradient dL_pix[n_pix][3]
+ * with respect to the pixels: dLq[k] = beta_c[k] * dL_pix[slot[k] / samples]
+ * / samples (0 for a slot outside the image).  Does not synchronise. */
+gpf_status gpf_camera_compose_backward(const float *dL_pix, int64_t n_pix, int samples,
+                                       const int64_t *slot, const float *beta_c, int64_t m,
+                                       float *dLq, void *stream);
 
 /* ---- exact pair count (roofline numerator) --------------------------------
  * Writes to *pairs (host) the number of (query, primitive) pairs with

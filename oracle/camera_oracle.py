@@ -44,7 +44,7 @@ import numpy as np
 
 from oracle import photon_oracle as P
 
-MIRROR_RHO = np.array([0.95, 0.64, 0.54])
+MIRROR_RHO = P.MIRROR_RHO.astype(np.float64)
 GLASS, MIRROR = 1, 2
 T_EPS = P.T_EPS
 
@@ -68,18 +68,25 @@ def pinhole_rays(eye, target, up, vfov_deg, width, height):
 
 
 def integrate(o, d, samples, seed, max_depth=16, sphere=GLASS, light=(P.LIGHT_LO, P.LIGHT_HI),
-              margin=1e-6):
+              margin=1e-6, jitter=0.0, jitter_seed=0):
     """Camera paths for rays (o, d) [m,3], `samples` per ray.  Returns dict of
     arrays over the m * samples paths: x [.,3], face [.] (0..4 diffuse hit,
     -1 none), beta [.,3] (at the diffuse hit), Le [.,3] (emitted radiance
     times beta, zero unless the path ends on the light), ambiguous [.] (depth
     of the first decision within `margin` of its threshold, max_depth + 1 if
-    none)."""
+    none).  jitter > 0 perturbs every segment's origin and direction by
+    uniform offsets in [-jitter, jitter] per coordinate, to measure each
+    record's sensitivity to rounding."""
+    jrng = np.random.default_rng(jitter_seed) if jitter > 0 else None
     m = o.shape[0]
     n = m * samples
     k = np.arange(n, dtype=np.uint64)
     o = np.repeat(np.asarray(o, np.float64), samples, axis=0)
     d = np.repeat(np.asarray(d, np.float64), samples, axis=0)
+    if jrng is not None:
+        o = o + jitter * jrng.uniform(-1, 1, o.shape)
+        d = d + jitter * jrng.uniform(-1, 1, d.shape)
+        d = d / np.linalg.norm(d, axis=1, keepdims=True)
     beta = np.ones((n, 3))
     x_out = np.zeros((n, 3))
     face_out = np.full(n, -1, np.int64)
@@ -141,8 +148,11 @@ def integrate(o, d, samples, seed, max_depth=16, sphere=GLASS, light=(P.LIGHT_LO
         cont = alive & hit_s
         beta = np.where(cont[:, None], beta_s, beta)
         d = np.where(cont[:, None], d_s, d)
-        d = d / np.linalg.norm(d, axis=1, keepdims=True)
         o = np.where(cont[:, None], x, o)
+        if jrng is not None:
+            o = o + jitter * jrng.uniform(-1, 1, o.shape)
+            d = d + jitter * jrng.uniform(-1, 1, d.shape)
+        d = d / np.linalg.norm(d, axis=1, keepdims=True)
         alive = cont
     return dict(x=x_out, face=face_out, beta=beta_out, Le=le_out, ambiguous=amb)
 

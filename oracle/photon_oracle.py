@@ -28,7 +28,9 @@ uniforms of counter (i, j): the nearest intersection beyond T_EPS among the
 sphere and the box faces (the open side ends the path);
   * sphere: exact unpolarised Fresnel reflectance F of the dielectric
     boundary (total internal reflection gives F = 1); reflect when u0 < F,
-    otherwise refract by Snell's law; the power is unchanged;
+    otherwise refract by Snell's law; the power is unchanged.  With
+    sphere=2 the sphere is instead a mirror that always reflects and scales
+    the power by MIRROR_RHO;
   * face k: store a photon (hit position, current power, k, j); continue with
     probability q = max(albedo_k) when u0 < q, with power * albedo_k / q and a
     cosine-distributed direction about the face normal from u1, u2
@@ -69,6 +71,7 @@ IOR = 1.5
 T_EPS = 1e-4
 LIGHT_LO, LIGHT_HI = 0.4, 0.6
 SPHERE = 5
+MIRROR_RHO = np.array([0.95, 0.64, 0.54], np.float32)
 
 
 # ----------------------------------------------------------------------------
@@ -215,7 +218,7 @@ def trace(n_paths, seed, max_events=10, margin=1e-6, sphere=True, light=(LIGHT_L
             ts, graze = np.full(n_paths, np.inf), np.full(n_paths, np.inf)
         hit_s = ts < tb
         close = (np.abs(ts - tb) < margin * (1 + tb)) | (gap < margin * (1 + tb)) | \
-            (np.isfinite(ts) & (graze < margin)) | (~np.isfinite(ts) & (graze < margin) & sphere)
+            (np.isfinite(ts) & (graze < margin)) | (~np.isfinite(ts) & (graze < margin) & bool(sphere))
         t = np.where(hit_s, ts, tb)
         x = o + t[:, None] * d
         esc = ~hit_s & (face < 0)
@@ -234,6 +237,9 @@ def trace(n_paths, seed, max_events=10, margin=1e-6, sphere=True, light=(LIGHT_L
         d_refr = eta * d + (eta * cos_i[:, None] - cos_t[:, None]) * n_eff
         d_s = np.where(refl[:, None], d_refl, d_refr)
         close_s = (np.abs(uj[0] - F) < margin) | (np.abs(sin2_t - 1.0) < margin)
+        if sphere == 2:
+            d_s = d_refl
+            close_s = np.zeros(n_paths, bool)
         # face events
         fk = np.clip(face, 0, 4)
         store = alive & ~hit_s & ~esc
@@ -252,6 +258,8 @@ def trace(n_paths, seed, max_events=10, margin=1e-6, sphere=True, light=(LIGHT_L
         newly_amb = alive & (amb == E) & (close | (hit_s & close_s))
         amb[newly_amb] = j - 1
         power = np.where((store & cont)[:, None], power * alb / q[:, None], power)
+        if sphere == 2:
+            power = np.where((alive & hit_s)[:, None], power * MIRROR_RHO.astype(F64), power)
         d = np.where(hit_s[:, None], d_s, d_f)
         o = x
         if jrng is not None:

@@ -28,6 +28,12 @@ class Field(ctypes.Structure):
                 ("log_scale", ctypes.c_void_p), ("rgb", ctypes.c_void_p), ("n", ctypes.c_int64)]
 
 
+class Camera(ctypes.Structure):
+    _fields_ = [("eye", ctypes.c_float * 3), ("target", ctypes.c_float * 3),
+                ("up", ctypes.c_float * 3), ("vfov_deg", ctypes.c_float),
+                ("width", ctypes.c_int), ("height", ctypes.c_int)]
+
+
 class FieldGrad(ctypes.Structure):
     _fields_ = [("mu", ctypes.c_void_p), ("quat", ctypes.c_void_p),
                 ("log_scale", ctypes.c_void_p), ("rgb", ctypes.c_void_p)]
@@ -66,6 +72,10 @@ _SIG = {
     "gpf_photon_map_build": (ctypes.c_int, [_P, _P, _P, _I64, _F, _P, ctypes.POINTER(_P)]),
     "gpf_photon_map_destroy": (None, [_P]),
     "gpf_photon_map_gather": (ctypes.c_int, [_P, _P, _P, _I64, _F, ctypes.c_int, _P, _P, _P]),
+    "gpf_camera_trace": (ctypes.c_int, [ctypes.POINTER(Camera), ctypes.c_int, ctypes.c_uint64,
+                                        ctypes.c_int, _F, _F, ctypes.c_int, _P, _P, _P, _P, _P]),
+    "gpf_camera_compose": (ctypes.c_int, [_P, _I64, ctypes.c_int, _P, _P, _P, _I64, _P, _P]),
+    "gpf_camera_compose_backward": (ctypes.c_int, [_P, _I64, ctypes.c_int, _P, _P, _I64, _P, _P]),
     "gpf_photon_density": (ctypes.c_int, [_P, _P, _I64, _P, _P, _P, _I64, _F, _F, ctypes.c_int,
                                             _P, _P, _P]),
     "gpf_mse_loss": (ctypes.c_int, [_P, _P, _I64, _P, _P, _P]),

@@ -18,7 +18,7 @@ LIB = os.path.join(HERE, "libgpf.so")
 ARCH = "gfx950"
 
 SOURCES = ["capi.cpp", "capi_init.cpp", "bin_queries.hip", "grid.hip", "eval.hip", "optim.hip",
-           "mlp.hip", "init.hip", "probe.hip", "hybrid.hip", "photon.hip"]
+           "mlp.hip", "init.hip", "probe.hip", "hybrid.hip", "photon.hip", "camera.hip"]
 
 COMMON = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", f"-I{INCLUDE}", f"-I{CSRC}",

@@ -316,7 +316,8 @@ gpf_status gpf_trace_photons(int64_t n_paths, uint64_t seed, int max_events, flo
   if (!(light_lo >= 0.f) || !(light_hi <= 1.f) || !(light_lo <= light_hi))
     return set_error(GPF_ERR_INVALID_ARGUMENT, "light square must satisfy 0 <= lo <= hi <= 1");
   if (!pos || !power || !surface) return set_error(GPF_ERR_INVALID_ARGUMENT, "NULL output");
-  return launch_trace_photons(n_paths, seed, max_events, light_lo, light_hi, sphere ? 1 : 0, pos,
+  if (sphere < 0 || sphere > 2) return set_error(GPF_ERR_INVALID_ARGUMENT, "sphere must be 0, 1 or 2");
+  return launch_trace_photons(n_paths, seed, max_events, light_lo, light_hi, sphere, pos,
                               power, surface, (hipStream_t)stream);
 }
 
@@ -370,6 +371,58 @@ gpf_status gpf_photon_density(const float* x, const int* x_surface, int64_t q, c
   photon_map_free(m);
   if (st == GPF_OK && e != hipSuccess) st = hip_fail(e, "density estimate");
   return st;
+}
+
+gpf_status gpf_camera_trace(const gpf_camera* cam, int samples, uint64_t seed, int max_depth,
+                            float light_lo, float light_hi, int sphere, float* x, float* beta,
+                            int* face, float* Le, void* stream) {
+  if (!cam || !x || !beta || !face || !Le) return set_error(GPF_ERR_INVALID_ARGUMENT, "NULL argument");
+  if (cam->width < 1 || cam->height < 1) return set_error(GPF_ERR_INVALID_ARGUMENT, "empty image");
+  if (samples < 1 || samples > 1024) return set_error(GPF_ERR_INVALID_ARGUMENT, "samples must lie in [1, 1024]");
+  if ((int64_t)cam->width * cam->height * samples >= ((int64_t)1 << 31))
+    return set_error(GPF_ERR_INVALID_ARGUMENT, "width * height * samples must stay below 2^31");
+  if (max_depth < 1 || max_depth > 64) return set_error(GPF_ERR_INVALID_ARGUMENT, "max_depth must lie in [1, 64]");
+  if (sphere < 0 || sphere > 2) return set_error(GPF_ERR_INVALID_ARGUMENT, "sphere must be 0, 1 or 2");
+  if (!(light_lo >= 0.f) || !(light_hi <= 1.f) || !(light_lo <= light_hi))
+    return set_error(GPF_ERR_INVALID_ARGUMENT, "light square must satisfy 0 <= lo <= hi <= 1");
+  if (!(cam->vfov_deg > 0.f && cam->vfov_deg < 180.f))
+    return set_error(GPF_ERR_INVALID_ARGUMENT, "vfov_deg must lie in (0, 180)");
+  double f[3], c[3];
+  for (int a = 0; a < 3; ++a) {
+    if (!std::isfinite(cam->eye[a]) || !std::isfinite(cam->target[a]) || !std::isfinite(cam->up[a]))
+      return set_error(GPF_ERR_INVALID_ARGUMENT, "camera vectors must be finite");
+    f[a] = (double)cam->target[a] - cam->eye[a];
+  }
+  c[0] = f[1] * cam->up[2] - f[2] * cam->up[1];
+  c[1] = f[2] * cam->up[0] - f[0] * cam->up[2];
+  c[2] = f[0] * cam->up[1] - f[1] * cam->up[0];
+  const double lf = std::sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+  const double lu = std::sqrt((double)cam->up[0] * cam->up[0] + (double)cam->up[1] * cam->up[1] +
+                              (double)cam->up[2] * cam->up[2]);
+  if (!(lf > 0) || !(std::sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]) > 1e-9 * lf * lu))
+    return set_error(GPF_ERR_INVALID_ARGUMENT, "eye equals target or up is parallel to the view");
+  return launch_camera_trace(cam, samples, seed, max_depth, light_lo, light_hi, sphere, x, beta, face,
+                             Le, (hipStream_t)stream);
+}
+
+gpf_status gpf_camera_compose(const float* Le, int64_t n_pix, int samples, const int64_t* slot,
+                              const float* beta_c, const float* Lq, int64_t m, float* L_pix,
+                              void* stream) {
+  if (!Le || !L_pix || (m > 0 && (!slot || !beta_c || !Lq)))
+    return set_error(GPF_ERR_INVALID_ARGUMENT, "NULL argument");
+  if (n_pix < 1 || samples < 1 || m < 0 || n_pix * (int64_t)samples >= ((int64_t)1 << 31))
+    return set_error(GPF_ERR_INVALID_ARGUMENT, "bad sizes");
+  return launch_camera_compose(Le, n_pix, samples, slot, beta_c, Lq, m, L_pix, (hipStream_t)stream);
+}
+
+gpf_status gpf_camera_compose_backward(const float* dL_pix, int64_t n_pix, int samples,
+                                       const int64_t* slot, const float* beta_c, int64_t m,
+                                       float* dLq, void* stream) {
+  if (!dL_pix || (m > 0 && (!slot || !beta_c || !dLq)))
+    return set_error(GPF_ERR_INVALID_ARGUMENT, "NULL argument");
+  if (n_pix < 1 || samples < 1 || m < 0) return set_error(GPF_ERR_INVALID_ARGUMENT, "bad sizes");
+  return launch_camera_compose_backward(dL_pix, n_pix, samples, slot, beta_c, m, dLq,
+                                        (hipStream_t)stream);
 }
 
 gpf_status gpf_valu_probe(float* out, int64_t out_len, int blocks, int iters, void* stream) {

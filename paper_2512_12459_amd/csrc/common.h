@@ -145,6 +145,15 @@ gpf_status photon_map_build(const float* ppos, const float* ppw, const int* psur
 gpf_status photon_map_gather(const gpf_photon_map* m, const float* x, const int* xs, int64_t q,
                              float weight, bool accumulate, float* L, int* count, hipStream_t s);
 void photon_map_free(gpf_photon_map* m);
+gpf_status launch_camera_trace(const gpf_camera* cam, int samples, uint64_t seed, int max_depth,
+                               float lo, float hi, int sphere, float* x, float* beta, int* face,
+                               float* Le, hipStream_t s);
+gpf_status launch_camera_compose(const float* Le, int64_t n_pix, int S, const int64_t* slot,
+                                 const float* beta_c, const float* Lq, int64_t m, float* L,
+                                 hipStream_t s);
+gpf_status launch_camera_compose_backward(const float* dL, int64_t n_pix, int S,
+                                          const int64_t* slot, const float* beta_c, int64_t m,
+                                          float* dLq, hipStream_t s);
 gpf_status launch_valu_probe(float* out, int blocks, int iters, hipStream_t s);
 gpf_status launch_mse(const float* L, const float* T, int64_t q, double* loss, float* dL,
                       hipStream_t s);

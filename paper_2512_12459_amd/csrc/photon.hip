@@ -18,56 +18,17 @@
 // otherwise; a face stores (position, power, face) in slot event-1, then
 // continues when u0 < q = max(albedo) with power * albedo / q and a cosine
 // direction about the normal (azimuth 2 pi u1, sin^2 of the polar angle u2).
+#include <rocprim/device/device_radix_sort.hpp>
 #include <rocprim/device/device_scan.hpp>
 
 #include "common.h"
 #include "pointgrid.h"
+#include "scene.h"
 
 namespace gpf {
 namespace {
 
-constexpr float kTEps = 1e-4f;
-constexpr float kIor = 1.5f;
-constexpr float kSphR = 0.2f;
-constexpr float kPi = 3.14159265358979323846f;
 constexpr int kPhotonGridDim = 256;
-
-__constant__ float kAlbedo[5][3] = {{0.73f, 0.73f, 0.73f}, {0.73f, 0.73f, 0.73f},
-                                     {0.63f, 0.06f, 0.05f}, {0.14f, 0.45f, 0.09f},
-                                     {0.73f, 0.73f, 0.73f}};
-__constant__ float kNormal[5][3] = {{0, 1, 0}, {0, -1, 0}, {1, 0, 0}, {-1, 0, 0}, {0, 0, 1}};
-__constant__ float kTangT[5][3] = {{0, 0, 1}, {1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {1, 0, 0}};
-__constant__ float kTangB[5][3] = {{1, 0, 0}, {0, 0, 1}, {0, 0, 1}, {0, 1, 0}, {0, 1, 0}};
-
-// Philox4x64-10.
-__device__ __forceinline__ void philox(uint64_t c[4], uint64_t k0, uint64_t k1) {
-  const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
-#pragma unroll
-  for (int r = 0; r < 10; ++r) {
-    if (r) {
-      k0 += 0x9E3779B97F4A7C15ull;
-      k1 += 0xBB67AE8584CAA73Bull;
-    }
-    const uint64_t hi0 = __umul64hi(M0, c[0]), lo0 = M0 * c[0];
-    const uint64_t hi1 = __umul64hi(M1, c[2]), lo1 = M1 * c[2];
-    const uint64_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
-    c[0] = n0;
-    c[1] = lo1;
-    c[2] = n2;
-    c[3] = lo0;
-  }
-}
-
-__device__ __forceinline__ void uniforms(uint64_t path, uint64_t event, uint64_t seed, float u[4]) {
-  uint64_t c[4] = {path, event, 0ull, 0ull};
-  philox(c, seed, 0ull);
-#pragma unroll
-  for (int i = 0; i < 4; ++i) u[i] = (float)(c[i] >> 40) * (1.0f / 16777216.0f);
-}
-
-__device__ __forceinline__ float dot3(const float a[3], const float b[3]) {
-  return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
-}
 
 __global__ void __launch_bounds__(256) trace_kernel(int64_t n, uint64_t seed, int E, float lo,
                                                     float hi, int sphere, float3 power0,
@@ -78,73 +39,28 @@ __global__ void __launch_bounds__(256) trace_kernel(int64_t n, uint64_t seed, in
   if (i >= n) return;
   for (int j = 0; j < E; ++j) surf[i * E + j] = -1;
   float u[4];
-  uniforms((uint64_t)i, 0, seed, u);
+  uniforms((uint64_t)i, 0, 0, seed, u);
   float o[3] = {lo + (hi - lo) * u[0], 1.f, lo + (hi - lo) * u[1]};
   const float phi = 2.f * kPi * u[2];
   const float r = sqrtf(u[3]);
   float d[3] = {r * cosf(phi), -sqrtf(1.f - u[3]), r * sinf(phi)};
   float p[3] = {power0.x, power0.y, power0.z};
-  const float c[3] = {0.5f, 0.5f, 0.5f};
   for (int j = 1; j <= E; ++j) {
-    uniforms((uint64_t)i, (uint64_t)j, seed, u);
-    // box: nearest crossing ahead (face 5 = the open side z = 1)
-    float tb = INFINITY;
-    int face = -1;
-    const float tf[6] = {d[1] < 0.f ? (0.f - o[1]) / d[1] : INFINITY,
-                         d[1] > 0.f ? (1.f - o[1]) / d[1] : INFINITY,
-                         d[0] < 0.f ? (0.f - o[0]) / d[0] : INFINITY,
-                         d[0] > 0.f ? (1.f - o[0]) / d[0] : INFINITY,
-                         d[2] < 0.f ? (0.f - o[2]) / d[2] : INFINITY,
-                         d[2] > 0.f ? (1.f - o[2]) / d[2] : INFINITY};
-#pragma unroll
-    for (int k = 0; k < 6; ++k)
-      if (tf[k] > kTEps && tf[k] < tb) {
-        tb = tf[k];
-        face = k;
-      }
-    float ts = INFINITY;
-    if (sphere) {
-      const float oc[3] = {o[0] - c[0], o[1] - c[1], o[2] - c[2]};
-      const float b = dot3(oc, d);
-      const float cc = dot3(oc, oc) - kSphR * kSphR;
-      const float disc = b * b - cc;
-      if (disc > 0.f) {
-        const float sq = sqrtf(disc);
-        const float t0 = -b - sq, t1 = -b + sq;
-        ts = t0 > kTEps ? t0 : (t1 > kTEps ? t1 : INFINITY);
-      }
-    }
+    uniforms((uint64_t)i, (uint64_t)j, 0, seed, u);
+    int face;
+    const float tb = box_crossing(o, d, face);
+    const float ts = sphere ? sphere_crossing(o, d) : INFINITY;
     const bool hit_s = ts < tb;
     if (!hit_s && (face < 0 || face == 5)) break;  // escaped through the open side
     const float t = hit_s ? ts : tb;
     const float x[3] = {o[0] + t * d[0], o[1] + t * d[1], o[2] + t * d[2]};
     if (hit_s) {
-      float ns[3] = {(x[0] - c[0]) / kSphR, (x[1] - c[1]) / kSphR, (x[2] - c[2]) / kSphR};
-      const float cos_o = -dot3(d, ns);
-      const bool inside = cos_o < 0.f;
-      if (inside) ns[0] = -ns[0], ns[1] = -ns[1], ns[2] = -ns[2];
-      const float cos_i = fabsf(cos_o);
-      const float ei = inside ? kIor : 1.f, et = inside ? 1.f : kIor;
-      const float eta = ei / et;
-      const float sin2_t = eta * eta * fmaxf(0.f, 1.f - cos_i * cos_i);
-      float F = 1.f, cos_t = 0.f;
-      if (sin2_t < 1.f) {
-        cos_t = sqrtf(fmaxf(0.f, 1.f - sin2_t));
-        const float rs = (ei * cos_i - et * cos_t) / (ei * cos_i + et * cos_t);
-        const float rp = (ei * cos_t - et * cos_i) / (ei * cos_t + et * cos_i);
-        F = 0.5f * (rs * rs + rp * rp);
+      float fac[3];
+      sphere_scatter(d, x, u[0], sphere, fac);
+      if (sphere == kSphereMirror) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) p[a] *= fac[a];
       }
-      float nd[3];
-      if (u[0] < F) {
-#pragma unroll
-        for (int a = 0; a < 3; ++a) nd[a] = d[a] + 2.f * cos_i * ns[a];
-      } else {
-#pragma unroll
-        for (int a = 0; a < 3; ++a) nd[a] = eta * d[a] + (eta * cos_i - cos_t) * ns[a];
-      }
-      const float inv = 1.f / sqrtf(dot3(nd, nd));
-#pragma unroll
-      for (int a = 0; a < 3; ++a) d[a] = nd[a] * inv;
     } else {
       const int64_t slot = i * E + (j - 1);
       pos[slot * 3] = x[0];
@@ -194,6 +110,17 @@ __global__ void __launch_bounds__(256) photon_scatter_kernel(
   }
   osurf[k] = surf[i];
   if (oslot) oslot[k] = i;
+}
+
+// Cell of each photon (sort key) and its index (sort value).
+__global__ void __launch_bounds__(256) photon_key_kernel(const float* __restrict__ ppos, int64_t np,
+                                                         PGrid g, unsigned* __restrict__ key,
+                                                         int* __restrict__ val) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= np) return;
+  const int3 c = pcell(g, ppos[i * 3], ppos[i * 3 + 1], ppos[i * 3 + 2]);
+  key[i] = (unsigned)((c.z * g.dy + c.y) * g.dx + c.x);
+  val[i] = (int)i;
 }
 
 // Photon records gathered into cell order: (x, y, z, face) and (power, 0),
@@ -372,41 +299,59 @@ gpf_status photon_map_build(const float* ppos, const float* ppw, const int* psur
   }
   m->cells = (int64_t)m->g.dx * m->g.dy * m->g.dz;
   const int64_t cells = m->cells;
-  int *cnt = nullptr, *sorted = nullptr;
+  // cells: count -> exclusive scan gives the starts; photons: a stable radix
+  // sort by cell, so each cell holds its photons in index order and the
+  // gather's summation order does not depend on scheduling
+  int *cnt = nullptr, *val = nullptr, *sorted = nullptr;
+  unsigned *key = nullptr, *key_s = nullptr;
   void* tmp = nullptr;
   size_t tb = 0;
   auto cleanup = [&]() {
     dev_free(cnt, (cells + 1) * 4);
+    dev_free(val, np * 4);
     dev_free(sorted, np * 4);
+    dev_free(key, np * 4);
+    dev_free(key_s, np * 4);
     dev_free(tmp, tb);
   };
   if ((st = dev_alloc((void**)&m->start, (cells + 1) * 4, "photon cells")) != GPF_OK ||
       (st = dev_alloc((void**)&m->spos, np * sizeof(float4), "photon records")) != GPF_OK ||
       (st = dev_alloc((void**)&m->spw, np * sizeof(float4), "photon records")) != GPF_OK ||
       (st = dev_alloc((void**)&cnt, (cells + 1) * 4, "photon cells")) != GPF_OK ||
-      (st = dev_alloc((void**)&sorted, np * 4, "photon order")) != GPF_OK) {
+      (st = dev_alloc((void**)&val, np * 4, "photon order")) != GPF_OK ||
+      (st = dev_alloc((void**)&sorted, np * 4, "photon order")) != GPF_OK ||
+      (st = dev_alloc((void**)&key, np * 4, "photon keys")) != GPF_OK ||
+      (st = dev_alloc((void**)&key_s, np * 4, "photon keys")) != GPF_OK) {
     cleanup();
     photon_map_free(m);
     return st;
   }
-  e = hipMemsetAsync(cnt, 0, (cells + 1) * 4, s);
+  int bits = 1;
+  while (bits < 32 && ((int64_t)1 << bits) <= cells) ++bits;
+  size_t scan_b = 0, sort_b = 0;
+  e = rocprim::exclusive_scan(nullptr, scan_b, cnt, m->start, 0, (size_t)(cells + 1),
+                              rocprim::plus<int>(), s);
+  if (e == hipSuccess)
+    e = rocprim::radix_sort_pairs(nullptr, sort_b, key, key_s, val, sorted, (size_t)np, 0, bits, s);
+  tb = std::max(scan_b, sort_b);
+  if (e == hipSuccess && (st = dev_alloc(&tmp, tb, "photon sort")) != GPF_OK) {
+    cleanup();
+    photon_map_free(m);
+    return st;
+  }
   const unsigned pb = (unsigned)((np + 255) / 256);
-  hipLaunchKernelGGL(pcount_kernel, dim3(pb), dim3(256), 0, s, ppos, np, m->g, cnt);
-  if (e == hipSuccess)
-    e = rocprim::exclusive_scan(nullptr, tb, cnt, m->start, 0, (size_t)(cells + 1),
-                                rocprim::plus<int>(), s);
-  if (e == hipSuccess && (st = dev_alloc(&tmp, tb, "photon scan")) != GPF_OK) {
-    cleanup();
-    photon_map_free(m);
-    return st;
-  }
-  if (e == hipSuccess)
-    e = rocprim::exclusive_scan(tmp, tb, cnt, m->start, 0, (size_t)(cells + 1),
-                                rocprim::plus<int>(), s);
   if (e == hipSuccess) e = hipMemsetAsync(cnt, 0, (cells + 1) * 4, s);
   if (e == hipSuccess) {
-    hipLaunchKernelGGL(pscatter_kernel, dim3(pb), dim3(256), 0, s, ppos, np, m->g, m->start, cnt,
-                       sorted);
+    hipLaunchKernelGGL(pcount_kernel, dim3(pb), dim3(256), 0, s, ppos, np, m->g, cnt);
+    hipLaunchKernelGGL(photon_key_kernel, dim3(pb), dim3(256), 0, s, ppos, np, m->g, key, val);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess)
+    e = rocprim::exclusive_scan(tmp, scan_b, cnt, m->start, 0, (size_t)(cells + 1),
+                                rocprim::plus<int>(), s);
+  if (e == hipSuccess)
+    e = rocprim::radix_sort_pairs(tmp, sort_b, key, key_s, val, sorted, (size_t)np, 0, bits, s);
+  if (e == hipSuccess) {
     hipLaunchKernelGGL(photon_gather_kernel, dim3(pb), dim3(256), 0, s, sorted, np, ppos, ppw,
                        psurf, m->spos, m->spw);
     e = hipGetLastError();

@@ -24,21 +24,26 @@ __device__ __forceinline__ int3 pcell(const PGrid& g, float x, float y, float z)
   return c;
 }
 
+// min / max that keep a NaN once seen (fminf / fmaxf would drop it), so
+// that a NaN coordinate reaches the host-side finiteness check.
+__device__ __forceinline__ float nan_min(float a, float b) { return (b < a || b != b) ? b : a; }
+__device__ __forceinline__ float nan_max(float a, float b) { return (b > a || b != b) ? b : a; }
+
 __global__ void pbox_kernel(const float* __restrict__ pos, int64_t n, float* part) {
   float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      lo[a] = fminf(lo[a], pos[i * 3 + a]);
-      hi[a] = fmaxf(hi[a], pos[i * 3 + a]);
+      lo[a] = nan_min(lo[a], pos[i * 3 + a]);
+      hi[a] = nan_max(hi[a], pos[i * 3 + a]);
     }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1)
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      lo[a] = fminf(lo[a], __shfl_xor(lo[a], off, 64));
-      hi[a] = fmaxf(hi[a], __shfl_xor(hi[a], off, 64));
+      lo[a] = nan_min(lo[a], __shfl_xor(lo[a], off, 64));
+      hi[a] = nan_max(hi[a], __shfl_xor(hi[a], off, 64));
     }
   __shared__ float s[4][6];
   const int w = threadIdx.x >> 6;
@@ -50,7 +55,8 @@ __global__ void pbox_kernel(const float* __restrict__ pos, int64_t n, float* par
   __syncthreads();
   if (threadIdx.x < 6) {
     float v = s[0][threadIdx.x];
-    for (int k = 1; k < 4; ++k) v = threadIdx.x < 3 ? fminf(v, s[k][threadIdx.x]) : fmaxf(v, s[k][threadIdx.x]);
+    for (int k = 1; k < 4; ++k)
+      v = threadIdx.x < 3 ? nan_min(v, s[k][threadIdx.x]) : nan_max(v, s[k][threadIdx.x]);
     part[blockIdx.x * 6 + threadIdx.x] = v;
   }
 }
@@ -97,8 +103,9 @@ inline gpf_status point_grid_geometry(const float* hp, int64_t n, int maxdim, PG
     lo[a] = hp[a];
     hi[a] = hp[3 + a];
     for (int b = 1; b < kPointBoxBlocks; ++b) {
-      lo[a] = std::fmin(lo[a], hp[b * 6 + a]);
-      hi[a] = std::fmax(hi[a], hp[b * 6 + 3 + a]);
+      const float l = hp[b * 6 + a], h = hp[b * 6 + 3 + a];
+      lo[a] = (l < lo[a] || l != l) ? l : lo[a];
+      hi[a] = (h > hi[a] || h != h) ? h : hi[a];
     }
     if (!std::isfinite(lo[a]) || !std::isfinite(hi[a]))
       return set_error(GPF_ERR_INVALID_ARGUMENT, "positions contain NaN or Inf");

@@ -104,6 +104,30 @@ def test_glass_sphere_images_a_point_light_like_a_ball_lens():
     assert np.median(ratio) == pytest.approx(1 / 6, rel=0.02)
 
 
+def test_mirror_sphere_reflects_photons_with_its_reflectance():
+    # photons from a point light straight above the mirror sphere: those that
+    # hit it first land on a face at event 2 carrying power * rho, along the
+    # mirrored direction (equal angles with the normal, coplanar with it)
+    n = 100000
+    out = P.trace(n, 19, max_events=2, sphere=2, light=(0.5, 0.5))
+    u = P.uniforms(np.arange(n, dtype=np.uint64), 0, 19)
+    phi, r = 2 * math.pi * u[2], np.sqrt(u[3])
+    d = np.stack([r * np.cos(phi), -np.sqrt(1 - u[3]), r * np.sin(phi)], 1)
+    o = np.tile([0.5, 1.0, 0.5], (n, 1))
+    t, _ = P.sphere_hit(o, d)
+    via = np.isfinite(t) & (out["surface"][:, 0] < 0) & (out["surface"][:, 1] >= 0)
+    assert via.sum() > 1000
+    np.testing.assert_allclose(out["power"][via, 1],
+                               np.broadcast_to(P.PHI_LIGHT / n * np.array([0.95, 0.64, 0.54]),
+                                               (via.sum(), 3)), rtol=1e-6)
+    h = o[via] + t[via, None] * d[via]
+    nrm = (h - P.SPHERE_C) / P.SPHERE_R
+    out_dir = out["pos"][via, 1] - h
+    out_dir /= np.linalg.norm(out_dir, axis=1, keepdims=True)
+    np.testing.assert_allclose(np.sum(-d[via] * nrm, 1), np.sum(out_dir * nrm, 1), atol=1e-9)
+    np.testing.assert_allclose(np.einsum("ij,ij->i", np.cross(d[via], nrm), out_dir), 0, atol=1e-9)
+
+
 def test_russian_roulette_is_unbiased():
     # at a diffuse face of albedo a (stated values: white 0.73, red (0.63, 0.06,
     # 0.05), green (0.14, 0.45, 0.09)), a photon continues exactly when its
