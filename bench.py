@@ -12,7 +12,9 @@ once before timing.  Prints one JSON line.
 ``--workload sppm`` instead times one progressive photon-mapping iteration per
 step: trace 100,000 photon paths, compact the stored photons, bin them, and
 gather the density estimate (r = 0.02) at the diffuse first hits of the same
-32 ring views at 800x800.
+32 ring views at 800x800.  ``--workload render`` times one 1024x1024 image
+through the hybrid camera integrator with a field of about 100,000 Gaussians
+seeded from traced photons.
 """
 from __future__ import annotations
 
@@ -124,10 +126,11 @@ def cpu_sppm_baseline(x, xs, n_paths, r, seed, sample: int):
 
 
 def bench_sppm(args):
-    """One progressive photon-mapping iteration per step (Sec. 3 photon pass
+    """One progressive photon-mapping iteration per step (Sec. 3.2 photon pass
     and radiance estimation; Sec. 4.3 reference equation): trace n_paths
     photon paths, compact the stored photons, bin them, and gather the density
-    estimate at every diffuse first hit of the camera ring."""
+    estimate at every diffuse first hit of the camera ring (binned once, tile
+    by tile)."""
     import numpy as np
     import torch
 
@@ -148,6 +151,8 @@ def bench_sppm(args):
     xsd = torch.from_numpy(xs).to(dev)
     L = torch.zeros((q, 3), device=dev)
     cnt = torch.empty(q, dtype=torch.int32, device=dev)
+    from paper_2512_12459_amd import radiance as R
+    qs = R.QuerySet(xd, args.cell)      # the points are binned once, like the fitting bench
     E = 8
     n_iter = args.warmup + args.steps          # L ends as the mean estimate over all iterations
     stream = torch.cuda.current_stream()
@@ -166,7 +171,7 @@ def bench_sppm(args):
         e2 = mark() if timed else None
         pm = PH.PhotonMap(ppos, ppw, psurf, args.radius)
         e3 = mark() if timed else None
-        pm.gather(xd, xsd, 1.0 / n_iter, out=L, accumulate=True, count=cnt)
+        pm.gather(xd, xsd, 1.0 / n_iter, out=L, accumulate=True, count=cnt, queries=qs)
         e4 = mark() if timed else None
         info["photons"] = ppos.shape[0]
         if timed:
@@ -205,7 +210,7 @@ def bench_sppm(args):
         "pairs": pairs,
         "pairs_per_point": pairs / q,
         "paths_per_s": args.paths / (ms["trace"] * 1e-3),
-        "roofline": {"bound": "alu", "kernel": "kde_kernel", "achieved": achieved / 1e12,
+        "roofline": {"bound": "alu", "kernel": "kde_tile_kernel", "achieved": achieved / 1e12,
                      "peak": PEAK_FP32_VALU / 1e12, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_VALU, "traffic": None,
                      "flops_per_pair": FLOPS_KDE_PAIR},
@@ -214,6 +219,93 @@ def bench_sppm(args):
         log("cpu baseline (oracle) ...")
         result["cpu_baseline"] = cpu_sppm_baseline(x, xs, args.paths, args.radius, 11,
                                                    20 * args.cpu_sample)
+    print(json.dumps(result), flush=True)
+
+
+def bench_render(args):
+    """One image per step through the hybrid camera integrator (Sec. 4.2;
+    supplementary Alg. S2): camera paths through the glass sphere, compaction
+    of the diffuse hits, query binning, the hybrid query's grid and forward,
+    and the pixel composition.  The field is seeded from traced photons
+    (one tracing iteration, each Gaussian's flux from the density estimate at
+    its photon), about the paper's 100,000 Gaussians."""
+    import numpy as np
+    import torch
+
+    from paper_2512_12459_amd import camera as CM
+    from paper_2512_12459_amd import photons as PH
+    from paper_2512_12459_amd import radiance as R
+    from paper_2512_12459_amd import scenes as S
+
+    torch.cuda.set_device(0)
+    res = args.res or 1024
+    cam = S.camera_ring(1, res)[0]
+    rec = PH.trace_photons(args.paths, 5, 8)
+    ppos, ppw, psurf = PH.compact_photons(*rec)
+    Lp = PH.photon_density(ppos, psurf, ppos, ppw, psurf, args.radius)
+    mu, quat, ls, rgb = PH.init_from_photons(ppos, Lp, k=16)
+    n = mu.shape[0]
+    log(f"render: {n} Gaussians seeded from {args.paths} traced paths; {res}x{res} image")
+    stream = torch.cuda.current_stream()
+    ev = {k: [] for k in ("camera", "compact", "bin", "grid", "query", "compose")}
+    info = {}
+
+    def step(t, timed):
+        def mark():
+            e = torch.cuda.Event(enable_timing=True)
+            e.record(stream)
+            return e
+        e0 = mark() if timed else None
+        x, beta, face, Le = CM.trace_camera(cam, 1, t, sphere=CM.GLASS)
+        e1 = mark() if timed else None
+        xc, bc, fc, slot = PH.compact_photons(x, beta, face, with_slot=True)
+        e2 = mark() if timed else None
+        qs = R.QuerySet(xc, args.cell)
+        e3 = mark() if timed else None
+        g = R.HybridGrid(qs, args.radius).build(mu, quat, ls, rgb)
+        e4 = mark() if timed else None
+        Lq, Z, cnt = R.eval_hybrid(g, mu, quat, ls, rgb)
+        e5 = mark() if timed else None
+        img = CM.compose_pixels(Le, 1, slot, bc, Lq)
+        e6 = mark() if timed else None
+        info["hits"] = xc.shape[0]
+        info["count"] = cnt
+        if timed:
+            for k, (a, b) in zip(ev, ((e0, e1), (e1, e2), (e2, e3), (e3, e4), (e4, e5), (e5, e6))):
+                ev[k].append((a, b))
+        return g, qs, img
+
+    for t in range(1, args.warmup + 1):
+        step(t, False)
+    torch.cuda.synchronize()
+    keep = []
+    t_start = time.perf_counter()
+    for t in range(args.warmup + 1, args.warmup + args.steps + 1):
+        keep.append(step(t, True))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    ms = {k: float(np.mean([a.elapsed_time(b) for a, b in v])) for k, v in ev.items()}
+    c = info["count"].to(torch.int64)
+    pairs = int(torch.where(c >= 3, c, torch.full_like(c, min(3, n))).sum().item())
+    step_ms = wall / args.steps * 1e3
+    achieved = pairs * FLOPS_FWD_HYBRID / (ms["query"] * 1e-3)
+    result = {
+        "metric": "rendered images/s through the hybrid camera integrator",
+        "value": 1e3 / step_ms, "unit": "images/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": step_ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"render: {n} Gaussians seeded from {args.paths} traced photon paths, "
+                               f"one ring view at {res}x{res}, 1 path per pixel, glass sphere, "
+                               f"hybrid query r={args.radius} k_min=3",
+                   "step": "camera paths + compaction + query binning + hybrid grid + hybrid "
+                           "forward + composition"},
+        "kernel_ms": ms, "diffuse_hits": info["hits"], "pairs": pairs,
+        "roofline": {"bound": "alu", "kernel": "hybrid_fwd", "achieved": achieved / 1e12,
+                     "peak": PEAK_FP32_VALU / 1e12, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32_VALU, "traffic": None,
+                     "flops_per_pair": FLOPS_FWD_HYBRID},
+    }
     print(json.dumps(result), flush=True)
 
 
@@ -261,6 +353,11 @@ def main():
 
     if args.workload == "sppm":
         bench_sppm(args)
+        return
+    if args.workload == "render":
+        if args.paths == 100_000:
+            args.paths = 60_000       # about 100,000 stored photons, one Gaussian each
+        bench_render(args)
         return
 
     from paper_2512_12459_amd import radiance as R

@@ -163,7 +163,7 @@ gpf_status gpf_eval_hybrid_backward(const gpf_grid *grid, const gpf_field *f, co
                                     const int *count, const float *dL, gpf_field_grad *grad,
                                     void *stream);
 
-/* ---- photon tracing (Sec. 3 photon pass) and density estimate (Sec. 3
+/* ---- photon tracing (Sec. 3.2 photon pass) and density estimate (Sec. 3
  * radiance estimation, Sec. 4.3 reference equation) ----------------------
  * Scene: the box [0,1]^3 with diffuse faces floor y=0 (0), ceiling y=1 (1),
  * x=0 (2), x=1 (3), back z=0 (4), open at z=1; a sphere of radius 0.2 at
@@ -206,7 +206,7 @@ gpf_status gpf_photon_map_build(const float *ppos, const float *ppower, const in
                                 int64_t np, float r, void *stream, gpf_photon_map **map);
 void gpf_photon_map_destroy(gpf_photon_map *map);
 
-/* Density estimate (Sec. 3 radiance estimation; the inner sum of the Sec. 4.3
+/* Density estimate (Sec. 3.2 radiance estimation; the inner sum of the Sec. 4.3
  * reference equation with a Lambertian BSDF) at q points x[q][3] lying on
  * faces x_surface[q] (a point on the sphere, or any value outside 0..4, gets
  * 0): E = albedo / pi / (pi r^2) * sum of the powers of the photons of the
@@ -220,6 +220,15 @@ void gpf_photon_map_destroy(gpf_photon_map *map);
 gpf_status gpf_photon_map_gather(const gpf_photon_map *map, const float *x, const int *x_surface,
                                  int64_t q, float weight, int accumulate, float *L, int *count,
                                  void *stream);
+
+/* The same estimate at the points of a binned query set (gpf_bin_queries),
+ * x_surface[q] in the caller's order of those points, L[q][3] and count[q]
+ * likewise: one wave per tile of points visits each photon of the cells near
+ * the tile once, so the results are bit-identical to gpf_photon_map_gather's
+ * at the same points.  Does not synchronise. */
+gpf_status gpf_photon_map_gather_binned(const gpf_photon_map *map, const gpf_queries *queries,
+                                        const int *x_surface, float weight, int accumulate,
+                                        float *L, int *count, void *stream);
 
 /* gpf_photon_map_build + gpf_photon_map_gather + destroy in one call.
  * Synchronises. */

@@ -4,7 +4,7 @@ TEST INFRASTRUCTURE ONLY.  Nothing in the product path imports, calls or links
 this module: only the tests use it.  It shares no code with the HIP kernels
 and imports nothing from the package.
 
-What it computes (Sec. 3, photon tracing pass and radiance estimation; Sec. 4.3,
+What it computes (Sec. 3.2, photon tracing pass and radiance estimation; Sec. 4.3,
 the reference radiance equation; the paper's caustic scenes stand in as a
 box with a glass sphere):
 
@@ -41,7 +41,7 @@ intersection distances, a grazing sphere hit, u0 near F or near the critical
 angle) are flagged: a single-precision tracer may take them the other way,
 after which the path differs.
 
-Density estimate (Sec. 3 radiance estimation, Sec. 4.3 reference equation,
+Density estimate (Sec. 3.2 radiance estimation, Sec. 4.3 reference equation,
 one iteration): at a diffuse point x of face k,
   L(x) = albedo_k / pi * 1 / (pi r^2) * sum of the powers of the photons on
   face k within distance r of x,
@@ -282,7 +282,7 @@ def stored_photons(out):
 
 
 def sppm_radii(T, r0, alpha=0.7):
-    """Progressive radii (Sec. 4.3 implementation details): r_1 = r0 and
+    """Progressive radii (supplementary Sec. A.1): r_1 = r0 and
     r_{t+1} = r_t sqrt((t + alpha) / (t + 1))."""
     r = [float(r0)]
     for t in range(1, T):

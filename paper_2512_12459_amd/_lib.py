@@ -76,6 +76,7 @@ _SIG = {
                                         ctypes.c_int, _F, _F, ctypes.c_int, _P, _P, _P, _P, _P]),
     "gpf_camera_compose": (ctypes.c_int, [_P, _I64, ctypes.c_int, _P, _P, _P, _I64, _P, _P]),
     "gpf_camera_compose_backward": (ctypes.c_int, [_P, _I64, ctypes.c_int, _P, _P, _I64, _P, _P]),
+    "gpf_photon_map_gather_binned": (ctypes.c_int, [_P, _P, _P, _F, ctypes.c_int, _P, _P, _P]),
     "gpf_photon_density": (ctypes.c_int, [_P, _P, _I64, _P, _P, _P, _I64, _F, _F, ctypes.c_int,
                                             _P, _P, _P]),
     "gpf_mse_loss": (ctypes.c_int, [_P, _P, _I64, _P, _P, _P]),

@@ -44,6 +44,23 @@ def trace_camera(cam, samples: int = 1, seed: int = 0, max_depth: int = 16, sphe
     return x, beta, face, Le
 
 
+def compose_pixels(Le, samples: int, slot, beta_c, Lq, out=None):
+    """Pixel radiance [n_pix, 3] = mean over each pixel's paths of Le + beta *
+    L, from the compacted diffuse hits (slot ascending, beta_c, Lq)."""
+    _need(Le, "Le", 3)
+    _need(beta_c, "beta_c", 3)
+    _need(Lq, "Lq", 3)
+    m = Lq.shape[0]
+    if beta_c.shape[0] != m or slot.numel() != m or slot.dtype != torch.int64:
+        raise ValueError("slot (int64), beta_c and Lq must have one row per hit")
+    n_pix = Le.shape[0] // int(samples)
+    if out is None:
+        out = torch.empty((n_pix, 3), device=Le.device)
+    C.check(C.lib().gpf_camera_compose(C.ptr(Le), n_pix, int(samples), C.ptr(slot), C.ptr(beta_c),
+                                       C.ptr(Lq), m, C.ptr(out), _stream()))
+    return out
+
+
 class CameraPaths:
     """The camera paths of a set of views, with their diffuse hits compacted
     in path order: the query points `x` (with `face`) carry throughputs
@@ -66,15 +83,7 @@ class CameraPaths:
     def compose(self, Lq: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
         """Pixel radiance [n_pix, 3] from the field's radiance Lq [m, 3] at the
         diffuse hits."""
-        _need(Lq, "Lq", 3)
-        if Lq.shape[0] != self.m:
-            raise ValueError("Lq must have one row per diffuse hit")
-        if out is None:
-            out = torch.empty((self.n_pix, 3), device=self.Le.device)
-        C.check(C.lib().gpf_camera_compose(C.ptr(self.Le), self.n_pix, self.samples,
-                                           C.ptr(self.slot), C.ptr(self.beta), C.ptr(Lq), self.m,
-                                           C.ptr(out), _stream()))
-        return out
+        return compose_pixels(self.Le, self.samples, self.slot, self.beta, Lq, out)
 
     def compose_backward(self, dL_pix: torch.Tensor, out: torch.Tensor | None = None):
         """Gradient [m, 3] with respect to the field's radiance at the hits."""

@@ -7,6 +7,8 @@
 #include <cmath>
 
 #include "common.h"
+#include <rocprim/device/device_scan.hpp>
+
 #include "scan.h"
 
 namespace gpf {
@@ -108,8 +110,8 @@ __global__ void gather_kernel(const float* __restrict__ x, const uint64_t* __res
   flag[k] = (k == 0 || (keys[k] >> 30) != (keys[k - 1] >> 30)) ? 1 : 0;
 }
 
-// flag[] was exclusive-scanned in place: slot of point k = scanned[k] for a
-// run start.  Records the first point and dense cell of each occupied slot.
+// scanned[] is the exclusive scan of the run-start flags: slot of point k =
+// scanned[k] for a run start.  Records the first point and dense cell of each occupied slot.
 __global__ void cell_runs_kernel(const float4* __restrict__ xs, const uint64_t* __restrict__ keys,
                                  const int* __restrict__ scanned, int64_t q, GridGeom g,
                                  int* cell_first, int* occ_dense) {
@@ -270,6 +272,7 @@ gpf_status launch_bin_queries(const float* x, int64_t q, float cell, hipStream_t
   void* tmp = nullptr;
   size_t tmp_bytes = 0;
   int* flag = nullptr;
+  int* flag_s = nullptr;
   int* cell_first = nullptr;
   int* ntile = nullptr;
   int* cell_first_g = nullptr;
@@ -280,6 +283,7 @@ gpf_status launch_bin_queries(const float* x, int64_t q, float cell, hipStream_t
     dev_free(idx, q * 4);
     dev_free(tmp, tmp_bytes);
     dev_free(flag, (q + 1) * 4);
+    dev_free(flag_s, (q + 1) * 4);
     dev_free(cell_first, (q + 1) * 4);
     dev_free(ntile, (q + 1) * 4);
   };
@@ -315,15 +319,34 @@ gpf_status launch_bin_queries(const float* x, int64_t q, float cell, hipStream_t
        "radix_sort");
   hipLaunchKernelGGL(gather_kernel, dim3(nb), dim3(256), 0, s, x, keys_s, out->perm, q, out->xs,
                      flag);
-  hipLaunchKernelGGL(scan_exclusive_kernel, dim3(1), dim3(kScanThreads), 0, s, flag, flag, (int)q);
+  // run starts -> occupied-cell slots: a device-wide scan over q + 1 flags
+  // (flag[q] = 0, so the last entry is the number of occupied cells)
+  TRY(dev_alloc((void**)&flag_s, (q + 1) * 4, "flag scan"));
+  TRYH(hipMemsetAsync(flag + q, 0, 4, s), "flag end");
+  {
+    size_t scan_bytes = 0;
+    TRYH(rocprim::exclusive_scan(nullptr, scan_bytes, flag, flag_s, 0, (size_t)(q + 1),
+                                 rocprim::plus<int>(), s),
+         "scan size");
+    if (scan_bytes > tmp_bytes) {
+      dev_free(tmp, tmp_bytes);
+      tmp = nullptr;
+      tmp_bytes = 0;
+      TRY(dev_alloc(&tmp, scan_bytes, "scan scratch"));
+      tmp_bytes = scan_bytes;
+    }
+    TRYH(rocprim::exclusive_scan(tmp, scan_bytes, flag, flag_s, 0, (size_t)(q + 1),
+                                 rocprim::plus<int>(), s),
+         "scan");
+  }
   int ncells = 0;
-  TRYH(hipMemcpyAsync(&ncells, flag + q, 4, hipMemcpyDeviceToHost, s), "ncells readback");
+  TRYH(hipMemcpyAsync(&ncells, flag_s + q, 4, hipMemcpyDeviceToHost, s), "ncells readback");
   TRYH(hipStreamSynchronize(s), "ncells sync");
   out->ncells = ncells;
   TRY(dev_alloc((void**)&cell_first, (int64_t)(ncells + 1) * 4, "cell_first"));
   TRY(dev_alloc((void**)&out->occ_dense, (int64_t)ncells * 4, "occ_dense"));
   TRY(dev_alloc((void**)&out->occ_of_dense, dense * 4, "occ_of_dense"));
-  hipLaunchKernelGGL(cell_runs_kernel, dim3(nb), dim3(256), 0, s, out->xs, keys_s, flag, q, g,
+  hipLaunchKernelGGL(cell_runs_kernel, dim3(nb), dim3(256), 0, s, out->xs, keys_s, flag_s, q, g,
                      cell_first, out->occ_dense);
   TRYH(hipMemsetAsync(out->occ_of_dense, 0xff, dense * 4, s), "occ table clear");
   TRY(dev_alloc((void**)&out->occ_bits, ((dense + 31) / 32) * 4, "occupancy bits"));

@@ -356,6 +356,15 @@ gpf_status gpf_photon_map_gather(const gpf_photon_map* map, const float* x, cons
                            (hipStream_t)stream);
 }
 
+gpf_status gpf_photon_map_gather_binned(const gpf_photon_map* map, const gpf_queries* queries,
+                                        const int* x_surface, float weight, int accumulate,
+                                        float* L, int* count, void* stream) {
+  if (!map || !queries || !x_surface || !L) return set_error(GPF_ERR_INVALID_ARGUMENT, "NULL argument");
+  if (!std::isfinite(weight)) return set_error(GPF_ERR_INVALID_ARGUMENT, "weight must be finite");
+  return photon_map_gather_binned(map, queries, x_surface, weight, accumulate != 0, L, count,
+                                  (hipStream_t)stream);
+}
+
 gpf_status gpf_photon_density(const float* x, const int* x_surface, int64_t q, const float* ppos,
                               const float* ppower, const int* psurface, int64_t np, float r,
                               float weight, int accumulate, float* L, int* count, void* stream) {

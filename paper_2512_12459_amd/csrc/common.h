@@ -145,6 +145,9 @@ gpf_status photon_map_build(const float* ppos, const float* ppw, const int* psur
 gpf_status photon_map_gather(const gpf_photon_map* m, const float* x, const int* xs, int64_t q,
                              float weight, bool accumulate, float* L, int* count, hipStream_t s);
 void photon_map_free(gpf_photon_map* m);
+gpf_status photon_map_gather_binned(const gpf_photon_map* m, const gpf_queries* qs,
+                                    const int* xs, float weight, bool accumulate, float* L,
+                                    int* count, hipStream_t s);
 gpf_status launch_camera_trace(const gpf_camera* cam, int samples, uint64_t seed, int max_depth,
                                float lo, float hi, int sphere, float* x, float* beta, int* face,
                                float* Le, hipStream_t s);

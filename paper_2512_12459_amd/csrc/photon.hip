@@ -1,4 +1,4 @@
-// Photon tracing (Sec. 3 photon pass: photons traced from the light and
+// Photon tracing (Sec. 3.2 photon pass: photons traced from the light and
 // stored at every diffuse hit) and the photon density estimate (Sec. 3
 // radiance estimation; Sec. 4.3 reference equation), for the box scene with a
 // glass sphere that the caustic workloads use.
@@ -123,28 +123,28 @@ __global__ void __launch_bounds__(256) photon_key_kernel(const float* __restrict
   val[i] = (int)i;
 }
 
-// Photon records gathered into cell order: (x, y, z, face) and (power, 0),
-// so the gather below reads each cell's photons as one contiguous run.
+// Photon records gathered into cell order, two float4 per photon:
+// (x, y, z, face bits) and (power, 0), so that a gather reads each cell's
+// photons as one contiguous run and one photon as one 32-byte load.
 __global__ void __launch_bounds__(256) photon_gather_kernel(
     const int* __restrict__ sorted, int64_t np, const float* __restrict__ ppos,
-    const float* __restrict__ ppw, const int* __restrict__ psurf, float4* __restrict__ spos,
-    float4* __restrict__ spw) {
+    const float* __restrict__ ppw, const int* __restrict__ psurf, float4* __restrict__ rec) {
   const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (s >= np) return;
   const int64_t j = sorted[s];
-  spos[s] = make_float4(ppos[j * 3], ppos[j * 3 + 1], ppos[j * 3 + 2], __int_as_float(psurf[j]));
-  spw[s] = make_float4(ppw[j * 3], ppw[j * 3 + 1], ppw[j * 3 + 2], 0.f);
+  rec[2 * s] = make_float4(ppos[j * 3], ppos[j * 3 + 1], ppos[j * 3 + 2], __int_as_float(psurf[j]));
+  rec[2 * s + 1] = make_float4(ppw[j * 3], ppw[j * 3 + 1], ppw[j * 3 + 2], 0.f);
 }
 
 // Density estimate at point i on face k: sum over the photons of face k
 // within r (FP32 squared distance in the fixed order), times
 // weight * albedo_k / pi / (pi r^2), stored or added.  Cells have edge >= r,
-// so the 27 cells around the point's cell cover the disc.
+// so the 27 cells around the point's cell cover the disc.  Photons are
+// visited in (cell z, cell y, cell x, photon index) order.
 __global__ void __launch_bounds__(256) kde_kernel(const float* __restrict__ x,
                                                   const int* __restrict__ xs, int64_t q, PGrid g,
                                                   const int* __restrict__ start,
-                                                  const float4* __restrict__ spos,
-                                                  const float4* __restrict__ spw, float r2,
+                                                  const float4* __restrict__ rec, float r2,
                                                   float scale, int accumulate,
                                                   float* __restrict__ L, int* __restrict__ count) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -161,7 +161,7 @@ __global__ void __launch_bounds__(256) kde_kernel(const float* __restrict__ x,
         const int row = (zc * g.dy + yc) * g.dx;
         const int e = start[row + min(c.x + 1, g.dx - 1) + 1];
         for (int s = start[row + max(c.x - 1, 0)]; s < e; ++s) {
-          const float4 p = spos[s];
+          const float4 p = rec[2 * s];
           if (__float_as_int(p.w) != k) continue;
           float d2;
           {
@@ -170,7 +170,7 @@ __global__ void __launch_bounds__(256) kde_kernel(const float* __restrict__ x,
             d2 = (dx * dx + dy * dy) + dz * dz;
           }
           if (d2 <= r2) {
-            const float4 w = spw[s];
+            const float4 w = rec[2 * s + 1];
             s0 += w.x;
             s1 += w.y;
             s2 += w.z;
@@ -192,6 +192,93 @@ __global__ void __launch_bounds__(256) kde_kernel(const float* __restrict__ x,
     L[i * 3 + 2] = s2;
   }
   if (count) count[i] = cnt;
+}
+
+// The same estimate over binned points: one wave per tile of <= 64 points
+// (lane = point), the photon cells covering the tile's box widened by r
+// visited in the same (z, y, x, index) order, each photon read once per wave
+// with wave-uniform scalar loads.  A photon within r of a point lies in the
+// point's 27-cell neighbourhood, which this range contains, so every point
+// sums the same photons in the same order as kde_kernel: the results are
+// bit-identical.
+constexpr int kKdeWaves = 4;
+
+__global__ void __launch_bounds__(kKdeWaves * 64) kde_tile_kernel(
+    const float4* __restrict__ xq, const int* __restrict__ perm,
+    const TileInfo* __restrict__ tiles, const float4* __restrict__ tlo,
+    const float4* __restrict__ thi, int ntiles, const int* __restrict__ xsurf, PGrid g,
+    const int* __restrict__ start, const float4* __restrict__ rec, float reach, float r2,
+    float scale, int accumulate, float* __restrict__ L, int* __restrict__ count) {
+  const int lane = threadIdx.x & 63;
+  // wave-uniform tile index, so that the tile's data and the photon records
+  // are read with scalar loads
+  const int t = __builtin_amdgcn_readfirstlane(xcd_remap(blockIdx.x) * kKdeWaves +
+                                               (int)(threadIdx.x >> 6));
+  if (t >= ntiles) return;
+  const TileInfo ti = tiles[t];
+  const int qi = ti.start + min(lane, ti.count - 1);
+  const float4 p = xq[qi];
+  const int o = perm[qi];
+  const int k = xsurf[o];
+  const float4 lo = tlo[t], hi = thi[t];
+  const int3 c0 = pcell(g, lo.x - reach, lo.y - reach, lo.z - reach);
+  const int3 c1 = pcell(g, hi.x + reach, hi.y + reach, hi.z + reach);
+  float s0 = 0.f, s1 = 0.f, s2 = 0.f;
+  int cnt = 0;
+  auto visit = [&](const float4& ph, const float4& w) {
+    float d2;
+    {
+#pragma clang fp contract(off)
+      const float dx = p.x - ph.x, dy = p.y - ph.y, dz = p.z - ph.z;
+      d2 = (dx * dx + dy * dy) + dz * dz;
+    }
+    const bool in = (__float_as_int(ph.w) == k) & (d2 <= r2);
+    // fma(1, w, s) rounds like s + w and fma(0, w, s) = s: the same sums as a
+    // branch, one instruction per channel
+    const float mf = in ? 1.f : 0.f;
+    s0 = fmaf(mf, w.x, s0);
+    s1 = fmaf(mf, w.y, s1);
+    s2 = fmaf(mf, w.z, s2);
+    cnt += in ? 1 : 0;
+  };
+  for (int zc = c0.z; zc <= c1.z; ++zc)
+    for (int yc = c0.y; yc <= c1.y; ++yc) {
+      const int row = (zc * g.dy + yc) * g.dx;
+      const int a = start[row + c0.x], b = start[row + c1.x + 1];
+      int s = a;
+      // four records per round: their scalar loads are issued together
+      for (; s + 4 <= b; s += 4) {
+        const float4 q0 = rec[2 * s], w0 = rec[2 * s + 1];
+        const float4 q1 = rec[2 * s + 2], w1 = rec[2 * s + 3];
+        const float4 q2 = rec[2 * s + 4], w2 = rec[2 * s + 5];
+        const float4 q3 = rec[2 * s + 6], w3 = rec[2 * s + 7];
+        visit(q0, w0);
+        visit(q1, w1);
+        visit(q2, w2);
+        visit(q3, w3);
+      }
+      for (; s < b; ++s) visit(rec[2 * s], rec[2 * s + 1]);
+    }
+  if (lane >= ti.count) return;
+  if (k >= 0 && k <= 4) {
+    s0 *= kAlbedo[k][0] * scale;
+    s1 *= kAlbedo[k][1] * scale;
+    s2 *= kAlbedo[k][2] * scale;
+  } else {
+    s0 = s1 = s2 = 0.f;
+    cnt = 0;
+  }
+  const int64_t oi = (int64_t)o * 3;
+  if (accumulate) {
+    L[oi] += s0;
+    L[oi + 1] += s1;
+    L[oi + 2] += s2;
+  } else {
+    L[oi] = s0;
+    L[oi + 1] = s1;
+    L[oi + 2] = s2;
+  }
+  if (count) count[o] = cnt;
 }
 
 }  // namespace
@@ -264,8 +351,7 @@ struct gpf_photon_map {
   int64_t np = 0, cells = 0;
   float r = 0.f;
   int* start = nullptr;      // [cells + 1] exclusive prefix of photons per cell
-  float4* spos = nullptr;    // [np] (x, y, z, face bits) in cell order
-  float4* spw = nullptr;     // [np] (power, 0) in cell order
+  float4* rec = nullptr;     // [2 np] (x, y, z, face bits), (power, 0) in cell order
 };
 
 namespace gpf {
@@ -273,8 +359,7 @@ namespace gpf {
 void photon_map_free(gpf_photon_map* m) {
   if (!m) return;
   dev_free(m->start, (m->cells + 1) * 4);
-  dev_free(m->spos, m->np * sizeof(float4));
-  dev_free(m->spw, m->np * sizeof(float4));
+  dev_free(m->rec, 2 * m->np * sizeof(float4));
   delete m;
 }
 
@@ -315,8 +400,7 @@ gpf_status photon_map_build(const float* ppos, const float* ppw, const int* psur
     dev_free(tmp, tb);
   };
   if ((st = dev_alloc((void**)&m->start, (cells + 1) * 4, "photon cells")) != GPF_OK ||
-      (st = dev_alloc((void**)&m->spos, np * sizeof(float4), "photon records")) != GPF_OK ||
-      (st = dev_alloc((void**)&m->spw, np * sizeof(float4), "photon records")) != GPF_OK ||
+      (st = dev_alloc((void**)&m->rec, 2 * np * sizeof(float4), "photon records")) != GPF_OK ||
       (st = dev_alloc((void**)&cnt, (cells + 1) * 4, "photon cells")) != GPF_OK ||
       (st = dev_alloc((void**)&val, np * 4, "photon order")) != GPF_OK ||
       (st = dev_alloc((void**)&sorted, np * 4, "photon order")) != GPF_OK ||
@@ -353,7 +437,7 @@ gpf_status photon_map_build(const float* ppos, const float* ppw, const int* psur
     e = rocprim::radix_sort_pairs(tmp, sort_b, key, key_s, val, sorted, (size_t)np, 0, bits, s);
   if (e == hipSuccess) {
     hipLaunchKernelGGL(photon_gather_kernel, dim3(pb), dim3(256), 0, s, sorted, np, ppos, ppw,
-                       psurf, m->spos, m->spw);
+                       psurf, m->rec);
     e = hipGetLastError();
   }
   if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -372,7 +456,25 @@ gpf_status photon_map_gather(const gpf_photon_map* m, const float* x, const int*
   const float r2 = r * r;
   const float scale = (float)((double)weight / (M_PI * M_PI * (double)r * (double)r));
   hipLaunchKernelGGL(kde_kernel, dim3((unsigned)((q + 255) / 256)), dim3(256), 0, s, x, xs, q, m->g,
-                     m->start, m->spos, m->spw, r2, scale, accumulate ? 1 : 0, L, count);
+                     m->start, m->rec, r2, scale, accumulate ? 1 : 0, L, count);
+  GPF_HIP(hipGetLastError());
+  return GPF_OK;
+}
+
+gpf_status photon_map_gather_binned(const gpf_photon_map* m, const gpf_queries* qs,
+                                    const int* xs, float weight, bool accumulate, float* L,
+                                    int* count, hipStream_t s) {
+  if (qs->ntiles == 0) return GPF_OK;
+  const float r = m->r;
+  const float r2 = r * r;
+  // the candidate range only needs to contain the discs; widening it adds
+  // candidates, never results
+  const float reach = r * 1.0001f + 1e-6f;
+  const float scale = (float)((double)weight / (M_PI * M_PI * (double)r * (double)r));
+  const int64_t blocks = (qs->ntiles + kKdeWaves - 1) / kKdeWaves;
+  hipLaunchKernelGGL(kde_tile_kernel, dim3(xcd_grid(blocks)), dim3(kKdeWaves * 64), 0, s, qs->xs,
+                     qs->perm, qs->tiles, qs->tile_lo, qs->tile_hi, (int)qs->ntiles, xs, m->g,
+                     m->start, m->rec, reach, r2, scale, accumulate ? 1 : 0, L, count);
   GPF_HIP(hipGetLastError());
   return GPF_OK;
 }

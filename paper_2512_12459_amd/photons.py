@@ -130,7 +130,7 @@ def mlp_targets(power, d2, mu, quat, log_scale, rgb) -> torch.Tensor:
 
 
 # ----------------------------------------------------------------------------
-# Photon tracing and the photon density estimate (Sec. 3 photon pass and
+# Photon tracing and the photon density estimate (Sec. 3.2 photon pass and
 # radiance estimation; Sec. 4.3 reference equation)
 # ----------------------------------------------------------------------------
 LIGHT = (0.4, 0.6)
@@ -223,10 +223,20 @@ class PhotonMap:
         self.n = ppos.shape[0]
 
     def gather(self, x, x_surface, weight: float = 1.0, out=None, accumulate: bool = False,
-               count=None):
+               count=None, queries=None):
         """weight * density estimate at x (added into `out` when accumulate);
-        asynchronous on the current stream."""
+        asynchronous on the current stream.  With `queries` (a radiance
+        QuerySet built over x) the points are gathered tile by tile, with the
+        same bits."""
         out = _check_points(x, x_surface, out, accumulate, count)
+        if queries is not None:
+            if queries.x is not x and queries.x.data_ptr() != x.data_ptr():
+                raise ValueError("queries must be the query set of x")
+            C.check(C.lib().gpf_photon_map_gather_binned(self.handle, queries.handle,
+                                                         C.ptr(x_surface), float(weight),
+                                                         1 if accumulate else 0, C.ptr(out),
+                                                         C.ptr(count), _stream()))
+            return out
         C.check(C.lib().gpf_photon_map_gather(self.handle, C.ptr(x), C.ptr(x_surface), x.shape[0],
                                               float(weight), 1 if accumulate else 0, C.ptr(out),
                                               C.ptr(count), _stream()))
@@ -263,7 +273,7 @@ def photon_density(x: torch.Tensor, x_surface: torch.Tensor, ppos: torch.Tensor,
 
 def sppm_radii(T: int, r0: float, alpha: float = 0.7):
     """Radius of each progressive iteration: r_1 = r0, r_{t+1} = r_t *
-    sqrt((t + alpha) / (t + 1)) (Sec. 4.3 implementation details)."""
+    sqrt((t + alpha) / (t + 1)) (supplementary Sec. A.1)."""
     r = [float(r0)]
     for t in range(1, int(T)):
         r.append(r[-1] * math.sqrt((t + alpha) / (t + 1)))
@@ -276,11 +286,16 @@ def sppm_reference(x: torch.Tensor, x_surface: torch.Tensor, iters: int, n_paths
     """Progressive reference radiance (Sec. 4.3 reference equation): the mean
     over `iters` iterations of the density estimate from a fresh photon map
     (key seed + t - 1) with the shrinking radius of sppm_radii."""
+    from .radiance import QuerySet
     out = torch.zeros((x.shape[0], 3), dtype=torch.float32, device=x.device)
+    qs = QuerySet(x, 0.025)
     for t, r in enumerate(sppm_radii(iters, r0, alpha), start=1):
         rec = trace_photons(n_paths, seed + t - 1, max_events, light, sphere, x.device)
         ppos, ppw, psurf = compact_photons(*rec)
         if ppos.shape[0] == 0:
             continue
-        photon_density(x, x_surface, ppos, ppw, psurf, r, 1.0 / iters, out, accumulate=True)
+        pm = PhotonMap(ppos, ppw, psurf, r)
+        pm.gather(x, x_surface, 1.0 / iters, out, accumulate=True, queries=qs)
+        pm.close()
+    qs.close()
     return out

@@ -2,10 +2,10 @@
 
 The pipeline of Sec. 4 with every stage in libgpf.so:
 
-1. one photon-tracing iteration (Sec. 3 photon pass) gives the photon map
+1. one photon-tracing iteration (Sec. 3.2 photon pass) gives the photon map
    that seeds the field, one Gaussian per stored photon (Sec. 4.1);
 2. each seed Gaussian's radiance is the density estimate at its own photon
-   (Sec. 3 radiance estimation, radius r0), so that flux becomes the radiance
+   (Sec. 3.2 radiance estimation, radius r0), so that flux becomes the radiance
    the query returns;
 3. the targets are the progressive reference (Sec. 4.3 reference equation)
    at the first diffuse hits of the camera ring, from `ref_iters` further

@@ -1,4 +1,4 @@
-"""GPU parity of photon tracing and the photon density estimate (Sec. 3 photon
+"""GPU parity of photon tracing and the photon density estimate (Sec. 3.2 photon
 pass and radiance estimation; Sec. 4.3 reference equation) against the FP64
 oracle, through the C ABI:
 
@@ -204,16 +204,50 @@ def test_density_matches_oracle(ph, r):
     L = ph.photon_density(dx, dxs, dp, dw, ds, r, count=cnt)
     _check_density(L.cpu().numpy(), ref, counts)
     assert np.array_equal(cnt.cpu().numpy(), counts)      # membership decided identically
-    # a map built once and gathered twice gives the same bits
+    # a map built once and gathered twice gives the same bits, and so does
+    # the tile-by-tile gather over the binned points
+    from paper_2512_12459_amd import radiance as R
     pm = ph.PhotonMap(dp, dw, ds, r)
     for _ in range(2):
         assert torch.equal(pm.gather(dx, dxs), L)
+    for cell in (0.0125, 0.05):
+        qs = R.QuerySet(dx, cell)
+        cnt_b = torch.empty_like(cnt)
+        assert torch.equal(pm.gather(dx, dxs, queries=qs, count=cnt_b), L)
+        assert torch.equal(cnt_b, cnt)
+        qs.close()
     pm.close()
     assert np.all(ref[xs > 4] == 0) and (ref[xs <= 4] > 0).mean() > 0.9
     # weight and accumulation: L + 0.5 * estimate
     L2 = ph.photon_density(dx, dxs, dp, dw, ds, r, weight=0.5, out=L.clone(), accumulate=True)
     np.testing.assert_allclose(L2.cpu().numpy(), 1.5 * ref, rtol=(counts.max() + 8) * 2.0 ** -24,
                                atol=1e-30)
+
+
+def test_binned_gather_at_camera_hits_equals_the_plain_gather(ph):
+    # full-size shape: the diffuse first hits of 8 ring views at 512^2 and the
+    # photon map of 200,000 traced paths; both gathers sum the same photons in
+    # the same order, so they agree bit for bit
+    from paper_2512_12459_amd import radiance as R
+    from paper_2512_12459_amd import scenes as S
+    say("case: binned gather, 8 ring views at 512^2, 200000 paths")
+    x, sid = S.hit_points(S.camera_ring(8, 512), return_surface=True)
+    keep = sid <= 4
+    dx, dxs = _dev(np.ascontiguousarray(x[keep]), sid[keep].astype(np.int32))
+    ppos, ppw, psurf = ph.compact_photons(*ph.trace_photons(200000, 12, 8))
+    pm = ph.PhotonMap(ppos, ppw, psurf, 0.02)
+    c0 = torch.empty(dx.shape[0], dtype=torch.int32, device="cuda")
+    c1 = torch.empty_like(c0)
+    L0 = pm.gather(dx, dxs, count=c0)
+    qs = R.QuerySet(dx, 0.025)
+    L1 = pm.gather(dx, dxs, queries=qs, count=c1)
+    torch.cuda.synchronize()
+    say(f"  {dx.shape[0]} points, {int(c0.sum())} gathered photons")
+    assert torch.equal(L0, L1) and torch.equal(c0, c1)
+    # accumulation over two calls
+    L2 = pm.gather(dx, dxs, 0.5, out=L1.clone(), accumulate=True, queries=qs)
+    L3 = pm.gather(dx, dxs, 0.5, out=L0.clone(), accumulate=True)
+    assert torch.equal(L2, L3)
 
 
 def test_density_single_photon_and_point(ph):

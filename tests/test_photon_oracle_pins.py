@@ -1,4 +1,4 @@
-"""Pins for the photon-tracing oracle (Sec. 3 photon pass; Sec. 4.3 reference
+"""Pins for the photon-tracing oracle (Sec. 3.2 photon pass; Sec. 4.3 reference
 estimate): its generator against numpy's library Philox, its emission against
 the moments of a cosine source, its first-hit statistics against the closed
 form of the view factor from a differential area to a parallel rectangle, its
