@@ -24,8 +24,9 @@ single and double precision.
 Path of photon i (power PHI_LIGHT / n_paths), event 0 = emission: position
 (0.4 + 0.2 u0, 1, 0.4 + 0.2 u1); direction (r cos p, -sqrt(1 - u3), r sin p),
 p = 2 pi u2, r = sqrt(u3).  Then for events j = 1 .. max_events, with the
-uniforms of counter (i, j): the nearest intersection beyond T_EPS among the
-sphere and the box faces (the open side ends the path);
+uniforms of counter (i, j): the nearest intersection among the sphere (beyond
+T_EPS, so a path leaving the sphere does not meet it again at once) and the box
+faces it moves out through (the open side ends the path);
   * sphere: exact unpolarised Fresnel reflectance F of the dielectric
     boundary (total internal reflection gives F = 1); reflect when u0 < F,
     otherwise refract by Snell's law; the power is unchanged.  With
@@ -129,18 +130,22 @@ FACE_B = np.array([[1, 0, 0], [0, 0, 1], [0, 0, 1], [0, 1, 0], [0, 1, 0]], F64)
 
 def box_exit(o, d):
     """Nearest face crossing ahead of o along d: (t, face, margin), face -1 =
-    the open side z = 1; margin = gap to the second-nearest crossing."""
+    the open side z = 1; margin = gap to the second-nearest crossing.  Only
+    faces the direction leaves through count (so the face a photon sits on,
+    which it leaves inwards, never does), and a point on or past such a face
+    meets it at once (t = 0): a path that starts on an edge of the box cannot
+    slip out through the neighbouring face.  Ties go to the lower face
+    index."""
     n = o.shape[0]
     ts = np.full((n, 6), np.inf)
     with np.errstate(divide="ignore", invalid="ignore"):
-        ts[:, 0] = np.where(d[:, 1] < 0, (0.0 - o[:, 1]) / d[:, 1], np.inf)
-        ts[:, 1] = np.where(d[:, 1] > 0, (1.0 - o[:, 1]) / d[:, 1], np.inf)
-        ts[:, 2] = np.where(d[:, 0] < 0, (0.0 - o[:, 0]) / d[:, 0], np.inf)
-        ts[:, 3] = np.where(d[:, 0] > 0, (1.0 - o[:, 0]) / d[:, 0], np.inf)
-        ts[:, 4] = np.where(d[:, 2] < 0, (0.0 - o[:, 2]) / d[:, 2], np.inf)
-        ts[:, 5] = np.where(d[:, 2] > 0, (1.0 - o[:, 2]) / d[:, 2], np.inf)
-    ts = np.where(ts > T_EPS, ts, np.inf)
-    order = np.argsort(ts, axis=1)
+        ts[:, 0] = np.where(d[:, 1] < 0, np.maximum((0.0 - o[:, 1]) / d[:, 1], 0.0), np.inf)
+        ts[:, 1] = np.where(d[:, 1] > 0, np.maximum((1.0 - o[:, 1]) / d[:, 1], 0.0), np.inf)
+        ts[:, 2] = np.where(d[:, 0] < 0, np.maximum((0.0 - o[:, 0]) / d[:, 0], 0.0), np.inf)
+        ts[:, 3] = np.where(d[:, 0] > 0, np.maximum((1.0 - o[:, 0]) / d[:, 0], 0.0), np.inf)
+        ts[:, 4] = np.where(d[:, 2] < 0, np.maximum((0.0 - o[:, 2]) / d[:, 2], 0.0), np.inf)
+        ts[:, 5] = np.where(d[:, 2] > 0, np.maximum((1.0 - o[:, 2]) / d[:, 2], 0.0), np.inf)
+    order = np.argsort(ts, axis=1, kind="stable")
     t1 = ts[np.arange(n), order[:, 0]]
     t2 = ts[np.arange(n), order[:, 1]]
     face = np.where(order[:, 0] == 5, -1, order[:, 0])

@@ -59,20 +59,24 @@ __device__ __forceinline__ float dot3(const float a[3], const float b[3]) {
   return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
 }
 
-// Nearest box face crossed ahead of o along d (beyond kTEps): its distance,
-// and the face (5 = the open side, -1 = none).
+// Nearest box face crossed ahead of o along d: its distance and the face
+// (5 = the open side, -1 = none).  Only faces the direction leaves through
+// count (the face a path sits on, which it leaves inwards, never does), and a
+// point on or past such a face meets it at once (distance 0), so a path that
+// starts on an edge cannot slip out through the neighbouring face.  Ties go
+// to the lower face index.
 __device__ __forceinline__ float box_crossing(const float o[3], const float d[3], int& face) {
   float tb = INFINITY;
   face = -1;
-  const float tf[6] = {d[1] < 0.f ? (0.f - o[1]) / d[1] : INFINITY,
-                       d[1] > 0.f ? (1.f - o[1]) / d[1] : INFINITY,
-                       d[0] < 0.f ? (0.f - o[0]) / d[0] : INFINITY,
-                       d[0] > 0.f ? (1.f - o[0]) / d[0] : INFINITY,
-                       d[2] < 0.f ? (0.f - o[2]) / d[2] : INFINITY,
-                       d[2] > 0.f ? (1.f - o[2]) / d[2] : INFINITY};
+  const float tf[6] = {d[1] < 0.f ? fmaxf((0.f - o[1]) / d[1], 0.f) : INFINITY,
+                       d[1] > 0.f ? fmaxf((1.f - o[1]) / d[1], 0.f) : INFINITY,
+                       d[0] < 0.f ? fmaxf((0.f - o[0]) / d[0], 0.f) : INFINITY,
+                       d[0] > 0.f ? fmaxf((1.f - o[0]) / d[0], 0.f) : INFINITY,
+                       d[2] < 0.f ? fmaxf((0.f - o[2]) / d[2], 0.f) : INFINITY,
+                       d[2] > 0.f ? fmaxf((1.f - o[2]) / d[2], 0.f) : INFINITY};
 #pragma unroll
   for (int k = 0; k < 6; ++k)
-    if (tf[k] > kTEps && tf[k] < tb) {
+    if (tf[k] < tb) {
       tb = tf[k];
       face = k;
     }

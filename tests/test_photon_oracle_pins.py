@@ -128,6 +128,24 @@ def test_mirror_sphere_reflects_photons_with_its_reflectance():
     np.testing.assert_allclose(np.einsum("ij,ij->i", np.cross(d[via], nrm), out_dir), 0, atol=1e-9)
 
 
+@pytest.mark.parametrize("sphere", [1, 2])
+def test_stored_photons_lie_on_their_faces_inside_the_box(sphere):
+    # the box is closed but for the z = 1 side: every stored photon lies on
+    # the plane of its face and inside the box, also the ones whose path ran
+    # along an edge (a photon stored within 1e-4 of an edge and sent out
+    # through the neighbouring face must meet that face)
+    out = P.trace(60000, 5, 8, sphere=sphere)
+    st = out["surface"] >= 0
+    pos, face = out["pos"][st], out["surface"][st]
+    assert pos.min() >= -1e-12 and pos.max() <= 1 + 1e-12
+    axis = np.array([1, 1, 0, 0, 2])[face]
+    val = np.array([0.0, 1.0, 0.0, 1.0, 0.0])[face]
+    assert np.abs(pos[np.arange(len(face)), axis] - val).max() <= 1e-12
+    # and some paths do start within 1e-4 of an edge
+    near = np.sort(np.minimum(pos, 1 - pos), axis=1)[:, 1]
+    assert (near < 1e-4).sum() > 3
+
+
 def test_russian_roulette_is_unbiased():
     # at a diffuse face of albedo a (stated values: white 0.73, red (0.63, 0.06,
     # 0.05), green (0.14, 0.45, 0.09)), a photon continues exactly when its
@@ -219,7 +237,7 @@ def test_progressive_reference_of_one_iteration_is_one_density_estimate():
 
 
 @pytest.mark.parametrize("mutation", ["fresnel_swap", "wrong_index", "no_cosine", "rr_biased",
-                                      "philox_round", "light_power"])
+                                      "philox_round", "light_power", "edge_leak"])
 def test_planted_mistakes_are_caught(monkeypatch, mutation):
     if mutation == "fresnel_swap":
         orig = P.fresnel
@@ -249,6 +267,25 @@ def test_planted_mistakes_are_caught(monkeypatch, mutation):
         monkeypatch.setattr(P, "PHI_LIGHT", P.PHI_LIGHT * 1.25)
         with pytest.raises(AssertionError):
             test_traced_density_matches_direct_irradiance_of_the_light()
+    elif mutation == "edge_leak":
+        orig = P.box_exit
+
+        def leaky(o, d):        # faces closer than T_EPS ignored, as a self-hit guard would
+            n = o.shape[0]
+            ts = np.full((n, 6), np.inf)
+            with np.errstate(divide="ignore", invalid="ignore"):
+                for k, (a, v, sgn) in enumerate([(1, 0.0, -1), (1, 1.0, 1), (0, 0.0, -1), (0, 1.0, 1),
+                                                 (2, 0.0, -1), (2, 1.0, 1)]):
+                    ts[:, k] = np.where(sgn * d[:, a] > 0, (v - o[:, a]) / d[:, a], np.inf)
+            ts = np.where(ts > P.T_EPS, ts, np.inf)
+            order = np.argsort(ts, axis=1, kind="stable")
+            t1 = ts[np.arange(n), order[:, 0]]
+            t2 = ts[np.arange(n), order[:, 1]]
+            return t1, np.where(order[:, 0] == 5, -1, order[:, 0]), t2 - t1
+        assert orig is not leaky
+        monkeypatch.setattr(P, "box_exit", leaky)
+        with pytest.raises(AssertionError):
+            test_stored_photons_lie_on_their_faces_inside_the_box(1)
     elif mutation == "philox_round":
         orig = P.philox4x64
         monkeypatch.setattr(P, "philox4x64", lambda *a, rounds=10: orig(*a, rounds=9))
