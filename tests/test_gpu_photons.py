@@ -94,9 +94,13 @@ def test_trace_full_size_sampled_paths(ph):
     sample = [t[ri].cpu().numpy() for t in gpu]
     ref = _oracle_with_conditioning(n, seed, E, paths=rows)
     _compare_paths(sample, ref)
-    stored = int((gpu[2] >= 0).sum())
+    st = gpu[2] >= 0
+    stored = int(st.sum())
     say(f"  stored {stored} photons from {n} paths")
     assert stored > n
+    # every stored photon of the launch lies inside the closed box
+    p = gpu[0][st]
+    assert float(p.min()) >= -1e-6 and float(p.max()) <= 1 + 1e-6
 
 
 def test_floor_share_of_a_point_light(ph):
