@@ -15,6 +15,12 @@ The pipeline of Sec. 4 with every stage in libgpf.so:
     python -m paper_2512_12459_amd.traced [--paths 100000] [--ref-iters 64]
         [--views 8 --res 256] [--steps 300] [--query hybrid]
 
+With ``--compare`` it instead trains the learned initialiser on fits from
+traced photon maps (other seeds, fitted to the reference of a different
+camera ring) and then fits the held-out photon map twice, from the plain and
+from the learned initialisation, reporting steps and wall time to each PSNR
+level.
+
 Prints one JSON object.
 """
 from __future__ import annotations
@@ -27,6 +33,7 @@ import time
 import numpy as np
 import torch
 
+from . import learned_init as LI
 from . import photons as PH
 from . import radiance as R
 from . import scenes as S
@@ -87,6 +94,76 @@ def run(n_paths=100_000, ref_iters=64, ref_paths=None, views=8, res=256, steps=3
                 ref_mean=T.mean(dim=0).tolist(), history=hist)
 
 
+LEVELS = (40.0, 45.0, 50.0, 55.0, 60.0)
+
+
+def build_traced_dataset(seeds, n_paths, x, xs, T, fit_steps=200, r0=0.02, query="hybrid",
+                         cell=0.025, log=None):
+    """(X [m,96] bfloat16, Y [m,10]) from photon maps of the given seeds, each
+    seeding a field by the plain initialisation that is then fitted to the
+    targets T at points x."""
+    qs = R.QuerySet(x, cell)
+    Xs, Ys = [], []
+    t0 = time.perf_counter()
+    for i, seed in enumerate(seeds):
+        ppos, ppw, psurf = photon_map(n_paths, seed)
+        Lp = PH.photon_density(ppos, psurf, ppos, ppw, psurf, r0)
+        f = Field(*PH.init_from_photons(ppos, Lp, k=16))
+        Fitter(f, qs, T, query=query).run(fit_steps)
+        idx, d2 = PH.photon_knn(ppos, 16)
+        Xs.append(PH.photon_features(ppos, Lp, idx, d2))
+        Ys.append(PH.mlp_targets(Lp, d2, *f.arrays()))
+        if log and (i + 1) % max(1, len(seeds) // 10) == 0:
+            log(f"dataset: {i + 1}/{len(seeds)} photon maps fitted ({time.perf_counter() - t0:.1f} s)")
+    qs.close()
+    return torch.cat(Xs), torch.cat(Ys)
+
+
+def compare_traced(n_paths=100_000, train_maps=64, train_views=6, views=8, res=256, ref_iters=64,
+                   fit_steps=200, epochs=20, max_steps=600, target=60.0, r0=0.02, query="hybrid",
+                   cell=0.025, eval_seed=1, train_res=None, log=log):
+    dev = "cuda"
+    t0 = time.perf_counter()
+    # training data: other photon maps fitted to the reference of another ring
+    xt, xst = diffuse_points(train_views, train_res or res)
+    xtd, xstd = torch.from_numpy(xt).to(dev), torch.from_numpy(xst).to(dev)
+    Tt = PH.sppm_reference(xtd, xstd, ref_iters, n_paths, 50_000, r0=r0)
+    X, Y = build_traced_dataset(list(range(1000, 1000 + train_maps)), n_paths, xtd, xstd, Tt,
+                                fit_steps, r0, query, cell, log)
+    t_data = time.perf_counter() - t0
+    net, hist = LI.train(X, Y, epochs, log=log)
+    t_train = time.perf_counter() - t0 - t_data
+    # evaluation: the held-out map, the evaluation ring and its reference
+    x, xs = diffuse_points(views, res)
+    xd, xsd = torch.from_numpy(x).to(dev), torch.from_numpy(xs).to(dev)
+    T = PH.sppm_reference(xd, xsd, ref_iters, n_paths, 2_000, r0=r0)
+    qs = R.QuerySet(xd, cell)
+    out = {}
+    for name, mlp in (("plain", None), ("learned", net)):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ppos, ppw, psurf = photon_map(n_paths, eval_seed)
+        f = Field(*seed_field(ppos, ppw, psurf, r0, mlp=mlp))
+        torch.cuda.synchronize()
+        t_init = time.perf_counter() - t1
+        fitter = Fitter(f, qs, T, query=query)
+        p0 = fitter.current_psnr()
+        r_ = fitter.run(max_steps, target, 10, log=lambda m: log(f"[{name}] {m}"))
+        h = r_["history"]
+        levels = {}
+        for lv in sorted(set(LEVELS + (target,))):
+            hit = next((e for e in h if e[1] >= lv), None)
+            levels[f"{lv:g}"] = None if hit is None else dict(steps=hit[0], seconds=t_init + hit[2])
+        out[name] = dict(gaussians=f.n, init_psnr=p0, init_seconds=t_init, final_psnr=h[-1][1],
+                         steps_run=h[-1][0], steps_to_target=r_["reached"],
+                         seconds_to_target=(t_init + r_["seconds"]) if r_["reached"] else None,
+                         levels=levels, history=h)
+        log(f"{name}: init {p0:.2f} dB, target reached at {r_['reached']}")
+    return dict(n_paths=n_paths, q=int(x.shape[0]), query=query, target_psnr=target, runs=out,
+                training=dict(maps=train_maps, views=train_views, samples=int(X.shape[0]),
+                              dataset_seconds=t_data, train_seconds=t_train, epoch_mse=hist))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--paths", type=int, default=100_000)
@@ -97,8 +174,19 @@ def main():
     ap.add_argument("--steps", type=int, default=300)
     ap.add_argument("--query", choices=("truncated", "hybrid"), default="hybrid")
     ap.add_argument("--r0", type=float, default=0.02)
+    ap.add_argument("--compare", action="store_true")
+    ap.add_argument("--train-maps", type=int, default=64)
+    ap.add_argument("--train-views", type=int, default=6)
+    ap.add_argument("--train-res", type=int, default=None)
+    ap.add_argument("--fit-steps", type=int, default=200)
+    ap.add_argument("--target", type=float, default=60.0)
     a = ap.parse_args()
-    out = run(a.paths, a.ref_iters, a.ref_paths, a.views, a.res, a.steps, a.query, a.r0)
+    if a.compare:
+        out = compare_traced(a.paths, a.train_maps, a.train_views, views=a.views, res=a.res,
+                             ref_iters=a.ref_iters, fit_steps=a.fit_steps, max_steps=a.steps,
+                             target=a.target, r0=a.r0, query=a.query, train_res=a.train_res)
+    else:
+        out = run(a.paths, a.ref_iters, a.ref_paths, a.views, a.res, a.steps, a.query, a.r0)
     print(json.dumps(out))
 
 
