@@ -311,3 +311,17 @@ def test_single_path_single_event(ph):
     ref = _oracle_with_conditioning(1, 0, 1)
     if ref["ambiguous"][0] == 1 and ref["stable"][0]:
         _compare_paths(gpu, ref)
+
+
+def test_fitting_from_traced_photons_raises_psnr(ph):
+    """The pipeline of traced.py at a small size: one traced photon map seeds
+    the field (each Gaussian's flux from the density estimate at its photon),
+    the targets are the progressive reference at the diffuse hits of two
+    ring views, and fitting with the hybrid query raises PSNR."""
+    from paper_2512_12459_amd import traced
+    say("case: fitting from traced photons, 20000 paths, 2 views at 64^2")
+    out = traced.run(n_paths=20000, ref_iters=8, views=2, res=64, steps=60, check_every=20)
+    say(f"  {out['gaussians']} Gaussians, {out['q']} points: {out['init_psnr']:.2f} -> "
+        f"{out['final_psnr']:.2f} dB")
+    assert out["gaussians"] > 20000 and out["q"] > 5000
+    assert out["final_psnr"] > out["init_psnr"] + 5.0
