@@ -68,7 +68,7 @@ def pinhole_rays(eye, target, up, vfov_deg, width, height):
 
 
 def integrate(o, d, samples, seed, max_depth=16, sphere=GLASS, light=(P.LIGHT_LO, P.LIGHT_HI),
-              margin=1e-6, jitter=0.0, jitter_seed=0):
+              margin=1e-6, jitter=0.0, jitter_seed=0, first_ray=None):
     """Camera paths for rays (o, d) [m,3], `samples` per ray.  Returns dict of
     arrays over the m * samples paths: x [.,3], face [.] (0..4 diffuse hit,
     -1 none), beta [.,3] (at the diffuse hit), Le [.,3] (emitted radiance
@@ -76,11 +76,17 @@ def integrate(o, d, samples, seed, max_depth=16, sphere=GLASS, light=(P.LIGHT_LO
     of the first decision within `margin` of its threshold, max_depth + 1 if
     none).  jitter > 0 perturbs every segment's origin and direction by
     uniform offsets in [-jitter, jitter] per coordinate, to measure each
-    record's sensitivity to rounding."""
+    record's sensitivity to rounding.  `first_ray` [m] gives the image index
+    of each ray when (o, d) is a subset of an image's rays, so that path
+    numbers (and their random numbers) are those of the whole image."""
     jrng = np.random.default_rng(jitter_seed) if jitter > 0 else None
     m = o.shape[0]
     n = m * samples
-    k = np.arange(n, dtype=np.uint64)
+    if first_ray is None:
+        k = np.arange(n, dtype=np.uint64)
+    else:
+        k = (np.repeat(np.asarray(first_ray, np.uint64) * np.uint64(samples), samples)
+             + np.tile(np.arange(samples, dtype=np.uint64), m))
     o = np.repeat(np.asarray(o, np.float64), samples, axis=0)
     d = np.repeat(np.asarray(d, np.float64), samples, axis=0)
     if jrng is not None:

@@ -40,51 +40,70 @@ def _views(res):
     return S.camera_ring(2, res) + [up_view]
 
 
-def _oracle(cam, samples, seed, sphere, max_depth=16):
+def _oracle(cam, samples, seed, sphere, max_depth=16, pixels=None):
     """Oracle paths from the camera parameters as the library receives them
-    (FP32), plus each record's sensitivity to rounding and path stability."""
+    (FP32), plus each record's sensitivity to rounding and path stability;
+    `pixels` restricts them to a subset of the image."""
     f32 = [np.asarray(getattr(cam, k), np.float32).astype(np.float64) for k in ("eye", "target", "up")]
     o, d = CO.pinhole_rays(*f32, float(np.float32(cam.vfov_deg)), cam.width, cam.height)
-    ref = CO.integrate(o, d, samples, seed, max_depth, sphere, margin=MARGIN)
+    if pixels is not None:
+        o, d = o[pixels], d[pixels]
+    ref = CO.integrate(o, d, samples, seed, max_depth, sphere, margin=MARGIN, first_ray=pixels)
     cond = np.zeros(ref["face"].shape)
     stable = np.ones(ref["face"].shape, bool)
     for js in (1, 2):
         j = CO.integrate(o, d, samples, seed, max_depth, sphere, margin=MARGIN, jitter=2.0 ** -23,
-                         jitter_seed=js)
+                         jitter_seed=js, first_ray=pixels)
         stable &= (j["face"] == ref["face"]) & ((j["Le"] > 0).any(1) == (ref["Le"] > 0).any(1))
         cond = np.maximum(cond, np.abs(j["x"] - ref["x"]).max(axis=1))
     ref["cond"], ref["stable"] = cond, stable
     return ref
 
 
+def _compare(x, beta, face, Le, ref):
+    """GPU path records against the oracle's on the paths clear of its margin
+    and stable under rounding-size perturbations; returns (paths, diffuse,
+    lit) counts."""
+    ok = ref["stable"] & (ref["ambiguous"] > 16)
+    assert ok.mean() > 0.99, ok.mean()
+    assert np.array_equal(face[ok], ref["face"][ok]), "path ends differ"
+    lit = ok & (ref["Le"] > 0).any(axis=1)
+    np.testing.assert_allclose(Le[ok], ref["Le"][ok], rtol=1e-5, atol=0)
+    dif = ok & (ref["face"] >= 0)
+    err = np.abs(x[dif] - ref["x"][dif]).max(axis=1)
+    bar = 32 * ref["cond"][dif] + 4e-6
+    say(f"  {dif.sum()} diffuse, {lit.sum()} on the light; hit error max {err.max():.2e}, "
+        f"max error / bar {np.max(err / bar):.3f}")
+    assert np.all(err <= bar)
+    np.testing.assert_allclose(beta[dif], ref["beta"][dif], rtol=1e-5)
+    assert np.all(x[face < 0] == 0) and np.all(beta[face < 0] == 0)
+    return ok.sum(), dif.sum(), lit.sum()
+
+
 @pytest.mark.parametrize("sphere", [CO.GLASS, CO.MIRROR])
 def test_camera_paths_match_oracle(cm, sphere):
     samples = 4
-    tot = dict(paths=0, diffuse=0, lit=0)
+    tot = np.zeros(3, np.int64)
     for i, cam in enumerate(_views(48)):
         seed = 100 + i
         say(f"case: camera view {i} {cam.width}x{cam.height} samples={samples} sphere={sphere}")
-        x, beta, face, Le = (t.cpu().numpy() for t in cm.trace_camera(cam, samples, seed,
-                                                                      sphere=sphere))
-        ref = _oracle(cam, samples, seed, sphere)
-        ok = ref["stable"] & (ref["ambiguous"] > 16)
-        assert ok.mean() > 0.99, ok.mean()
-        assert np.array_equal(face[ok], ref["face"][ok]), "path ends differ"
-        lit = ok & (ref["Le"] > 0).any(axis=1)
-        np.testing.assert_allclose(Le[ok], ref["Le"][ok], rtol=1e-5, atol=0)
-        dif = ok & (ref["face"] >= 0)
-        err = np.abs(x[dif] - ref["x"][dif]).max(axis=1)
-        bar = 32 * ref["cond"][dif] + 4e-6
-        say(f"  {dif.sum()} diffuse, {lit.sum()} on the light; hit error max {err.max():.2e}, "
-            f"max error / bar {np.max(err / bar):.3f}")
-        assert np.all(err <= bar)
-        np.testing.assert_allclose(beta[dif], ref["beta"][dif], rtol=1e-5)
-        assert np.all(x[face < 0] == 0) and np.all(beta[face < 0] == 0)
-        tot["paths"] += ok.sum()
-        tot["diffuse"] += dif.sum()
-        tot["lit"] += lit.sum()
-    say(f"  totals {tot}")
-    assert tot["lit"] > 100 and tot["diffuse"] > 10000
+        rec = (t.cpu().numpy() for t in cm.trace_camera(cam, samples, seed, sphere=sphere))
+        tot += np.array(_compare(*rec, _oracle(cam, samples, seed, sphere)))
+    say(f"  totals (paths, diffuse, lit) {tot}")
+    assert tot[2] > 100 and tot[1] > 10000
+
+
+def test_camera_full_size_sampled(cm):
+    # the benchmark's launch: one ring view at 1024x1024, one path per pixel,
+    # glass sphere; 20,000 sampled pixels against the oracle
+    cam = S.camera_ring(1, 1024)[0]
+    say("case: camera 1024x1024, 20000 sampled pixels")
+    rec = cm.trace_camera(cam, 1, 7, sphere=CO.GLASS)
+    pix = np.sort(np.random.default_rng(3).choice(1024 * 1024, 20000, replace=False))
+    ri = torch.from_numpy(pix).cuda()
+    x, beta, face, Le = (t[ri].cpu().numpy() for t in rec)
+    n, dif, lit = _compare(x, beta, face, Le, _oracle(cam, 1, 7, CO.GLASS, pixels=pix))
+    assert dif > 15000
 
 
 def test_compaction_keeps_the_diffuse_hits_in_path_order(cm):

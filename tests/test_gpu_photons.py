@@ -254,6 +254,37 @@ def test_binned_gather_at_camera_hits_equals_the_plain_gather(ph):
     assert torch.equal(L2, L3)
 
 
+def test_density_full_size_sampled(ph):
+    # the launch configuration the benchmark times: the diffuse first hits of
+    # 32 ring views at 800x800 (15.8M points) binned with cells of 0.025, a
+    # photon map of 100,000 paths gathered at r = 0.02 tile by tile; sampled
+    # points against the oracle's estimate from the same (oracle-traced) map
+    from paper_2512_12459_amd import radiance as R
+    from paper_2512_12459_amd import scenes as S
+    say("case: density at full size (32 views at 800^2, 100000 paths), 3000 sampled points")
+    x, sid = S.hit_points(S.camera_ring(32, 800), return_surface=True)
+    keep = sid <= 4
+    x = np.ascontiguousarray(x[keep])
+    xs = sid[keep].astype(np.int32)
+    pos, pw, surf = P.stored_photons(P.trace(100000, 21, 8))
+    ppos, ppw, psurf = pos.astype(np.float32), pw.astype(np.float32), surf.astype(np.int32)
+    dx, dxs, dp, dw, ds = _dev(x, xs, ppos, ppw, psurf)
+    qs = R.QuerySet(dx, 0.025)
+    pm = ph.PhotonMap(dp, dw, ds, 0.02)
+    cnt = torch.empty(dx.shape[0], dtype=torch.int32, device="cuda")
+    L = pm.gather(dx, dxs, queries=qs, count=cnt)
+    sel = np.sort(np.random.default_rng(5).choice(x.shape[0], 3000, replace=False))
+    got = L[torch.from_numpy(sel).cuda()].cpu().numpy()
+    got_cnt = cnt[torch.from_numpy(sel).cuda()].cpu().numpy()
+    ref = P.kde_radiance(x[sel], xs[sel], ppos, ppw, psurf, 0.02)
+    counts = _disc_counts(x[sel], xs[sel], ppos, psurf, 0.02)
+    say(f"  {x.shape[0]} points, {ppos.shape[0]} photons; sampled mean count {counts.mean():.1f}")
+    assert np.array_equal(got_cnt, counts)
+    _check_density(got, ref, counts)
+    pm.close()
+    qs.close()
+
+
 def test_density_single_photon_and_point(ph):
     say("case: density with one photon and one point")
     ppos = np.array([[0.5, 0.0, 0.5]], np.float32)
