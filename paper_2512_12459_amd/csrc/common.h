@@ -94,8 +94,9 @@ struct gpf_grid {
   int cg_dims[3] = {0, 0, 0};
   int64_t cg_cells_cap = 0, cg_n_cap = 0;
   int* cg_start = nullptr;      // [cells + 1]
-  int* cg_fill = nullptr;       // [cells + 1] counts / fill cursors
-  int* cg_sorted = nullptr;     // [n] centre indices by cell
+  unsigned* cg_key = nullptr;   // [n] cell of each centre, then [n] sorted
+  int* cg_val = nullptr;        // [n] centre indices before the sort
+  int* cg_sorted = nullptr;     // [n] centre indices by cell (index order within a cell)
   float* cg_box = nullptr;      // [64 * 6] partial boxes
   void* cg_tmp = nullptr;
   size_t cg_tmp_bytes = 0;

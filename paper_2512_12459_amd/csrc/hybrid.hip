@@ -24,7 +24,7 @@
 //    single-precision weight is exactly zero there whatever the Gaussian: the
 //    search only looks within D (cells of edge just over D/2, two rings), and
 //    nearest centres beyond D, which would add exact zeros, are left out.
-#include <rocprim/device/device_scan.hpp>
+#include <rocprim/device/device_radix_sort.hpp>
 
 #include "pointgrid.h"
 #include "radiance_common.h"
@@ -500,11 +500,13 @@ PGrid centre_geom(const gpf_grid* g) {
 
 void free_centre_grid(gpf_grid* g) {
   dev_free(g->cg_start, (g->cg_cells_cap + 1) * sizeof(int));
-  dev_free(g->cg_fill, (g->cg_cells_cap + 1) * sizeof(int));
+  dev_free(g->cg_key, 2 * g->cg_n_cap * sizeof(unsigned));
+  dev_free(g->cg_val, g->cg_n_cap * sizeof(int));
   dev_free(g->cg_sorted, g->cg_n_cap * sizeof(int));
   dev_free(g->cg_box, kPointBoxBlocks * 6 * sizeof(float));
   dev_free(g->cg_tmp, g->cg_tmp_bytes);
-  g->cg_start = g->cg_fill = g->cg_sorted = nullptr;
+  g->cg_start = g->cg_val = g->cg_sorted = nullptr;
+  g->cg_key = nullptr;
   g->cg_box = nullptr;
   g->cg_tmp = nullptr;
   g->cg_cells_cap = g->cg_n_cap = 0;
@@ -512,9 +514,6 @@ void free_centre_grid(gpf_grid* g) {
   g->cg_bytes = 0;
 }
 
-// Uniform grid over the Gaussian centres (cells of edge just over half the
-// top-up reach, at most kCentreDim per axis), rebuilt with the field.  Reads back
-// the centres' box once.
 gpf_status build_centre_grid(gpf_grid* g, hipStream_t s) {
   const int64_t n = g->n;
   if (!g->cg_box) {
@@ -534,15 +533,23 @@ gpf_status build_centre_grid(gpf_grid* g, hipStream_t s) {
     free_centre_grid(g);
     if ((st = dev_alloc((void**)&g->cg_box, kPointBoxBlocks * 6 * sizeof(float), "centre box")) != GPF_OK ||
         (st = dev_alloc((void**)&g->cg_start, (cells + 1) * sizeof(int), "centre cells")) != GPF_OK ||
-        (st = dev_alloc((void**)&g->cg_fill, (cells + 1) * sizeof(int), "centre cells")) != GPF_OK ||
+        (st = dev_alloc((void**)&g->cg_key, 2 * n * sizeof(unsigned), "centre keys")) != GPF_OK ||
+        (st = dev_alloc((void**)&g->cg_val, n * sizeof(int), "centre order")) != GPF_OK ||
         (st = dev_alloc((void**)&g->cg_sorted, n * sizeof(int), "centre order")) != GPF_OK)
       return st;
     g->cg_cells_cap = cells;
     g->cg_n_cap = n;
-    size_t tb = 0;
-    GPF_HIP(rocprim::exclusive_scan(nullptr, tb, g->cg_fill, g->cg_start, 0, (size_t)(cells + 1),
-                                    rocprim::plus<int>(), s));
-    if ((st = dev_alloc(&g->cg_tmp, tb, "centre scan")) != GPF_OK) return st;
+  }
+  // the sort's scratch depends on n and the key width: grown when needed
+  const int bits = cell_key_bits(cells);
+  size_t tb = 0;
+  GPF_HIP(rocprim::radix_sort_pairs(nullptr, tb, g->cg_key, g->cg_key + n, g->cg_val, g->cg_sorted,
+                                    (size_t)n, 0, bits, s));
+  if (g->cg_tmp_bytes < tb) {
+    dev_free(g->cg_tmp, g->cg_tmp_bytes);
+    g->cg_tmp = nullptr;
+    g->cg_tmp_bytes = 0;
+    if ((st = dev_alloc(&g->cg_tmp, tb, "centre sort")) != GPF_OK) return st;
     g->cg_tmp_bytes = tb;
   }
   g->cg_origin[0] = pg.ox;
@@ -552,17 +559,18 @@ gpf_status build_centre_grid(gpf_grid* g, hipStream_t s) {
   g->cg_dims[0] = pg.dx;
   g->cg_dims[1] = pg.dy;
   g->cg_dims[2] = pg.dz;
+  // centres by cell: a stable radix sort of (cell, index), then the cell
+  // starts by binary search (no atomics, so crowded cells cost nothing extra)
   const unsigned blocks = (unsigned)((n + 255) / 256);
-  GPF_HIP(hipMemsetAsync(g->cg_fill, 0, (cells + 1) * sizeof(int), s));
-  hipLaunchKernelGGL(pcount_kernel, dim3(blocks), dim3(256), 0, s, g->mu, n, pg, g->cg_fill);
-  size_t tb = g->cg_tmp_bytes;
-  GPF_HIP(rocprim::exclusive_scan(g->cg_tmp, tb, g->cg_fill, g->cg_start, 0, (size_t)(cells + 1),
-                                  rocprim::plus<int>(), s));
-  GPF_HIP(hipMemsetAsync(g->cg_fill, 0, (cells + 1) * sizeof(int), s));
-  hipLaunchKernelGGL(pscatter_kernel, dim3(blocks), dim3(256), 0, s, g->mu, n, pg, g->cg_start,
-                     g->cg_fill, g->cg_sorted);
+  hipLaunchKernelGGL(point_key_kernel, dim3(blocks), dim3(256), 0, s, g->mu, n, pg, g->cg_key,
+                     g->cg_val);
+  tb = g->cg_tmp_bytes;
+  GPF_HIP(rocprim::radix_sort_pairs(g->cg_tmp, tb, g->cg_key, g->cg_key + n, g->cg_val,
+                                    g->cg_sorted, (size_t)n, 0, bits, s));
+  hipLaunchKernelGGL(sorted_cell_starts_kernel, dim3((unsigned)((cells + 256) / 256)), dim3(256), 0,
+                     s, g->cg_key + n, n, cells, g->cg_start);
   GPF_HIP(hipGetLastError());
-  g->cg_bytes = (2 * (g->cg_cells_cap + 1) + g->cg_n_cap + kPointBoxBlocks * 6) * sizeof(int) +
+  g->cg_bytes = ((g->cg_cells_cap + 1) + 4 * g->cg_n_cap + kPointBoxBlocks * 6) * sizeof(int) +
                 g->cg_tmp_bytes;
   return GPF_OK;
 }

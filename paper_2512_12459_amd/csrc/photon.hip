@@ -112,17 +112,6 @@ __global__ void __launch_bounds__(256) photon_scatter_kernel(
   if (oslot) oslot[k] = i;
 }
 
-// Cell of each photon (sort key) and its index (sort value).
-__global__ void __launch_bounds__(256) photon_key_kernel(const float* __restrict__ ppos, int64_t np,
-                                                         PGrid g, unsigned* __restrict__ key,
-                                                         int* __restrict__ val) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= np) return;
-  const int3 c = pcell(g, ppos[i * 3], ppos[i * 3 + 1], ppos[i * 3 + 2]);
-  key[i] = (unsigned)((c.z * g.dy + c.y) * g.dx + c.x);
-  val[i] = (int)i;
-}
-
 // Photon records gathered into cell order, two float4 per photon:
 // (x, y, z, face bits) and (power, 0), so that a gather reads each cell's
 // photons as one contiguous run and one photon as one 32-byte load.
@@ -384,15 +373,15 @@ gpf_status photon_map_build(const float* ppos, const float* ppw, const int* psur
   }
   m->cells = (int64_t)m->g.dx * m->g.dy * m->g.dz;
   const int64_t cells = m->cells;
-  // cells: count -> exclusive scan gives the starts; photons: a stable radix
-  // sort by cell, so each cell holds its photons in index order and the
-  // gather's summation order does not depend on scheduling
-  int *cnt = nullptr, *val = nullptr, *sorted = nullptr;
+  // photons by cell: a stable radix sort of (cell, index), so each cell lists
+  // its photons in index order and the gather's summation order does not
+  // depend on scheduling; cell starts by binary search (no atomics, so the
+  // crowded cells of a caustic cost nothing extra)
+  int *val = nullptr, *sorted = nullptr;
   unsigned *key = nullptr, *key_s = nullptr;
   void* tmp = nullptr;
   size_t tb = 0;
   auto cleanup = [&]() {
-    dev_free(cnt, (cells + 1) * 4);
     dev_free(val, np * 4);
     dev_free(sorted, np * 4);
     dev_free(key, np * 4);
@@ -401,7 +390,6 @@ gpf_status photon_map_build(const float* ppos, const float* ppw, const int* psur
   };
   if ((st = dev_alloc((void**)&m->start, (cells + 1) * 4, "photon cells")) != GPF_OK ||
       (st = dev_alloc((void**)&m->rec, 2 * np * sizeof(float4), "photon records")) != GPF_OK ||
-      (st = dev_alloc((void**)&cnt, (cells + 1) * 4, "photon cells")) != GPF_OK ||
       (st = dev_alloc((void**)&val, np * 4, "photon order")) != GPF_OK ||
       (st = dev_alloc((void**)&sorted, np * 4, "photon order")) != GPF_OK ||
       (st = dev_alloc((void**)&key, np * 4, "photon keys")) != GPF_OK ||
@@ -410,32 +398,23 @@ gpf_status photon_map_build(const float* ppos, const float* ppw, const int* psur
     photon_map_free(m);
     return st;
   }
-  int bits = 1;
-  while (bits < 32 && ((int64_t)1 << bits) <= cells) ++bits;
-  size_t scan_b = 0, sort_b = 0;
-  e = rocprim::exclusive_scan(nullptr, scan_b, cnt, m->start, 0, (size_t)(cells + 1),
-                              rocprim::plus<int>(), s);
-  if (e == hipSuccess)
-    e = rocprim::radix_sort_pairs(nullptr, sort_b, key, key_s, val, sorted, (size_t)np, 0, bits, s);
-  tb = std::max(scan_b, sort_b);
+  const int bits = cell_key_bits(cells);
+  e = rocprim::radix_sort_pairs(nullptr, tb, key, key_s, val, sorted, (size_t)np, 0, bits, s);
   if (e == hipSuccess && (st = dev_alloc(&tmp, tb, "photon sort")) != GPF_OK) {
     cleanup();
     photon_map_free(m);
     return st;
   }
   const unsigned pb = (unsigned)((np + 255) / 256);
-  if (e == hipSuccess) e = hipMemsetAsync(cnt, 0, (cells + 1) * 4, s);
   if (e == hipSuccess) {
-    hipLaunchKernelGGL(pcount_kernel, dim3(pb), dim3(256), 0, s, ppos, np, m->g, cnt);
-    hipLaunchKernelGGL(photon_key_kernel, dim3(pb), dim3(256), 0, s, ppos, np, m->g, key, val);
+    hipLaunchKernelGGL(point_key_kernel, dim3(pb), dim3(256), 0, s, ppos, np, m->g, key, val);
     e = hipGetLastError();
   }
   if (e == hipSuccess)
-    e = rocprim::exclusive_scan(tmp, scan_b, cnt, m->start, 0, (size_t)(cells + 1),
-                                rocprim::plus<int>(), s);
-  if (e == hipSuccess)
-    e = rocprim::radix_sort_pairs(tmp, sort_b, key, key_s, val, sorted, (size_t)np, 0, bits, s);
+    e = rocprim::radix_sort_pairs(tmp, tb, key, key_s, val, sorted, (size_t)np, 0, bits, s);
   if (e == hipSuccess) {
+    hipLaunchKernelGGL(sorted_cell_starts_kernel, dim3((unsigned)((cells + 256) / 256)), dim3(256),
+                       0, s, key_s, np, cells, m->start);
     hipLaunchKernelGGL(photon_gather_kernel, dim3(pb), dim3(256), 0, s, sorted, np, ppos, ppw,
                        psurf, m->rec);
     e = hipGetLastError();

@@ -80,6 +80,39 @@ __global__ void pscatter_kernel(const float* __restrict__ pos, int64_t n, PGrid 
   sorted[start[cell] + slot] = (int)i;
 }
 
+// Cell of each point (sort key) and its index (sort value), for a stable
+// radix sort that lists every cell's points in index order without atomics.
+__global__ void point_key_kernel(const float* __restrict__ pos, int64_t n, PGrid g,
+                                 unsigned* __restrict__ key, int* __restrict__ val) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int3 c = pcell(g, pos[i * 3], pos[i * 3 + 1], pos[i * 3 + 2]);
+  key[i] = (unsigned)((c.z * g.dy + c.y) * g.dx + c.x);
+  val[i] = (int)i;
+}
+
+// start[c] = first position of cell c in the sorted keys (c = 0 .. cells;
+// start[cells] = n): a binary search per cell.
+__global__ void sorted_cell_starts_kernel(const unsigned* __restrict__ key_s, int64_t n,
+                                          int64_t cells, int* __restrict__ start) {
+  const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (c > cells) return;
+  int64_t lo = 0, hi = n;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if ((int64_t)key_s[mid] < c) lo = mid + 1;
+    else hi = mid;
+  }
+  start[c] = (int)lo;
+}
+
+// Bits of a radix sort over cell keys 0 .. cells - 1.
+inline int cell_key_bits(int64_t cells) {
+  int bits = 1;
+  while (bits < 32 && ((int64_t)1 << bits) < cells) ++bits;
+  return bits;
+}
+
 // (d2, index) order; FP32 squared distance without fused multiply-add
 __device__ __forceinline__ float sqd(float ax, float ay, float az, float bx, float by, float bz) {
 #pragma clang fp contract(off)
