@@ -97,6 +97,7 @@ struct gpf_grid {
   unsigned* cg_key = nullptr;   // [n] cell of each centre, then [n] sorted
   int* cg_val = nullptr;        // [n] centre indices before the sort
   int* cg_sorted = nullptr;     // [n] centre indices by cell (index order within a cell)
+  unsigned char* cg_near = nullptr;  // [cells] a centre lies within the top-up's rings
   float* cg_box = nullptr;      // [64 * 6] partial boxes
   void* cg_tmp = nullptr;
   size_t cg_tmp_bytes = 0;

@@ -162,10 +162,26 @@ __global__ void __launch_bounds__(kHWaves * 64) hybrid_fwd_kernel(
 // unvisited cell, or until every cell within the reach has been visited.
 // bd/bi hold the k nearest within squared distance reach2 in (d2, index)
 // order; unused slots keep index 0x7fffffff.
+// near[c] = some cell within `rings` cells of c (per axis) holds a centre.
+__global__ void centre_near_kernel(const int* __restrict__ cstart, int dx, int dy, int dz,
+                                   int rings, unsigned char* __restrict__ near) {
+  const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (c >= (int64_t)dx * dy * dz) return;
+  const int x = (int)(c % dx), y = (int)((c / dx) % dy), z = (int)(c / ((int64_t)dx * dy));
+  bool any = false;
+  for (int zc = max(z - rings, 0); zc <= min(z + rings, dz - 1) && !any; ++zc)
+    for (int yc = max(y - rings, 0); yc <= min(y + rings, dy - 1) && !any; ++yc) {
+      const int row = (zc * dy + yc) * dx;
+      any = cstart[row + min(x + rings, dx - 1) + 1] > cstart[row + max(x - rings, 0)];
+    }
+  near[c] = any ? 1 : 0;
+}
+
 // ---------------------------------------------------------------------------
 template <int K>
 __device__ void nearest_centres(float px, float py, float pz, const PGrid& cg,
                                 const int* __restrict__ cstart, const int* __restrict__ csorted,
+                                const unsigned char* __restrict__ near,
                                 const PrimRec* __restrict__ recs, int k, float reach2, int max_rings,
                                 float bd[K], int bi[K]) {
 #pragma unroll
@@ -174,6 +190,8 @@ __device__ void nearest_centres(float px, float py, float pz, const PGrid& cg,
     bi[a] = 0x7fffffff;
   }
   const int3 c = pcell(cg, px, py, pz);
+  // no centre in any cell the rings below would visit: nothing to find
+  if (!near[(c.z * cg.dy + c.y) * cg.dx + c.x]) return;
   const int maxr = min(max_rings, max(cg.dx, max(cg.dy, cg.dz)));
   for (int rr = 0; rr <= maxr; ++rr) {
     for (int zc = c.z - rr; zc <= c.z + rr; ++zc) {
@@ -235,7 +253,8 @@ __device__ __forceinline__ float topup_weight(const PrimRec& r, float px, float 
 template <int K>
 __global__ void __launch_bounds__(256) hybrid_topup_fwd_kernel(
     const float* __restrict__ x, int64_t q, PGrid cg, const int* __restrict__ cstart,
-    const int* __restrict__ csorted, const PrimRec* __restrict__ recs, int k_min, float rb,
+    const int* __restrict__ csorted, const unsigned char* __restrict__ cnear,
+    const PrimRec* __restrict__ recs, int k_min, float rb,
     float reach2, int max_rings, float eps, float* __restrict__ L, float* __restrict__ Zout,
     const int* __restrict__ count) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -243,7 +262,8 @@ __global__ void __launch_bounds__(256) hybrid_topup_fwd_kernel(
   const float px = x[i * 3], py = x[i * 3 + 1], pz = x[i * 3 + 2];
   float bd[K];
   int bi[K];
-  nearest_centres<K>(px, py, pz, cg, cstart, csorted, recs, k_min, reach2, max_rings, bd, bi);
+  nearest_centres<K>(px, py, pz, cg, cstart, csorted, cnear, recs, k_min, reach2, max_rings, bd,
+                     bi);
   float s0 = 0.f, s1 = 0.f, s2 = 0.f, z = 0.f;
 #pragma unroll
   for (int a = 0; a < K; ++a) {
@@ -433,7 +453,8 @@ __global__ void __launch_bounds__(kHWaves * 64) hybrid_bwd_kernel(
 template <int K>
 __global__ void __launch_bounds__(256) hybrid_topup_bwd_kernel(
     const float* __restrict__ x, int64_t q, PGrid cg, const int* __restrict__ cstart,
-    const int* __restrict__ csorted, const PrimRec* __restrict__ recs, int k_min, float rb,
+    const int* __restrict__ csorted, const unsigned char* __restrict__ cnear,
+    const PrimRec* __restrict__ recs, int k_min, float rb,
     float reach2, int max_rings, float eps, const float* __restrict__ Lf,
     const float* __restrict__ Zf, const int* __restrict__ count, const float* __restrict__ dL,
     float* __restrict__ grad_rows) {
@@ -446,7 +467,8 @@ __global__ void __launch_bounds__(256) hybrid_topup_bwd_kernel(
   const float gl = z >= eps ? g0 * Lf[i * 3] + g1 * Lf[i * 3 + 1] + g2 * Lf[i * 3 + 2] : 0.f;
   float bd[K];
   int bi[K];
-  nearest_centres<K>(px, py, pz, cg, cstart, csorted, recs, k_min, reach2, max_rings, bd, bi);
+  nearest_centres<K>(px, py, pz, cg, cstart, csorted, cnear, recs, k_min, reach2, max_rings, bd,
+                     bi);
   const float slope = 6.f / fmaxf(rb, 1e-6f);
 #pragma unroll
   for (int a = 0; a < K; ++a) {
@@ -503,10 +525,12 @@ void free_centre_grid(gpf_grid* g) {
   dev_free(g->cg_key, 2 * g->cg_n_cap * sizeof(unsigned));
   dev_free(g->cg_val, g->cg_n_cap * sizeof(int));
   dev_free(g->cg_sorted, g->cg_n_cap * sizeof(int));
+  dev_free(g->cg_near, g->cg_cells_cap);
   dev_free(g->cg_box, kPointBoxBlocks * 6 * sizeof(float));
   dev_free(g->cg_tmp, g->cg_tmp_bytes);
   g->cg_start = g->cg_val = g->cg_sorted = nullptr;
   g->cg_key = nullptr;
+  g->cg_near = nullptr;
   g->cg_box = nullptr;
   g->cg_tmp = nullptr;
   g->cg_cells_cap = g->cg_n_cap = 0;
@@ -535,7 +559,8 @@ gpf_status build_centre_grid(gpf_grid* g, hipStream_t s) {
         (st = dev_alloc((void**)&g->cg_start, (cells + 1) * sizeof(int), "centre cells")) != GPF_OK ||
         (st = dev_alloc((void**)&g->cg_key, 2 * n * sizeof(unsigned), "centre keys")) != GPF_OK ||
         (st = dev_alloc((void**)&g->cg_val, n * sizeof(int), "centre order")) != GPF_OK ||
-        (st = dev_alloc((void**)&g->cg_sorted, n * sizeof(int), "centre order")) != GPF_OK)
+        (st = dev_alloc((void**)&g->cg_sorted, n * sizeof(int), "centre order")) != GPF_OK ||
+        (st = dev_alloc((void**)&g->cg_near, cells, "centre reach")) != GPF_OK)
       return st;
     g->cg_cells_cap = cells;
     g->cg_n_cap = n;
@@ -569,9 +594,11 @@ gpf_status build_centre_grid(gpf_grid* g, hipStream_t s) {
                                     g->cg_sorted, (size_t)n, 0, bits, s));
   hipLaunchKernelGGL(sorted_cell_starts_kernel, dim3((unsigned)((cells + 256) / 256)), dim3(256), 0,
                      s, g->cg_key + n, n, cells, g->cg_start);
+  hipLaunchKernelGGL(centre_near_kernel, dim3((unsigned)((cells + 255) / 256)), dim3(256), 0, s,
+                     g->cg_start, pg.dx, pg.dy, pg.dz, topup_rings(g), g->cg_near);
   GPF_HIP(hipGetLastError());
   g->cg_bytes = ((g->cg_cells_cap + 1) + 4 * g->cg_n_cap + kPointBoxBlocks * 6) * sizeof(int) +
-                g->cg_tmp_bytes;
+                g->cg_cells_cap + g->cg_tmp_bytes;
   return GPF_OK;
 }
 
@@ -586,8 +613,9 @@ gpf_status launch_hybrid_fwd(const gpf_grid* g, float eps, float* L, float* Z, i
                      eps, L, Z, count);
   const unsigned blocks = (unsigned)((qs->q + 255) / 256);
   hipLaunchKernelGGL(hybrid_topup_fwd_kernel<kTopUpMax>, dim3(blocks), dim3(256), 0, s,
-                     qs->x_user, qs->q, centre_geom(g), g->cg_start, g->cg_sorted, g->rec,
-                     g->k_min, g->ball, topup_reach2(g->ball), topup_rings(g), eps, L, Z, count);
+                     qs->x_user, qs->q, centre_geom(g), g->cg_start, g->cg_sorted, g->cg_near,
+                     g->rec, g->k_min, g->ball, topup_reach2(g->ball), topup_rings(g), eps, L, Z,
+                     count);
   GPF_HIP(hipGetLastError());
   return GPF_OK;
 }
@@ -607,8 +635,9 @@ gpf_status launch_hybrid_bwd(const gpf_grid* gc, float eps, const float* L, cons
                      eps, g->k_min, L, Z, count, dL, (float*)g->grad_rows);
   const unsigned blocks = (unsigned)((qs->q + 255) / 256);
   hipLaunchKernelGGL(hybrid_topup_bwd_kernel<kTopUpMax>, dim3(blocks), dim3(256), 0, s,
-                     qs->x_user, qs->q, centre_geom(g), g->cg_start, g->cg_sorted, g->rec,
-                     g->k_min, g->ball, topup_reach2(g->ball), topup_rings(g), eps, L, Z, count, dL,
+                     qs->x_user, qs->q, centre_geom(g), g->cg_start, g->cg_sorted, g->cg_near,
+                     g->rec, g->k_min, g->ball, topup_reach2(g->ball), topup_rings(g), eps, L, Z,
+                     count, dL,
                      (float*)g->grad_rows);
   GPF_HIP(hipGetLastError());
   return launch_grad_finalize(g, grad, s);
