@@ -204,6 +204,14 @@ gpf_status gpf_compact_photons(const float *pos, const float *power, const int *
  * gpf_photon_map_destroy. */
 gpf_status gpf_photon_map_build(const float *ppos, const float *ppower, const int *psurface,
                                 int64_t np, float r, void *stream, gpf_photon_map **map);
+
+/* Rebinds an existing map to new photons and radius (same arguments and
+ * limits as gpf_photon_map_build), reusing its device buffers when they are
+ * large enough: the progressive reference rebuilds one map per iteration.  On
+ * failure the map holds no photons (gathers fail) until a rebuild succeeds.
+ * Synchronises. */
+gpf_status gpf_photon_map_rebuild(gpf_photon_map *map, const float *ppos, const float *ppower,
+                                  const int *psurface, int64_t np, float r, void *stream);
 void gpf_photon_map_destroy(gpf_photon_map *map);
 
 /* Density estimate (Sec. 3.2 radiance estimation; the inner sum of the Sec. 4.3

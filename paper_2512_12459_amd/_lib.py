@@ -71,6 +71,7 @@ _SIG = {
                                            ctypes.POINTER(_I64), _P]),
     "gpf_photon_map_build": (ctypes.c_int, [_P, _P, _P, _I64, _F, _P, ctypes.POINTER(_P)]),
     "gpf_photon_map_destroy": (None, [_P]),
+    "gpf_photon_map_rebuild": (ctypes.c_int, [_P, _P, _P, _P, _I64, _F, _P]),
     "gpf_photon_map_gather": (ctypes.c_int, [_P, _P, _P, _I64, _F, ctypes.c_int, _P, _P, _P]),
     "gpf_camera_trace": (ctypes.c_int, [ctypes.POINTER(Camera), ctypes.c_int, ctypes.c_uint64,
                                         ctypes.c_int, _F, _F, ctypes.c_int, _P, _P, _P, _P, _P]),

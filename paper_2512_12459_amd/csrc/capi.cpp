@@ -343,6 +343,15 @@ gpf_status gpf_photon_map_build(const float* ppos, const float* ppower, const in
   return photon_map_build(ppos, ppower, psurface, np, r, map, (hipStream_t)stream);
 }
 
+gpf_status gpf_photon_map_rebuild(gpf_photon_map* map, const float* ppos, const float* ppower,
+                                  const int* psurface, int64_t np, float r, void* stream) {
+  if (!map || !ppos || !ppower || !psurface) return set_error(GPF_ERR_INVALID_ARGUMENT, "NULL argument");
+  if (np < 1 || np >= ((int64_t)1 << 31))
+    return set_error(GPF_ERR_INVALID_ARGUMENT, "np must lie in [1, 2^31 - 1]");
+  if (!(r > 0.f) || !std::isfinite(r)) return set_error(GPF_ERR_INVALID_ARGUMENT, "r must be positive and finite");
+  return photon_map_fill(map, ppos, ppower, psurface, np, r, (hipStream_t)stream);
+}
+
 void gpf_photon_map_destroy(gpf_photon_map* map) { photon_map_free(map); }
 
 gpf_status gpf_photon_map_gather(const gpf_photon_map* map, const float* x, const int* x_surface,

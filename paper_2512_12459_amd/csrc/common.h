@@ -144,6 +144,8 @@ gpf_status compact_photons(const float* pos, const float* pw, const int* surf, i
                            int64_t* count, hipStream_t s);
 gpf_status photon_map_build(const float* ppos, const float* ppw, const int* psurf, int64_t np,
                             float r, gpf_photon_map** out, hipStream_t s);
+gpf_status photon_map_fill(gpf_photon_map* m, const float* ppos, const float* ppw,
+                           const int* psurf, int64_t np, float r, hipStream_t s);
 gpf_status photon_map_gather(const gpf_photon_map* m, const float* x, const int* xs, int64_t q,
                              float weight, bool accumulate, float* L, int* count, hipStream_t s);
 void photon_map_free(gpf_photon_map* m);

@@ -339,91 +339,120 @@ struct gpf_photon_map {
   gpf::PGrid g;
   int64_t np = 0, cells = 0;
   float r = 0.f;
-  int* start = nullptr;      // [cells + 1] exclusive prefix of photons per cell
+  int* start = nullptr;      // [cells + 1] first photon of each cell in cell order
   float4* rec = nullptr;     // [2 np] (x, y, z, face bits), (power, 0) in cell order
+  // scratch kept between rebuilds (grown when a larger map comes)
+  int64_t np_cap = 0, cells_cap = 0;
+  size_t tmp_bytes = 0;
+  float* part = nullptr;     // [64 * 6] partial boxes
+  unsigned* key = nullptr;   // [2 np_cap] cell keys, then sorted keys
+  int* val = nullptr;        // [np_cap] photon indices
+  int* sorted = nullptr;     // [np_cap] photon indices in cell order
+  void* tmp = nullptr;       // radix sort scratch
 };
 
 namespace gpf {
 
 void photon_map_free(gpf_photon_map* m) {
   if (!m) return;
-  dev_free(m->start, (m->cells + 1) * 4);
-  dev_free(m->rec, 2 * m->np * sizeof(float4));
+  dev_free(m->start, (m->cells_cap + 1) * 4);
+  dev_free(m->rec, 2 * m->np_cap * sizeof(float4));
+  dev_free(m->part, kPointBoxBlocks * 6 * sizeof(float));
+  dev_free(m->key, 2 * m->np_cap * 4);
+  dev_free(m->val, m->np_cap * 4);
+  dev_free(m->sorted, m->np_cap * 4);
+  dev_free(m->tmp, m->tmp_bytes);
   delete m;
 }
 
-gpf_status photon_map_build(const float* ppos, const float* ppw, const int* psurf, int64_t np,
-                            float r, gpf_photon_map** out, hipStream_t s) {
-  float* part = nullptr;
-  gpf_status st = dev_alloc((void**)&part, kPointBoxBlocks * 6 * sizeof(float), "photon box");
-  if (st != GPF_OK) return st;
-  hipLaunchKernelGGL(pbox_kernel, dim3(kPointBoxBlocks), dim3(256), 0, s, ppos, np, part);
-  float hp[kPointBoxBlocks * 6];
-  hipError_t e = hipMemcpyAsync(hp, part, sizeof(hp), hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
-  dev_free(part, kPointBoxBlocks * 6 * sizeof(float));
-  if (e != hipSuccess) return hip_fail(e, "photon box");
-  auto* m = new gpf_photon_map;
-  m->np = np;
-  m->r = r;
-  if ((st = point_grid_geometry(hp, np, kPhotonGridDim, &m->g, (double)r * (1.0 + 1e-4))) !=
-      GPF_OK) {
-    delete m;
+// Bins the photons into m, growing its buffers when needed.  On failure the
+// map holds no valid photons (np = 0) but stays releasable.
+gpf_status photon_map_fill(gpf_photon_map* m, const float* ppos, const float* ppw,
+                           const int* psurf, int64_t np, float r, hipStream_t s) {
+  m->np = 0;
+  gpf_status st;
+  if (!m->part &&
+      (st = dev_alloc((void**)&m->part, kPointBoxBlocks * 6 * sizeof(float), "photon box")) != GPF_OK)
     return st;
+  hipLaunchKernelGGL(pbox_kernel, dim3(kPointBoxBlocks), dim3(256), 0, s, ppos, np, m->part);
+  float hp[kPointBoxBlocks * 6];
+  GPF_HIP(hipMemcpyAsync(hp, m->part, sizeof(hp), hipMemcpyDeviceToHost, s));
+  GPF_HIP(hipStreamSynchronize(s));
+  PGrid g;
+  if ((st = point_grid_geometry(hp, np, kPhotonGridDim, &g, (double)r * (1.0 + 1e-4))) != GPF_OK)
+    return st;
+  const int64_t cells = (int64_t)g.dx * g.dy * g.dz;
+  if (m->cells_cap < cells) {
+    dev_free(m->start, (m->cells_cap + 1) * 4);
+    m->start = nullptr;
+    m->cells_cap = 0;
+    if ((st = dev_alloc((void**)&m->start, (cells + 1) * 4, "photon cells")) != GPF_OK) return st;
+    m->cells_cap = cells;
   }
-  m->cells = (int64_t)m->g.dx * m->g.dy * m->g.dz;
-  const int64_t cells = m->cells;
+  if (m->np_cap < np) {
+    dev_free(m->rec, 2 * m->np_cap * sizeof(float4));
+    dev_free(m->key, 2 * m->np_cap * 4);
+    dev_free(m->val, m->np_cap * 4);
+    dev_free(m->sorted, m->np_cap * 4);
+    m->rec = nullptr;
+    m->key = nullptr;
+    m->val = m->sorted = nullptr;
+    m->np_cap = 0;
+    if ((st = dev_alloc((void**)&m->rec, 2 * np * sizeof(float4), "photon records")) != GPF_OK ||
+        (st = dev_alloc((void**)&m->key, 2 * np * 4, "photon keys")) != GPF_OK ||
+        (st = dev_alloc((void**)&m->val, np * 4, "photon order")) != GPF_OK ||
+        (st = dev_alloc((void**)&m->sorted, np * 4, "photon order")) != GPF_OK) {
+      dev_free(m->rec, 2 * np * sizeof(float4));
+      dev_free(m->key, 2 * np * 4);
+      dev_free(m->val, np * 4);
+      m->rec = nullptr;
+      m->key = nullptr;
+      m->val = nullptr;
+      return st;
+    }
+    m->np_cap = np;
+  }
   // photons by cell: a stable radix sort of (cell, index), so each cell lists
   // its photons in index order and the gather's summation order does not
   // depend on scheduling; cell starts by binary search (no atomics, so the
   // crowded cells of a caustic cost nothing extra)
-  int *val = nullptr, *sorted = nullptr;
-  unsigned *key = nullptr, *key_s = nullptr;
-  void* tmp = nullptr;
-  size_t tb = 0;
-  auto cleanup = [&]() {
-    dev_free(val, np * 4);
-    dev_free(sorted, np * 4);
-    dev_free(key, np * 4);
-    dev_free(key_s, np * 4);
-    dev_free(tmp, tb);
-  };
-  if ((st = dev_alloc((void**)&m->start, (cells + 1) * 4, "photon cells")) != GPF_OK ||
-      (st = dev_alloc((void**)&m->rec, 2 * np * sizeof(float4), "photon records")) != GPF_OK ||
-      (st = dev_alloc((void**)&val, np * 4, "photon order")) != GPF_OK ||
-      (st = dev_alloc((void**)&sorted, np * 4, "photon order")) != GPF_OK ||
-      (st = dev_alloc((void**)&key, np * 4, "photon keys")) != GPF_OK ||
-      (st = dev_alloc((void**)&key_s, np * 4, "photon keys")) != GPF_OK) {
-    cleanup();
-    photon_map_free(m);
-    return st;
-  }
   const int bits = cell_key_bits(cells);
-  e = rocprim::radix_sort_pairs(nullptr, tb, key, key_s, val, sorted, (size_t)np, 0, bits, s);
-  if (e == hipSuccess && (st = dev_alloc(&tmp, tb, "photon sort")) != GPF_OK) {
-    cleanup();
-    photon_map_free(m);
-    return st;
+  size_t tb = 0;
+  GPF_HIP(rocprim::radix_sort_pairs(nullptr, tb, m->key, m->key + np, m->val, m->sorted, (size_t)np,
+                                    0, bits, s));
+  if (m->tmp_bytes < tb) {
+    dev_free(m->tmp, m->tmp_bytes);
+    m->tmp = nullptr;
+    m->tmp_bytes = 0;
+    if ((st = dev_alloc(&m->tmp, tb, "photon sort")) != GPF_OK) return st;
+    m->tmp_bytes = tb;
   }
   const unsigned pb = (unsigned)((np + 255) / 256);
-  if (e == hipSuccess) {
-    hipLaunchKernelGGL(point_key_kernel, dim3(pb), dim3(256), 0, s, ppos, np, m->g, key, val);
-    e = hipGetLastError();
-  }
-  if (e == hipSuccess)
-    e = rocprim::radix_sort_pairs(tmp, tb, key, key_s, val, sorted, (size_t)np, 0, bits, s);
-  if (e == hipSuccess) {
-    hipLaunchKernelGGL(sorted_cell_starts_kernel, dim3((unsigned)((cells + 256) / 256)), dim3(256),
-                       0, s, key_s, np, cells, m->start);
-    hipLaunchKernelGGL(photon_gather_kernel, dim3(pb), dim3(256), 0, s, sorted, np, ppos, ppw,
-                       psurf, m->rec);
-    e = hipGetLastError();
-  }
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
-  cleanup();
-  if (e != hipSuccess) {
+  hipLaunchKernelGGL(point_key_kernel, dim3(pb), dim3(256), 0, s, ppos, np, g, m->key, m->val);
+  tb = m->tmp_bytes;
+  GPF_HIP(rocprim::radix_sort_pairs(m->tmp, tb, m->key, m->key + np, m->val, m->sorted, (size_t)np,
+                                    0, bits, s));
+  hipLaunchKernelGGL(sorted_cell_starts_kernel, dim3((unsigned)((cells + 256) / 256)), dim3(256), 0,
+                     s, m->key + np, np, cells, m->start);
+  hipLaunchKernelGGL(photon_gather_kernel, dim3(pb), dim3(256), 0, s, m->sorted, np, ppos, ppw,
+                     psurf, m->rec);
+  GPF_HIP(hipGetLastError());
+  // the caller may release its photon arrays once this returns
+  GPF_HIP(hipStreamSynchronize(s));
+  m->g = g;
+  m->cells = cells;
+  m->r = r;
+  m->np = np;
+  return GPF_OK;
+}
+
+gpf_status photon_map_build(const float* ppos, const float* ppw, const int* psurf, int64_t np,
+                            float r, gpf_photon_map** out, hipStream_t s) {
+  auto* m = new gpf_photon_map;
+  const gpf_status st = photon_map_fill(m, ppos, ppw, psurf, np, r, s);
+  if (st != GPF_OK) {
     photon_map_free(m);
-    return hip_fail(e, "photon map");
+    return st;
   }
   *out = m;
   return GPF_OK;
@@ -431,6 +460,7 @@ gpf_status photon_map_build(const float* ppos, const float* ppw, const int* psur
 
 gpf_status photon_map_gather(const gpf_photon_map* m, const float* x, const int* xs, int64_t q,
                              float weight, bool accumulate, float* L, int* count, hipStream_t s) {
+  if (m->np == 0) return set_error(GPF_ERR_INVALID_ARGUMENT, "photon map holds no photons");
   const float r = m->r;
   const float r2 = r * r;
   const float scale = (float)((double)weight / (M_PI * M_PI * (double)r * (double)r));
@@ -443,6 +473,7 @@ gpf_status photon_map_gather(const gpf_photon_map* m, const float* x, const int*
 gpf_status photon_map_gather_binned(const gpf_photon_map* m, const gpf_queries* qs,
                                     const int* xs, float weight, bool accumulate, float* L,
                                     int* count, hipStream_t s) {
+  if (m->np == 0) return set_error(GPF_ERR_INVALID_ARGUMENT, "photon map holds no photons");
   if (qs->ntiles == 0) return GPF_OK;
   const float r = m->r;
   const float r2 = r * r;

@@ -222,6 +222,15 @@ class PhotonMap:
         self.r = float(r)
         self.n = ppos.shape[0]
 
+    def rebuild(self, ppos, ppower, psurface, r: float) -> "PhotonMap":
+        """Rebinds the map to new photons and radius, reusing its buffers."""
+        _check_photons(ppos, ppower, psurface)
+        C.check(C.lib().gpf_photon_map_rebuild(self.handle, C.ptr(ppos), C.ptr(ppower),
+                                               C.ptr(psurface), ppos.shape[0], float(r), _stream()))
+        self.r = float(r)
+        self.n = ppos.shape[0]
+        return self
+
     def gather(self, x, x_surface, weight: float = 1.0, out=None, accumulate: bool = False,
                count=None, queries=None):
         """weight * density estimate at x (added into `out` when accumulate);
@@ -289,13 +298,15 @@ def sppm_reference(x: torch.Tensor, x_surface: torch.Tensor, iters: int, n_paths
     from .radiance import QuerySet
     out = torch.zeros((x.shape[0], 3), dtype=torch.float32, device=x.device)
     qs = QuerySet(x, 0.025)
+    pm = None
     for t, r in enumerate(sppm_radii(iters, r0, alpha), start=1):
         rec = trace_photons(n_paths, seed + t - 1, max_events, light, sphere, x.device)
         ppos, ppw, psurf = compact_photons(*rec)
         if ppos.shape[0] == 0:
             continue
-        pm = PhotonMap(ppos, ppw, psurf, r)
+        pm = PhotonMap(ppos, ppw, psurf, r) if pm is None else pm.rebuild(ppos, ppw, psurf, r)
         pm.gather(x, x_surface, 1.0 / iters, out, accumulate=True, queries=qs)
+    if pm is not None:
         pm.close()
     qs.close()
     return out

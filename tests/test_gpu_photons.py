@@ -220,6 +220,20 @@ def test_density_matches_oracle(ph, r):
         assert torch.equal(pm.gather(dx, dxs, queries=qs, count=cnt_b), L)
         assert torch.equal(cnt_b, cnt)
         qs.close()
+    # rebuilding the map on other photons and radius equals a fresh map; a
+    # failed rebuild leaves it empty until the next one succeeds
+    from paper_2512_12459_amd._lib import GPFError
+    half = slice(0, dp.shape[0] // 2)
+    sub = [t[half].contiguous() for t in (dp, dw, ds)]
+    fresh = ph.photon_density(dx, dxs, *sub, r * 0.7)
+    assert torch.equal(pm.rebuild(*sub, r * 0.7).gather(dx, dxs), fresh)
+    bad = sub[0].clone()
+    bad[3, 1] = float("nan")
+    with pytest.raises(GPFError):
+        pm.rebuild(bad, sub[1], sub[2], r)
+    with pytest.raises(GPFError):
+        pm.gather(dx, dxs)
+    assert torch.equal(pm.rebuild(dp, dw, ds, r).gather(dx, dxs), L)
     pm.close()
     assert np.all(ref[xs > 4] == 0) and (ref[xs <= 4] > 0).mean() > 0.9
     # weight and accumulation: L + 0.5 * estimate
