@@ -56,3 +56,62 @@ def test_host_validation_without_device_work():
     L.gpf_queries_destroy(None)
     L.gpf_grid_destroy(None)
     assert L.gpf_version().startswith(b"gpf")
+
+
+def test_photon_and_camera_validation_without_device_work():
+    L = C.lib()
+    fake = ctypes.c_void_p(0x1000)
+    # photon tracing: path count, event count, light square, sphere kind, outputs
+    for args in ((0, 1, 4, 0.4, 0.6, 1), (10, 1, 0, 0.4, 0.6, 1), (10, 1, 17, 0.4, 0.6, 1),
+                 (10, 1, 4, 0.6, 0.4, 1), (10, 1, 4, -0.1, 0.6, 1), (10, 1, 4, 0.4, 1.1, 1),
+                 (10, 1, 4, 0.4, 0.6, 3), (1 << 31, 1, 4, 0.4, 0.6, 1)):
+        assert L.gpf_trace_photons(*args, fake, fake, fake, None) == 1, args
+    assert L.gpf_trace_photons(10, 1, 4, 0.4, 0.6, 1, None, fake, fake, None) == 1
+    # compaction
+    cnt = ctypes.c_int64()
+    assert L.gpf_compact_photons(None, fake, fake, 5, fake, fake, fake, None, 5,
+                                 ctypes.byref(cnt), None) == 1
+    assert L.gpf_compact_photons(fake, fake, fake, 0, fake, fake, fake, None, 5,
+                                 ctypes.byref(cnt), None) == 1
+    assert L.gpf_compact_photons(fake, fake, fake, 5, fake, fake, fake, None, -1,
+                                 ctypes.byref(cnt), None) == 1
+    # photon map and density estimate
+    h = ctypes.c_void_p()
+    assert L.gpf_photon_map_build(None, fake, fake, 5, 0.1, None, ctypes.byref(h)) == 1
+    assert L.gpf_photon_map_build(fake, fake, fake, 0, 0.1, None, ctypes.byref(h)) == 1
+    assert L.gpf_photon_map_build(fake, fake, fake, 5, 0.0, None, ctypes.byref(h)) == 1
+    assert L.gpf_photon_map_build(fake, fake, fake, 5, float("inf"), None, ctypes.byref(h)) == 1
+    assert L.gpf_photon_map_rebuild(None, fake, fake, fake, 5, 0.1, None) == 1
+    assert L.gpf_photon_map_gather(None, fake, fake, 5, 1.0, 0, fake, None, None) == 1
+    assert L.gpf_photon_map_gather_binned(None, fake, fake, 1.0, 0, fake, None, None) == 1
+    assert L.gpf_photon_density(fake, fake, 0, fake, fake, fake, 5, 0.1, 1.0, 0, fake, None,
+                                None) == 1
+    assert L.gpf_photon_density(fake, fake, 5, fake, fake, fake, 5, 0.1, float("nan"), 0, fake,
+                                None, None) == 1
+    L.gpf_photon_map_destroy(None)
+    # camera integrator
+    def cam(**kw):
+        c = C.Camera()
+        c.eye[:] = kw.get("eye", [0.5, 0.5, 0.95])
+        c.target[:] = kw.get("target", [0.5, 0.5, 0.0])
+        c.up[:] = kw.get("up", [0.0, 1.0, 0.0])
+        c.vfov_deg = kw.get("vfov", 60.0)
+        c.width, c.height = kw.get("w", 8), kw.get("h", 8)
+        return c
+    good = cam()
+    for c_, args in ((cam(w=0), (1, 0, 16, 0.4, 0.6, 1)), (good, (0, 0, 16, 0.4, 0.6, 1)),
+                     (good, (1025, 0, 16, 0.4, 0.6, 1)), (good, (1, 0, 0, 0.4, 0.6, 1)),
+                     (good, (1, 0, 65, 0.4, 0.6, 1)), (good, (1, 0, 16, 0.4, 0.6, 3)),
+                     (good, (1, 0, 16, 0.6, 0.4, 1)), (cam(vfov=0.0), (1, 0, 16, 0.4, 0.6, 1)),
+                     (cam(vfov=180.0), (1, 0, 16, 0.4, 0.6, 1)),
+                     (cam(target=[0.5, 0.5, 0.95]), (1, 0, 16, 0.4, 0.6, 1)),
+                     (cam(up=[0.0, 0.0, 1.0]), (1, 0, 16, 0.4, 0.6, 1)),
+                     (cam(eye=[float("nan"), 0.5, 0.9]), (1, 0, 16, 0.4, 0.6, 1)),
+                     (cam(w=65536, h=65536), (1, 0, 16, 0.4, 0.6, 1))):
+        assert L.gpf_camera_trace(ctypes.byref(c_), *args, fake, fake, fake, fake, None) == 1, args
+    assert L.gpf_camera_trace(None, 1, 0, 16, 0.4, 0.6, 1, fake, fake, fake, fake, None) == 1
+    assert L.gpf_camera_compose(None, 5, 1, fake, fake, fake, 3, fake, None) == 1
+    assert L.gpf_camera_compose(fake, 0, 1, fake, fake, fake, 3, fake, None) == 1
+    assert L.gpf_camera_compose(fake, 5, 1, None, fake, fake, 3, fake, None) == 1
+    assert L.gpf_camera_compose_backward(fake, 0, 1, fake, fake, 3, fake, None) == 1
+    assert L.gpf_camera_compose_backward(None, 5, 1, fake, fake, 3, fake, None) == 1
