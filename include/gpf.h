@@ -109,7 +109,11 @@ gpf_status gpf_grid_info(const gpf_grid *grid, int64_t *entries, size_t *device_
  * for the q points x[q][3] that were binned into the grid's query set (same
  * buffer, same contents).  L[q][3] is overwritten; a point with no
  * contributing primitive gets exactly 0.  `f` must be the field the grid was
- * built from (same pointers and n), else GPF_ERR_STALE. */
+ * built from (same pointers and n), else GPF_ERR_STALE.  The grid keeps the
+ * primitives that survive the cull of each group of query points (up to 2048
+ * per group, 4 bytes each; allocated on the first call and kept, not
+ * allocated at all if the device byte budget refuses), which a backward on
+ * the same build then reuses instead of culling again. */
 gpf_status gpf_eval_radiance(const gpf_grid *grid, const gpf_field *f, const float *x, int64_t q,
                              float *L, void *stream);
 
@@ -119,7 +123,9 @@ gpf_status gpf_eval_radiance(const gpf_grid *grid, const gpf_field *f, const flo
  * rgb.  Kernel weights are recomputed per pair, nothing per pair is stored.
  * The derivative of the cutoff indicator is taken as zero.  Gradient buffers
  * must not alias the field.  Accumulation order is not deterministic
- * (floating-point atomics). */
+ * (floating-point atomics).  After a gpf_eval_radiance on the same build the
+ * backward reads that call's survivor lists rather than culling (same pairs);
+ * on a stream other than the forward's the caller orders the two calls. */
 gpf_status gpf_eval_radiance_backward(const gpf_grid *grid, const gpf_field *f, const float *x,
                                       int64_t q, const float *dL, gpf_field_grad *grad,
                                       void *stream);
@@ -181,8 +187,8 @@ gpf_status gpf_eval_hybrid_backward(const gpf_grid *grid, const gpf_field *f, co
  * by its reflectance; a diffuse face stores a photon in slot
  * [path][event - 1] and continues when u0 < q = max(albedo) with power
  * * albedo / q in a cosine direction.  Outputs (device, caller-owned, written
- * whole): pos[n_paths][max_events][3], power[..][3], surface[..] (-1 where
- * nothing was stored).  1 <= n_paths < 2^31, 1 <= max_events <= 16,
+ * whole): pos[n_paths][max_events][3], power[..][3], surface[..] (-1, with
+ * zero position and power, where nothing was stored).  1 <= n_paths < 2^31, 1 <= max_events <= 16,
  * 0 <= light_lo <= light_hi <= 1, sphere in {0, 1, 2}. */
 gpf_status gpf_trace_photons(int64_t n_paths, uint64_t seed, int max_events, float light_lo,
                              float light_hi, int sphere, float *pos, float *power, int *surface,

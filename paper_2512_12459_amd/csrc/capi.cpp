@@ -189,6 +189,8 @@ void gpf_grid_destroy(gpf_grid* g) {
   dev_free(g->cell_prims, g->cap * sizeof(int));
   dev_free(g->sort_tmp, g->sort_tmp_bytes);
   dev_free(g->grad_rows, g->grad_cap * sizeof(float4) * 4);
+  dev_free(g->surv, (size_t)g->surv_groups * kSurvPerGroup * sizeof(int));
+  dev_free(g->surv_count, (size_t)g->surv_groups * sizeof(int));
   free_centre_grid(g);
   delete g;
 }
@@ -196,7 +198,9 @@ void gpf_grid_destroy(gpf_grid* g) {
 gpf_status gpf_grid_info(const gpf_grid* g, int64_t* entries, size_t* device_bytes) {
   if (!g) return set_error(GPF_ERR_INVALID_ARGUMENT, "grid is NULL");
   if (entries) *entries = g->entries;
-  if (device_bytes) *device_bytes = g->bytes;
+  if (device_bytes)
+    *device_bytes = g->bytes + (size_t)g->grad_cap * 4 * sizeof(float4) +
+                    (size_t)g->surv_groups * (kSurvPerGroup + 1) * sizeof(int);
   return GPF_OK;
 }
 

@@ -85,6 +85,14 @@ struct gpf_grid {
   int64_t entries = 0;
   float4* grad_rows = nullptr;  // [n][4] backward scratch: one 64-byte row per primitive
   int64_t grad_cap = 0;
+  // Survivors of the forward's cull, per group (primitive | tile mask << 30,
+  // in cell-list order, at most kSurvPerGroup each) and their number, for the
+  // backward of the same build; surv_ready is set by a forward and cleared by
+  // a build.
+  int* surv = nullptr;          // [surv_groups][kSurvPerGroup]
+  int* surv_count = nullptr;    // [surv_groups]
+  int64_t surv_groups = 0;
+  bool surv_ready = false;
   // Hybrid query (ball > 0): ball radius r, nearest-centre top-up size, and a
   // uniform grid over the centres for the top-up search.
   float ball = 0.f;
@@ -177,6 +185,12 @@ gpf_status launch_adam(float* p, const float* g, float* m, float* v, int64_t n, 
 #define GPF_XCD_CHUNK 16
 #endif
 constexpr int kXcd = 8;
+// Survivors per group kept from the forward for the backward; a group with
+// more culls again in the backward.
+#ifndef GPF_SURV_PER_GROUP
+#define GPF_SURV_PER_GROUP 2048
+#endif
+constexpr int kSurvPerGroup = GPF_SURV_PER_GROUP;
 constexpr int kXcdChunk = GPF_XCD_CHUNK;
 
 inline unsigned xcd_grid(int64_t n) {

@@ -64,7 +64,7 @@ __global__ void __launch_bounds__(kWaves * 64) eval_fwd_kernel(
     const float4* __restrict__ ghi, int ngroups, const float4* __restrict__ tlo,
     const float4* __restrict__ thi, const int* __restrict__ cell_start,
     const int* __restrict__ cell_prims, const PrimRec* __restrict__ recs, float c2,
-    float* __restrict__ L) {
+    float* __restrict__ L, int* __restrict__ keep, int* __restrict__ keep_count) {
   static_assert(kGroupTiles == 2, "the forward pairs the two tiles of a group");
   __shared__ int4 surv[kWaves][kFwdSurvCap];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -86,7 +86,8 @@ __global__ void __launch_bounds__(kWaves * 64) eval_fwd_kernel(
   }
   const int cs = cell_start[gi.cell], ce = cell_start[gi.cell + 1];
   int4* sv = surv[wave];
-  int ns = 0;
+  int ns = 0, kept = 0;  // kept: survivors so far (all of them, also past the list's capacity)
+  int* kl = keep ? keep + (int64_t)g * kSurvPerGroup : nullptr;
   for (int base = cs; base < ce; base += 64) {
     const int j = base + lane;
     int mask = 0, pid = 0;
@@ -112,6 +113,10 @@ __global__ void __launch_bounds__(kWaves * 64) eval_fwd_kernel(
     if (ns > kFwdSurvCap - 64 || base + 64 >= ce) {
       wave_sync_lds();
       const int nsu = __builtin_amdgcn_readfirstlane(ns);  // wave-uniform trip count
+      if (kl) {  // keep the survivors (cell-list order) for the backward
+        for (int s = lane; s < nsu && kept + s < kSurvPerGroup; s += 64) kl[kept + s] = sv[s].x;
+        kept += nsu;
+      }
       for (int s = 0; s < nsu; ++s) {
         const int4 e = sv[s];
         const int head = __builtin_amdgcn_readfirstlane(e.x);
@@ -134,6 +139,7 @@ __global__ void __launch_bounds__(kWaves * 64) eval_fwd_kernel(
       wave_sync_lds();
     }
   }
+  if (keep_count && lane == 0) keep_count[g] = kept;
 #pragma unroll
   for (int i = 0; i < 2; ++i) {
     const int k = lane + 64 * i;
@@ -291,7 +297,8 @@ __global__ void __launch_bounds__(kBwdThreads) eval_bwd_kernel(
     const float4* __restrict__ ghi, int ngroups, const float4* __restrict__ tlo,
     const float4* __restrict__ thi, const int* __restrict__ cell_start,
     const int* __restrict__ cell_prims, const PrimRec* __restrict__ recs, float c2,
-    const float* __restrict__ dL, float* __restrict__ grad_rows) {
+    const float* __restrict__ dL, float* __restrict__ grad_rows, const int* __restrict__ keep,
+    const int* __restrict__ keep_count) {
   static_assert(kGroupTiles == 2, "the backward splits survivors over the two tiles of a group");
   __shared__ int sv_all[kBwdWaves][3][kListCap];
   __shared__ float4 qx_all[kBwdWaves][kGroupQ];
@@ -327,6 +334,40 @@ __global__ void __launch_bounds__(kBwdThreads) eval_bwd_kernel(
   const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const int cs = cell_start[gi.cell], ce = cell_start[gi.cell + 1];
   int n0 = 0, n1 = 0, n2 = 0;  // stack heights, each below 64 between batches
+  // The forward's survivors of this group, when it kept them all: the same
+  // (primitive, tile mask) pairs, in the same order, as the cull below would
+  // find, so the same (primitive, point) slots are evaluated without testing
+  // any candidate again (stacks drain at other moments, which only regroups
+  // the sums).
+  const int nk = keep_count ? keep_count[g] : kSurvPerGroup + 1;
+  if (nk <= kSurvPerGroup) {
+    const int* kl = keep + (int64_t)g * kSurvPerGroup;
+    for (int base = 0; base < nk; base += 64) {
+      const int ent = (base + lane < nk) ? kl[base + lane] : 0;
+      const int mask = (base + lane < nk) ? ((ent >> 30) & 3) : 0;
+      const int pid = ent & 0x3fffffff;
+      const uint64_t m0 = __ballot(mask == 1), m1 = __ballot(mask == 2), m2 = __ballot(mask == 3);
+      if (mask == 1) sv0[n0 + __popcll(m0 & below)] = pid;
+      if (mask == 2) sv1[n1 + __popcll(m1 & below)] = pid;
+      if (mask == 3) sv2[n2 + __popcll(m2 & below)] = pid;
+      n0 += __popcll(m0);
+      n1 += __popcll(m1);
+      n2 += __popcll(m2);
+      wave_sync_lds();
+      if (n0 >= 64) {
+        n0 -= 64;
+        bwd_chunk(sv0[n0 + lane], true, 0, qe_a, tc, recs, c2, qx, qg, rw, grad_rows, lane);
+      }
+      if (n1 >= 64) {
+        n1 -= 64;
+        bwd_chunk(sv1[n1 + lane], true, kTile, qe_all, tc, recs, c2, qx, qg, rw, grad_rows, lane);
+      }
+      if (n2 >= 64) {
+        n2 -= 64;
+        bwd_chunk(sv2[n2 + lane], true, 0, qe_all, tc, recs, c2, qx, qg, rw, grad_rows, lane);
+      }
+    }
+  } else {
   // Software pipeline over the candidates in batches of 64: the records of
   // batch b + 1 and the indices of batch b + 2 are requested before batch b is
   // tested, so their latency overlaps the tests and the draining of full
@@ -371,6 +412,7 @@ __global__ void __launch_bounds__(kBwdThreads) eval_bwd_kernel(
     rec_c = rec_n;
     pid_n = pid_nn;
   }
+  }
   const int total = n0 + n1 + n2;
   for (int chunk = 0; chunk < total; chunk += 64) {
     const int v = chunk + lane;
@@ -396,13 +438,37 @@ __global__ void __launch_bounds__(kBwdThreads) eval_bwd_kernel(
 
 static int fwd_blocks(int64_t ntiles) { return (int)((ntiles + kWaves - 1) / kWaves); }
 
-gpf_status launch_eval_fwd(const gpf_grid* g, float* L, hipStream_t s) {
+// The forward's survivor lists (kept for the backward of the same build);
+// allocated on first use and grown with the number of groups.  Without them
+// (allocation refused) the forward keeps nothing and the backward culls.
+static void ensure_survivor_lists(gpf_grid* g) {
+  const int64_t ng = g->qs->ngroups;
+  if (g->surv_groups >= ng) return;
+  dev_free(g->surv, (size_t)g->surv_groups * kSurvPerGroup * sizeof(int));
+  dev_free(g->surv_count, (size_t)g->surv_groups * sizeof(int));
+  g->surv = g->surv_count = nullptr;
+  g->surv_groups = 0;
+  if (dev_alloc((void**)&g->surv, (size_t)ng * kSurvPerGroup * sizeof(int), "survivor lists") !=
+          GPF_OK ||
+      dev_alloc((void**)&g->surv_count, (size_t)ng * sizeof(int), "survivor counts") != GPF_OK) {
+    dev_free(g->surv, (size_t)ng * kSurvPerGroup * sizeof(int));
+    g->surv = nullptr;
+    return;
+  }
+  g->surv_groups = ng;
+}
+
+gpf_status launch_eval_fwd(const gpf_grid* gc, float* L, hipStream_t s) {
+  gpf_grid* g = const_cast<gpf_grid*>(gc);  // the survivor lists live in the handle
   const gpf_queries* qs = g->qs;
   const float c2 = (float)(kKappa2 * g->cutoff * g->cutoff);
+  ensure_survivor_lists(g);
   hipLaunchKernelGGL(eval_fwd_kernel, dim3(xcd_grid(fwd_blocks(qs->ngroups))), dim3(kWaves * 64), 0, s,
                      qs->xs, qs->perm, qs->groups, qs->group_lo, qs->group_hi, (int)qs->ngroups,
-                     qs->tile_lo, qs->tile_hi, g->cell_start, g->cell_prims, g->rec, c2, L);
+                     qs->tile_lo, qs->tile_hi, g->cell_start, g->cell_prims, g->rec, c2, L, g->surv,
+                     g->surv ? g->surv_count : nullptr);
   GPF_HIP(hipGetLastError());
+  g->surv_ready = g->surv != nullptr;
   return GPF_OK;
 }
 
@@ -442,7 +508,8 @@ gpf_status launch_eval_bwd(const gpf_grid* gc, const float* dL, gpf_field_grad* 
                      dim3(kBwdThreads), 0, s, qs->xs,
                      qs->perm, qs->groups, qs->group_lo, qs->group_hi, (int)qs->ngroups,
                      qs->tile_lo, qs->tile_hi, g->cell_start, g->cell_prims, g->rec, c2, dL,
-                     (float*)g->grad_rows);
+                     (float*)g->grad_rows, g->surv_ready ? g->surv : nullptr,
+                     g->surv_ready ? g->surv_count : nullptr);
   return launch_grad_finalize(g, grad, s);
 }
 

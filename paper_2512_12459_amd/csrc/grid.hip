@@ -210,6 +210,7 @@ __global__ void cell_start_kernel(const int* __restrict__ keys, int E, int ncell
 }  // namespace
 
 gpf_status launch_build_grid(gpf_grid* g, hipStream_t s) {
+  g->surv_ready = false;  // the forward's survivor lists belong to the previous build
   const gpf_queries* qs = g->qs;
   const int n = (int)g->n;
   const int nc = (int)qs->ncells;

@@ -37,7 +37,16 @@ __global__ void __launch_bounds__(256) trace_kernel(int64_t n, uint64_t seed, in
                                                     int* __restrict__ surf) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= n) return;
-  for (int j = 0; j < E; ++j) surf[i * E + j] = -1;
+  // every slot is written: unused ones hold face -1 and zero position and power
+  for (int j = 0; j < E; ++j) {
+    const int64_t slot = i * E + j;
+    surf[slot] = -1;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      pos[slot * 3 + a] = 0.f;
+      pw[slot * 3 + a] = 0.f;
+    }
+  }
   float u[4];
   uniforms((uint64_t)i, 0, 0, seed, u);
   float o[3] = {lo + (hi - lo) * u[0], 1.f, lo + (hi - lo) * u[1]};

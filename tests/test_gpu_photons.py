@@ -83,6 +83,8 @@ def test_trace_matches_oracle(ph, sphere, E):
     gpu = [t.cpu().numpy() for t in ph.trace_photons(n, seed, E, sphere=sphere)]
     ref = _oracle_with_conditioning(n, seed, E, sphere)
     assert _compare_paths(gpu, ref) > n
+    unused = gpu[2] < 0
+    assert np.all(gpu[0][unused] == 0) and np.all(gpu[1][unused] == 0)
 
 
 def test_trace_full_size_sampled_paths(ph):
