@@ -137,6 +137,7 @@ gpf_status launch_eval_bwd(const gpf_grid* g, const float* dL, gpf_field_grad* g
                            hipStream_t s);
 gpf_status launch_count_pairs(const gpf_grid* g, unsigned long long* d_count, hipStream_t s);
 gpf_status ensure_grad_rows(gpf_grid* g, hipStream_t s);
+void ensure_survivor_lists(gpf_grid* g);
 gpf_status launch_grad_finalize(gpf_grid* g, gpf_field_grad* grad, hipStream_t s);
 gpf_status build_centre_grid(gpf_grid* g, hipStream_t s);
 void free_centre_grid(gpf_grid* g);

@@ -441,7 +441,7 @@ static int fwd_blocks(int64_t ntiles) { return (int)((ntiles + kWaves - 1) / kWa
 // The forward's survivor lists (kept for the backward of the same build);
 // allocated on first use and grown with the number of groups.  Without them
 // (allocation refused) the forward keeps nothing and the backward culls.
-static void ensure_survivor_lists(gpf_grid* g) {
+void ensure_survivor_lists(gpf_grid* g) {
   const int64_t ng = g->qs->ngroups;
   if (g->surv_groups >= ng) return;
   dev_free(g->surv, (size_t)g->surv_groups * kSurvPerGroup * sizeof(int));

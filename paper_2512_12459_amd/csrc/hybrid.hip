@@ -77,7 +77,8 @@ __global__ void __launch_bounds__(kHWaves * 64) hybrid_fwd_kernel(
     const GroupInfo* __restrict__ groups, int ngroups, const float4* __restrict__ tlo,
     const float4* __restrict__ thi, const int* __restrict__ cell_start,
     const int* __restrict__ cell_prims, const PrimRec* __restrict__ recs, float r2, float r2pad,
-    float eps, float* __restrict__ L, float* __restrict__ Zout, int* __restrict__ count) {
+    float eps, float* __restrict__ L, float* __restrict__ Zout, int* __restrict__ count,
+    int* __restrict__ keep, int* __restrict__ keep_count) {
   static_assert(kGroupTiles == 2, "the forward pairs the two tiles of a group");
   __shared__ int surv[kHWaves][kHFwdCap];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -102,7 +103,8 @@ __global__ void __launch_bounds__(kHWaves * 64) hybrid_fwd_kernel(
   const int cs = cell_start[gi.cell], ce = cell_start[gi.cell + 1];
   const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   int* sv = surv[wave];
-  int ns = 0;
+  int ns = 0, kept = 0;  // kept: survivors so far (all of them, also past the list's capacity)
+  int* kl = keep ? keep + (int64_t)g * kSurvPerGroup : nullptr;
   for (int base = cs; base < ce; base += 64) {
     const int j = base + lane;
     int mask = 0, pid = 0;
@@ -118,6 +120,10 @@ __global__ void __launch_bounds__(kHWaves * 64) hybrid_fwd_kernel(
     if (ns > kHFwdCap - 64 || base + 64 >= ce) {
       wave_sync_lds();
       const int nsu = __builtin_amdgcn_readfirstlane(ns);
+      if (kl) {  // keep the survivors (cell-list order) for the backward
+        for (int s = lane; s < nsu && kept + s < kSurvPerGroup; s += 64) kl[kept + s] = sv[s];
+        kept += nsu;
+      }
       for (int s = 0; s < nsu; ++s) {
         const int head = __builtin_amdgcn_readfirstlane(sv[s]);
         const PrimRec r = recs[head & 0x3fffffff];
@@ -141,6 +147,7 @@ __global__ void __launch_bounds__(kHWaves * 64) hybrid_fwd_kernel(
       wave_sync_lds();
     }
   }
+  if (keep_count && lane == 0) keep_count[g] = kept;
 #pragma unroll
   for (int i = 0; i < 2; ++i) {
     const int k = lane + 64 * i;
@@ -354,7 +361,8 @@ __global__ void __launch_bounds__(kHWaves * 64) hybrid_bwd_kernel(
     const float4* __restrict__ thi, const int* __restrict__ cell_start,
     const int* __restrict__ cell_prims, const PrimRec* __restrict__ recs, float r2, float r2pad,
     float eps, int k_min, const float* __restrict__ Lf, const float* __restrict__ Zf,
-    const int* __restrict__ count, const float* __restrict__ dL, float* __restrict__ grad_rows) {
+    const int* __restrict__ count, const float* __restrict__ dL, float* __restrict__ grad_rows,
+    const int* __restrict__ keep, const int* __restrict__ keep_count) {
   static_assert(kGroupTiles == 2, "the backward splits survivors over the two tiles of a group");
   __shared__ int sv_all[kHWaves][3][kHListCap];
   __shared__ float4 qx_all[kHWaves][kHGroupQ];
@@ -397,14 +405,26 @@ __global__ void __launch_bounds__(kHWaves * 64) hybrid_bwd_kernel(
   const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const int cs = cell_start[gi.cell], ce = cell_start[gi.cell + 1];
   int n0 = 0, n1 = 0, n2 = 0;
-  for (int base = cs; base < ce; base += 64) {
+  // the forward's survivors of this group when it kept them all (the same
+  // (centre, tile mask) pairs in the same order as the cull), else the cull
+  const int nk = keep_count ? keep_count[g] : kSurvPerGroup + 1;
+  const bool listed = nk <= kSurvPerGroup;
+  const int* kl = listed ? keep + (int64_t)g * kSurvPerGroup : nullptr;
+  const int lb = listed ? 0 : cs, le = listed ? nk : ce;
+  for (int base = lb; base < le; base += 64) {
     const int j = base + lane;
     int mask = 0, pid = 0;
-    if (j < ce) {
-      pid = cell_prims[j];
-      const float4 m = recs[pid].r0;
-      mask = (ball_touch(m.x, m.y, m.z, ta, r2pad) ? 1 : 0) |
-             ((has_b && ball_touch(m.x, m.y, m.z, tb, r2pad)) ? 2 : 0);
+    if (j < le) {
+      if (listed) {
+        const int ent = kl[j];
+        pid = ent & 0x3fffffff;
+        mask = (ent >> 30) & 3;
+      } else {
+        pid = cell_prims[j];
+        const float4 m = recs[pid].r0;
+        mask = (ball_touch(m.x, m.y, m.z, ta, r2pad) ? 1 : 0) |
+               ((has_b && ball_touch(m.x, m.y, m.z, tb, r2pad)) ? 2 : 0);
+      }
     }
     const uint64_t m0 = __ballot(mask == 1), m1 = __ballot(mask == 2), m2 = __ballot(mask == 3);
     if (mask == 1) sv0[n0 + __popcll(m0 & below)] = pid;
@@ -602,21 +622,24 @@ gpf_status build_centre_grid(gpf_grid* g, hipStream_t s) {
   return GPF_OK;
 }
 
-gpf_status launch_hybrid_fwd(const gpf_grid* g, float eps, float* L, float* Z, int* count,
+gpf_status launch_hybrid_fwd(const gpf_grid* gc, float eps, float* L, float* Z, int* count,
                              hipStream_t s) {
+  gpf_grid* g = const_cast<gpf_grid*>(gc);  // the survivor lists live in the handle
   const gpf_queries* qs = g->qs;
+  ensure_survivor_lists(g);
   const float r2 = g->ball * g->ball;
   const float r2pad = r2 * 1.001f + 1e-10f;
   hipLaunchKernelGGL(hybrid_fwd_kernel, dim3(xcd_grid((qs->ngroups + kHWaves - 1) / kHWaves)),
                      dim3(kHWaves * 64), 0, s, qs->xs, qs->perm, qs->groups, (int)qs->ngroups,
                      qs->tile_lo, qs->tile_hi, g->cell_start, g->cell_prims, g->rec, r2, r2pad,
-                     eps, L, Z, count);
+                     eps, L, Z, count, g->surv, g->surv ? g->surv_count : nullptr);
   const unsigned blocks = (unsigned)((qs->q + 255) / 256);
   hipLaunchKernelGGL(hybrid_topup_fwd_kernel<kTopUpMax>, dim3(blocks), dim3(256), 0, s,
                      qs->x_user, qs->q, centre_geom(g), g->cg_start, g->cg_sorted, g->cg_near,
                      g->rec, g->k_min, g->ball, topup_reach2(g->ball), topup_rings(g), eps, L, Z,
                      count);
   GPF_HIP(hipGetLastError());
+  g->surv_ready = g->surv != nullptr;
   return GPF_OK;
 }
 
@@ -632,7 +655,8 @@ gpf_status launch_hybrid_bwd(const gpf_grid* gc, float eps, const float* L, cons
   hipLaunchKernelGGL(hybrid_bwd_kernel, dim3(xcd_grid((qs->ngroups + kHWaves - 1) / kHWaves)),
                      dim3(kHWaves * 64), 0, s, qs->xs, qs->perm, qs->groups, (int)qs->ngroups,
                      qs->tile_lo, qs->tile_hi, g->cell_start, g->cell_prims, g->rec, r2, r2pad,
-                     eps, g->k_min, L, Z, count, dL, (float*)g->grad_rows);
+                     eps, g->k_min, L, Z, count, dL, (float*)g->grad_rows,
+                     g->surv_ready ? g->surv : nullptr, g->surv_ready ? g->surv_count : nullptr);
   const unsigned blocks = (unsigned)((qs->q + 255) / 256);
   hipLaunchKernelGGL(hybrid_topup_bwd_kernel<kTopUpMax>, dim3(blocks), dim3(256), 0, s,
                      qs->x_user, qs->q, centre_geom(g), g->cg_start, g->cg_sorted, g->cg_near,
