@@ -169,6 +169,49 @@ def test_backward_random_volume(rad):
     check_grads(gg, gref)
 
 
+def test_backward_with_and_without_the_forwards_survivor_lists(rad):
+    """The backward reads the survivor lists of a forward on the same build,
+    culls again after a rebuild without forward, and culls per group where a
+    group had more survivors than its list holds (a crowded cell of 3,000
+    primitives); every path matches the oracle."""
+    rng = np.random.default_rng(21)
+    n = 3000
+    mu = 0.5 + rng.normal(0, 0.002, (n, 3))
+    q = rng.normal(size=(n, 4))
+    ls = np.log(0.01) + rng.normal(0, 0.2, (n, 3))
+    rgb = np.exp(rng.normal(0, 1, (n, 3)))
+    x = 0.5 + rng.normal(0, 0.01, (400, 3))
+    mu, q, ls, rgb, x = (a.astype(np.float32) for a in (mu, q, ls, rgb, x))
+    ref = O.radiance(mu, q, ls, rgb, x)
+    T = rng.random((len(x), 3)).astype(np.float32)
+    _, dL = O.mse_loss(ref["L"], T)
+    dL = _mask_ambiguous(ref, dL).astype(np.float32)
+    gref = O.radiance_backward(mu, q, ls, rgb, x, dL)
+    (dLd,) = to_dev(dL)
+    L, g, dev, qs = _eval(rad, (mu, q, ls, rgb), x, cell=0.05)
+    say("case: crowded cell backward after a forward (lists overflow: per-group cull)")
+    check_grads({k: v.cpu().numpy() for k, v in rad.eval_radiance_backward(g, *dev, dLd).items()},
+                gref)
+    say("case: crowded cell backward after a rebuild without forward (cull)")
+    g.build(*dev)
+    check_grads({k: v.cpu().numpy() for k, v in rad.eval_radiance_backward(g, *dev, dLd).items()},
+                gref)
+    # a sparse field where every group's survivors fit: lists against a cull
+    mu2, q2, ls2, rgb2, x2 = _grad_problem(22, 500, 3000, 0.2)
+    ref2 = O.radiance(mu2, q2, ls2, rgb2, x2)
+    _, dL2 = O.mse_loss(ref2["L"], rng.random((len(x2), 3)).astype(np.float32))
+    dL2 = _mask_ambiguous(ref2, dL2).astype(np.float32)
+    gref2 = O.radiance_backward(mu2, q2, ls2, rgb2, x2, dL2)
+    (dLd2,) = to_dev(dL2)
+    _, g2, dev2, qs2 = _eval(rad, (mu2, q2, ls2, rgb2), x2)
+    say("case: backward from lists vs after a rebuild (500 prims x 3000 points)")
+    listed = {k: v.cpu().numpy() for k, v in rad.eval_radiance_backward(g2, *dev2, dLd2).items()}
+    g2.build(*dev2)
+    culled = {k: v.cpu().numpy() for k, v in rad.eval_radiance_backward(g2, *dev2, dLd2).items()}
+    check_grads(listed, gref2)
+    check_grads(culled, gref2)
+
+
 def test_backward_c1_all_points(rad, c1):
     f, x, ref = c1
     T = np.random.default_rng(5).random((len(x), 3)).astype(np.float32) * 0.5
