@@ -260,9 +260,17 @@ def bench_render(args):
         e1 = mark() if timed else None
         xc, bc, fc, slot = PH.compact_photons(x, beta, face, with_slot=True)
         e2 = mark() if timed else None
-        qs = R.QuerySet(xc, args.cell)
+        # one query set and one grid for every image: after the first view
+        # they are re-binned and rebuilt in place, without allocating
+        if "qs" in info:
+            qs = info["qs"].rebin(xc)
+        else:
+            qs = info["qs"] = R.QuerySet(xc, args.cell)
         e3 = mark() if timed else None
-        g = R.HybridGrid(qs, args.radius).build(mu, quat, ls, rgb)
+        if "grid" in info:
+            g = info["grid"].build(mu, quat, ls, rgb)
+        else:
+            g = info["grid"] = R.HybridGrid(qs, args.radius).build(mu, quat, ls, rgb)
         e4 = mark() if timed else None
         Lq, Z, cnt = R.eval_hybrid(g, mu, quat, ls, rgb)
         e5 = mark() if timed else None
@@ -273,7 +281,7 @@ def bench_render(args):
         if timed:
             for k, (a, b) in zip(ev, ((e0, e1), (e1, e2), (e2, e3), (e3, e4), (e4, e5), (e5, e6))):
                 ev[k].append((a, b))
-        return g, qs, img
+        return img
 
     for t in range(1, args.warmup + 1):
         step(t, False)

@@ -80,6 +80,19 @@ const char *gpf_version(void);
  * box and the tile count).  *out receives a new handle. */
 gpf_status gpf_bin_queries(const float *x, int64_t q, float cell_size, void *stream,
                            gpf_queries **out);
+/* Re-bins new points x[q][3] into an existing handle, as gpf_bin_queries
+ * would, reusing its device buffers (and its binning scratch, which a rebin
+ * keeps): it allocates only when the new points need more room than any
+ * earlier binning of the handle, so a loop over views or frames stops
+ * allocating once the largest has been seen.  Every grid built on `qs`
+ * before the call is stale afterwards (its queries return GPF_ERR_STALE)
+ * until it is rebuilt with gpf_build_grid / gpf_build_grid_hybrid on the same
+ * handle.  On failure the handle holds no binning (q = 0) until the next
+ * successful rebin; it must still be destroyed.  Same limits on q and
+ * cell_size as gpf_bin_queries; the current device must be the one `qs` was
+ * created on.  Synchronises `stream`. */
+gpf_status gpf_rebin_queries(gpf_queries *qs, const float *x, int64_t q, float cell_size,
+                             void *stream);
 void gpf_queries_destroy(gpf_queries *qs);
 /* Host-side facts about a query set: number of points, of occupied cells and
  * of tiles, and the device bytes the handle holds. */

@@ -49,6 +49,7 @@ _SIG = {
     "gpf_last_error": (ctypes.c_char_p, []),
     "gpf_version": (ctypes.c_char_p, []),
     "gpf_bin_queries": (ctypes.c_int, [_P, _I64, _F, _P, ctypes.POINTER(_P)]),
+    "gpf_rebin_queries": (ctypes.c_int, [_P, _P, _I64, _F, _P]),
     "gpf_queries_destroy": (None, [_P]),
     "gpf_queries_info": (ctypes.c_int, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64),
                                         ctypes.POINTER(_I64), ctypes.POINTER(ctypes.c_size_t)]),

@@ -231,169 +231,198 @@ __global__ void group_box_kernel(const GroupInfo* __restrict__ groups, int ngrou
 
 }  // namespace
 
-gpf_status launch_bin_queries(const float* x, int64_t q, float cell, hipStream_t s,
-                              gpf_queries* out) {
-  out->x_user = x;
-  out->q = q;
-  out->cell = cell;
-  // 1. bounding box
-  float* part = nullptr;
-  gpf_status st = dev_alloc((void**)&part, (kRedBlocks * 6 + 6) * sizeof(float), "bbox");
+// (Re)allocates p to hold `want` bytes unless its current `cap` suffices.
+template <class T>
+static gpf_status grow(T*& p, size_t& cap, size_t want, const char* what) {
+  if (p && cap >= want) return GPF_OK;
+  dev_free((void*)p, cap);
+  p = nullptr;
+  cap = 0;
+  void* v = nullptr;
+  const gpf_status st = dev_alloc(&v, want, what);
   if (st != GPF_OK) return st;
-  hipLaunchKernelGGL(bbox_partial_kernel, dim3(kRedBlocks), dim3(256), 0, s, x, q, part);
-  hipLaunchKernelGGL(bbox_final_kernel, dim3(1), dim3(64), 0, s, part, kRedBlocks,
-                     part + kRedBlocks * 6);
+  p = (T*)v;
+  cap = want;
+  return GPF_OK;
+}
+
+template <class T>
+static void release(T*& p, size_t& cap) {
+  dev_free((void*)p, cap);
+  p = nullptr;
+  cap = 0;
+}
+
+void release_bin_scratch(gpf_queries* qs) {
+  release(qs->keys, qs->keys_cap);
+  release(qs->keys_s, qs->keys_s_cap);
+  release(qs->idx, qs->idx_cap);
+  release(qs->flag, qs->flag_cap);
+  release(qs->flag_s, qs->flag_s_cap);
+  release(qs->cell_first, qs->cell_first_cap);
+  release(qs->ntile, qs->ntile_cap);
+  release(qs->cell_first_g, qs->cell_first_g_cap);
+  release(qs->part, qs->part_cap);
+  release(qs->tmp, qs->tmp_cap);
+}
+
+void release_bin_outputs(gpf_queries* qs) {
+  release(qs->xs, qs->xs_cap);
+  release(qs->perm, qs->perm_cap);
+  release(qs->occ_of_dense, qs->occ_of_dense_cap);
+  release(qs->occ_dense, qs->occ_dense_cap);
+  release(qs->occ_bits, qs->occ_bits_cap);
+  release(qs->tiles, qs->tiles_cap);
+  release(qs->tile_lo, qs->tile_lo_cap);
+  release(qs->tile_hi, qs->tile_hi_cap);
+  release(qs->groups, qs->groups_cap);
+  release(qs->group_lo, qs->group_lo_cap);
+  release(qs->group_hi, qs->group_hi_cap);
+}
+
+// Bins x into `out`, reusing every buffer that is already large enough (a
+// rebin of a handle allocates only when the new points need more room).  The
+// scratch is released at the end unless keep_scratch.  On failure the handle
+// holds no valid binning (q = 0).
+gpf_status launch_bin_queries(const float* x, int64_t q, float cell, bool keep_scratch,
+                              hipStream_t s, gpf_queries* out) {
+  ++out->gen;  // grids built on the previous binning are stale from here on
+  out->q = 0;
+  out->ncells = out->ntiles = out->ngroups = 0;
+  gpf_status st;
+#define TRY(x)                                          \
+  do {                                                  \
+    gpf_status s_ = (x);                                \
+    if (s_ != GPF_OK) {                                 \
+      if (!keep_scratch) release_bin_scratch(out);      \
+      return s_;                                        \
+    }                                                   \
+  } while (0)
+#define TRYH(x, what)                                   \
+  do {                                                  \
+    hipError_t e_ = (x);                                \
+    if (e_ != hipSuccess) {                             \
+      if (!keep_scratch) release_bin_scratch(out);      \
+      return hip_fail(e_, what);                        \
+    }                                                   \
+  } while (0)
+  // 1. bounding box
+  TRY(grow(out->part, out->part_cap, (kRedBlocks * 6 + 6) * sizeof(float), "bbox"));
+  hipLaunchKernelGGL(bbox_partial_kernel, dim3(kRedBlocks), dim3(256), 0, s, x, q, out->part);
+  hipLaunchKernelGGL(bbox_final_kernel, dim3(1), dim3(64), 0, s, out->part, kRedBlocks,
+                     out->part + kRedBlocks * 6);
   float box[6];
-  hipError_t e = hipMemcpyAsync(box, part + kRedBlocks * 6, sizeof(box), hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
-  dev_free(part, (kRedBlocks * 6 + 6) * sizeof(float));
-  if (e != hipSuccess) return hip_fail(e, "bin_queries bbox");
+  TRYH(hipMemcpyAsync(box, out->part + kRedBlocks * 6, sizeof(box), hipMemcpyDeviceToHost, s),
+       "bin_queries bbox");
+  TRYH(hipStreamSynchronize(s), "bin_queries bbox");
   for (int a = 0; a < 6; ++a)
-    if (!std::isfinite(box[a]))
-      return set_error(GPF_ERR_INVALID_ARGUMENT, "query points contain NaN or Inf");
+    if (!std::isfinite(box[a])) TRY(set_error(GPF_ERR_INVALID_ARGUMENT, "query points contain NaN or Inf"));
   int64_t dense = 1;
   for (int a = 0; a < 3; ++a) {
     out->origin[a] = box[a];
     double ext = (double)box[3 + a] - (double)box[a];
     int64_t d = (int64_t)std::floor(ext / cell) + 1;
     if (d > kMaxDim)
-      return set_error(GPF_ERR_CAPACITY, "cell_size too small: more than 1024 cells per axis");
+      TRY(set_error(GPF_ERR_CAPACITY, "cell_size too small: more than 1024 cells per axis"));
     out->dims[a] = (int)d;
     dense *= d;
   }
-  if (dense > kMaxDense)
-    return set_error(GPF_ERR_CAPACITY, "cell_size too small: more than 2^26 cells");
+  if (dense > kMaxDense) TRY(set_error(GPF_ERR_CAPACITY, "cell_size too small: more than 2^26 cells"));
+  out->x_user = x;
+  out->cell = cell;
   GridGeom g{out->origin[0], out->origin[1], out->origin[2], 1.f / cell, out->dims[0],
              out->dims[1], out->dims[2]};
 
   // 2. keys and sort
-  uint64_t *keys = nullptr, *keys_s = nullptr;
-  int* idx = nullptr;
-  void* tmp = nullptr;
-  size_t tmp_bytes = 0;
-  int* flag = nullptr;
-  int* flag_s = nullptr;
-  int* cell_first = nullptr;
-  int* ntile = nullptr;
-  int* cell_first_g = nullptr;
-  auto cleanup = [&]() {
-    dev_free(cell_first_g, (q + 1) * 4);
-    dev_free(keys, q * 8);
-    dev_free(keys_s, q * 8);
-    dev_free(idx, q * 4);
-    dev_free(tmp, tmp_bytes);
-    dev_free(flag, (q + 1) * 4);
-    dev_free(flag_s, (q + 1) * 4);
-    dev_free(cell_first, (q + 1) * 4);
-    dev_free(ntile, (q + 1) * 4);
-  };
-#define TRY(x)              \
-  do {                      \
-    gpf_status s_ = (x);    \
-    if (s_ != GPF_OK) {     \
-      cleanup();            \
-      return s_;            \
-    }                       \
-  } while (0)
-#define TRYH(x, what)                               \
-  do {                                              \
-    hipError_t e_ = (x);                            \
-    if (e_ != hipSuccess) {                         \
-      cleanup();                                    \
-      return hip_fail(e_, what);                    \
-    }                                               \
-  } while (0)
-  TRY(dev_alloc((void**)&keys, q * 8, "keys"));
-  TRY(dev_alloc((void**)&keys_s, q * 8, "keys"));
-  TRY(dev_alloc((void**)&idx, q * 4, "idx"));
-  TRY(dev_alloc((void**)&out->perm, q * 4, "perm"));
-  TRY(dev_alloc((void**)&out->xs, q * sizeof(float4), "xs"));
-  TRY(dev_alloc((void**)&flag, (q + 1) * 4, "flag"));
-  int nb = (int)((q + 255) / 256);
-  hipLaunchKernelGGL(key_kernel, dim3(nb), dim3(256), 0, s, x, q, g, keys, idx);
-  TRYH(rocprim::radix_sort_pairs(nullptr, tmp_bytes, keys, keys_s, idx, out->perm, (size_t)q, 0, 60,
-                                 s),
+  TRY(grow(out->keys, out->keys_cap, q * 8, "keys"));
+  TRY(grow(out->keys_s, out->keys_s_cap, q * 8, "keys"));
+  TRY(grow(out->idx, out->idx_cap, q * 4, "idx"));
+  TRY(grow(out->perm, out->perm_cap, q * 4, "perm"));
+  TRY(grow(out->xs, out->xs_cap, q * sizeof(float4), "xs"));
+  TRY(grow(out->flag, out->flag_cap, (q + 1) * 4, "flag"));
+  TRY(grow(out->flag_s, out->flag_s_cap, (q + 1) * 4, "flag scan"));
+  const int nb = (int)((q + 255) / 256);
+  hipLaunchKernelGGL(key_kernel, dim3(nb), dim3(256), 0, s, x, q, g, out->keys, out->idx);
+  size_t sort_bytes = 0, scan_bytes = 0;
+  TRYH(rocprim::radix_sort_pairs(nullptr, sort_bytes, out->keys, out->keys_s, out->idx, out->perm,
+                                 (size_t)q, 0, 60, s),
        "radix_sort size");
-  TRY(dev_alloc(&tmp, tmp_bytes, "sort scratch"));
-  TRYH(rocprim::radix_sort_pairs(tmp, tmp_bytes, keys, keys_s, idx, out->perm, (size_t)q, 0, 60, s),
+  TRYH(rocprim::exclusive_scan(nullptr, scan_bytes, out->flag, out->flag_s, 0, (size_t)(q + 1),
+                               rocprim::plus<int>(), s),
+       "scan size");
+  TRY(grow(out->tmp, out->tmp_cap, std::max(sort_bytes, scan_bytes), "sort scratch"));
+  TRYH(rocprim::radix_sort_pairs(out->tmp, sort_bytes, out->keys, out->keys_s, out->idx, out->perm,
+                                 (size_t)q, 0, 60, s),
        "radix_sort");
-  hipLaunchKernelGGL(gather_kernel, dim3(nb), dim3(256), 0, s, x, keys_s, out->perm, q, out->xs,
-                     flag);
+  hipLaunchKernelGGL(gather_kernel, dim3(nb), dim3(256), 0, s, x, out->keys_s, out->perm, q,
+                     out->xs, out->flag);
   // run starts -> occupied-cell slots: a device-wide scan over q + 1 flags
   // (flag[q] = 0, so the last entry is the number of occupied cells)
-  TRY(dev_alloc((void**)&flag_s, (q + 1) * 4, "flag scan"));
-  TRYH(hipMemsetAsync(flag + q, 0, 4, s), "flag end");
-  {
-    size_t scan_bytes = 0;
-    TRYH(rocprim::exclusive_scan(nullptr, scan_bytes, flag, flag_s, 0, (size_t)(q + 1),
-                                 rocprim::plus<int>(), s),
-         "scan size");
-    if (scan_bytes > tmp_bytes) {
-      dev_free(tmp, tmp_bytes);
-      tmp = nullptr;
-      tmp_bytes = 0;
-      TRY(dev_alloc(&tmp, scan_bytes, "scan scratch"));
-      tmp_bytes = scan_bytes;
-    }
-    TRYH(rocprim::exclusive_scan(tmp, scan_bytes, flag, flag_s, 0, (size_t)(q + 1),
-                                 rocprim::plus<int>(), s),
-         "scan");
-  }
+  TRYH(hipMemsetAsync(out->flag + q, 0, 4, s), "flag end");
+  TRYH(rocprim::exclusive_scan(out->tmp, scan_bytes, out->flag, out->flag_s, 0, (size_t)(q + 1),
+                               rocprim::plus<int>(), s),
+       "scan");
   int ncells = 0;
-  TRYH(hipMemcpyAsync(&ncells, flag_s + q, 4, hipMemcpyDeviceToHost, s), "ncells readback");
+  TRYH(hipMemcpyAsync(&ncells, out->flag_s + q, 4, hipMemcpyDeviceToHost, s), "ncells readback");
   TRYH(hipStreamSynchronize(s), "ncells sync");
-  out->ncells = ncells;
-  TRY(dev_alloc((void**)&cell_first, (int64_t)(ncells + 1) * 4, "cell_first"));
-  TRY(dev_alloc((void**)&out->occ_dense, (int64_t)ncells * 4, "occ_dense"));
-  TRY(dev_alloc((void**)&out->occ_of_dense, dense * 4, "occ_of_dense"));
-  hipLaunchKernelGGL(cell_runs_kernel, dim3(nb), dim3(256), 0, s, out->xs, keys_s, flag_s, q, g,
-                     cell_first, out->occ_dense);
+  TRY(grow(out->cell_first, out->cell_first_cap, (int64_t)(ncells + 1) * 4, "cell_first"));
+  TRY(grow(out->occ_dense, out->occ_dense_cap, (int64_t)ncells * 4, "occ_dense"));
+  TRY(grow(out->occ_of_dense, out->occ_of_dense_cap, dense * 4, "occ_of_dense"));
+  TRY(grow(out->occ_bits, out->occ_bits_cap, ((dense + 31) / 32) * 4, "occupancy bits"));
+  hipLaunchKernelGGL(cell_runs_kernel, dim3(nb), dim3(256), 0, s, out->xs, out->keys_s, out->flag_s,
+                     q, g, out->cell_first, out->occ_dense);
   TRYH(hipMemsetAsync(out->occ_of_dense, 0xff, dense * 4, s), "occ table clear");
-  TRY(dev_alloc((void**)&out->occ_bits, ((dense + 31) / 32) * 4, "occupancy bits"));
   TRYH(hipMemsetAsync(out->occ_bits, 0, ((dense + 31) / 32) * 4, s), "occupancy bits clear");
-  int cb = (ncells + 255) / 256;
+  const int cb = (ncells + 255) / 256;
   hipLaunchKernelGGL(occ_table_kernel, dim3(cb), dim3(256), 0, s, out->occ_dense, ncells,
                      out->occ_of_dense, out->occ_bits);
-  TRY(dev_alloc((void**)&ntile, (int64_t)(ncells + 1) * 4, "ntile"));
-  hipLaunchKernelGGL(tiles_per_cell_kernel, dim3(cb), dim3(256), 0, s, cell_first, ncells, (int)q,
-                     ntile);
-  hipLaunchKernelGGL(scan_exclusive_kernel, dim3(1), dim3(kScanThreads), 0, s, ntile, ntile, ncells);
+  TRY(grow(out->ntile, out->ntile_cap, (int64_t)(ncells + 1) * 4, "ntile"));
+  hipLaunchKernelGGL(tiles_per_cell_kernel, dim3(cb), dim3(256), 0, s, out->cell_first, ncells,
+                     (int)q, out->ntile);
+  hipLaunchKernelGGL(scan_exclusive_kernel, dim3(1), dim3(kScanThreads), 0, s, out->ntile,
+                     out->ntile, ncells);
   int ntiles = 0;
-  TRYH(hipMemcpyAsync(&ntiles, ntile + ncells, 4, hipMemcpyDeviceToHost, s), "ntiles readback");
+  TRYH(hipMemcpyAsync(&ntiles, out->ntile + ncells, 4, hipMemcpyDeviceToHost, s), "ntiles readback");
   TRYH(hipStreamSynchronize(s), "ntiles sync");
-  out->ntiles = ntiles;
-  TRY(dev_alloc((void**)&out->tiles, (int64_t)ntiles * sizeof(TileInfo), "tiles"));
-  TRY(dev_alloc((void**)&out->tile_lo, (int64_t)ntiles * sizeof(float4), "tile_lo"));
-  TRY(dev_alloc((void**)&out->tile_hi, (int64_t)ntiles * sizeof(float4), "tile_hi"));
-  hipLaunchKernelGGL(tiles_fill_kernel, dim3(cb), dim3(256), 0, s, cell_first, ntile, ncells, (int)q,
-                     out->tiles);
+  TRY(grow(out->tiles, out->tiles_cap, (int64_t)ntiles * sizeof(TileInfo), "tiles"));
+  TRY(grow(out->tile_lo, out->tile_lo_cap, (int64_t)ntiles * sizeof(float4), "tile_lo"));
+  TRY(grow(out->tile_hi, out->tile_hi_cap, (int64_t)ntiles * sizeof(float4), "tile_hi"));
+  hipLaunchKernelGGL(tiles_fill_kernel, dim3(cb), dim3(256), 0, s, out->cell_first, out->ntile,
+                     ncells, (int)q, out->tiles);
   hipLaunchKernelGGL(tile_box_kernel, dim3((ntiles + 3) / 4), dim3(256), 0, s, out->xs, out->tiles,
                      ntiles, out->tile_lo, out->tile_hi);
   // groups of consecutive tiles per cell (ntile[] now holds the tile offsets)
-  TRY(dev_alloc((void**)&cell_first_g, (q + 1) * 4, "group offsets"));
-  hipLaunchKernelGGL(groups_per_cell_kernel, dim3(cb), dim3(256), 0, s, ntile, ncells, cell_first_g);
-  hipLaunchKernelGGL(scan_exclusive_kernel, dim3(1), dim3(kScanThreads), 0, s, cell_first_g,
-                     cell_first_g, ncells);
+  TRY(grow(out->cell_first_g, out->cell_first_g_cap, (q + 1) * 4, "group offsets"));
+  hipLaunchKernelGGL(groups_per_cell_kernel, dim3(cb), dim3(256), 0, s, out->ntile, ncells,
+                     out->cell_first_g);
+  hipLaunchKernelGGL(scan_exclusive_kernel, dim3(1), dim3(kScanThreads), 0, s, out->cell_first_g,
+                     out->cell_first_g, ncells);
   int ngroups = 0;
-  TRYH(hipMemcpyAsync(&ngroups, cell_first_g + ncells, 4, hipMemcpyDeviceToHost, s),
+  TRYH(hipMemcpyAsync(&ngroups, out->cell_first_g + ncells, 4, hipMemcpyDeviceToHost, s),
        "ngroups readback");
   TRYH(hipStreamSynchronize(s), "ngroups sync");
-  out->ngroups = ngroups;
-  TRY(dev_alloc((void**)&out->groups, (int64_t)ngroups * sizeof(GroupInfo), "groups"));
-  TRY(dev_alloc((void**)&out->group_lo, (int64_t)ngroups * sizeof(float4), "group_lo"));
-  TRY(dev_alloc((void**)&out->group_hi, (int64_t)ngroups * sizeof(float4), "group_hi"));
-  hipLaunchKernelGGL(groups_fill_kernel, dim3(cb), dim3(256), 0, s, ntile, cell_first_g, out->tiles,
-                     ncells, out->groups);
+  TRY(grow(out->groups, out->groups_cap, (int64_t)ngroups * sizeof(GroupInfo), "groups"));
+  TRY(grow(out->group_lo, out->group_lo_cap, (int64_t)ngroups * sizeof(float4), "group_lo"));
+  TRY(grow(out->group_hi, out->group_hi_cap, (int64_t)ngroups * sizeof(float4), "group_hi"));
+  hipLaunchKernelGGL(groups_fill_kernel, dim3(cb), dim3(256), 0, s, out->ntile, out->cell_first_g,
+                     out->tiles, ncells, out->groups);
   hipLaunchKernelGGL(group_box_kernel, dim3((ngroups + 255) / 256), dim3(256), 0, s, out->groups,
                      ngroups, out->tile_lo, out->tile_hi, out->group_lo, out->group_hi);
   TRYH(hipGetLastError(), "bin_queries launch");
   TRYH(hipStreamSynchronize(s), "bin_queries sync");
-  cleanup();
+  if (!keep_scratch) release_bin_scratch(out);
 #undef TRY
 #undef TRYH
-  out->bytes = q * (sizeof(float4) + 4) + dense * 4 + ((dense + 31) / 32) * 4 + (int64_t)ncells * 4 +
-               (int64_t)ntiles * (sizeof(TileInfo) + 2 * sizeof(float4)) +
-               (int64_t)ngroups * (sizeof(GroupInfo) + 2 * sizeof(float4));
+  out->q = q;
+  out->ncells = ncells;
+  out->ntiles = ntiles;
+  out->ngroups = ngroups;
+  out->bytes = out->xs_cap + out->perm_cap + out->occ_of_dense_cap + out->occ_dense_cap +
+               out->occ_bits_cap + out->tiles_cap + out->tile_lo_cap + out->tile_hi_cap +
+               out->groups_cap + out->group_lo_cap + out->group_hi_cap + out->keys_cap +
+               out->keys_s_cap + out->idx_cap + out->flag_cap + out->flag_s_cap +
+               out->cell_first_cap + out->ntile_cap + out->cell_first_g_cap + out->part_cap +
+               out->tmp_cap;
   return GPF_OK;
 }
 

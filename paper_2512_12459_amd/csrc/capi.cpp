@@ -83,6 +83,8 @@ static gpf_status check_grid_use(const gpf_grid* g, const gpf_field* f, const fl
   if (g->mu != f->mu || g->quat != f->quat || g->log_scale != f->log_scale ||
       g->rgb != f->rgb || g->n != f->n)
     return set_error(GPF_ERR_STALE, "field differs from the one the grid was built from");
+  if (g->qs_gen != g->qs->gen)
+    return set_error(GPF_ERR_STALE, "query set was re-binned after the grid was built");
   if (x != g->qs->x_user || q != g->qs->q)
     return set_error(GPF_ERR_STALE, "query points differ from the binned query set");
   return GPF_OK;
@@ -108,7 +110,7 @@ gpf_status gpf_bin_queries(const float* x, int64_t q, float cell_size, void* str
     return set_error(GPF_ERR_INVALID_ARGUMENT, "cell_size must be positive and finite");
   gpf_queries* qs = new gpf_queries();
   GPF_HIP(hipGetDevice(&qs->device));
-  gpf_status st = launch_bin_queries(x, q, cell_size, (hipStream_t)stream, qs);
+  gpf_status st = launch_bin_queries(x, q, cell_size, false, (hipStream_t)stream, qs);
   if (st != GPF_OK) {
     gpf_queries_destroy(qs);
     return st;
@@ -117,20 +119,25 @@ gpf_status gpf_bin_queries(const float* x, int64_t q, float cell_size, void* str
   return GPF_OK;
 }
 
+gpf_status gpf_rebin_queries(gpf_queries* qs, const float* x, int64_t q, float cell_size,
+                             void* stream) {
+  if (!qs) return set_error(GPF_ERR_INVALID_ARGUMENT, "query set is NULL");
+  if (!x) return set_error(GPF_ERR_INVALID_ARGUMENT, "x is NULL");
+  if (q < 1 || q > (int64_t)INT32_MAX - 64)
+    return set_error(GPF_ERR_INVALID_ARGUMENT, "q out of range [1, 2^31-65]");
+  if (!(cell_size > 0.f) || !(cell_size < 1e30f))
+    return set_error(GPF_ERR_INVALID_ARGUMENT, "cell_size must be positive and finite");
+  int dev = 0;
+  GPF_HIP(hipGetDevice(&dev));
+  if (dev != qs->device)
+    return set_error(GPF_ERR_INVALID_ARGUMENT, "query set belongs to another device");
+  return launch_bin_queries(x, q, cell_size, true, (hipStream_t)stream, qs);
+}
+
 void gpf_queries_destroy(gpf_queries* qs) {
   if (!qs) return;
-  int64_t nd = (int64_t)qs->dims[0] * qs->dims[1] * qs->dims[2];
-  dev_free(qs->xs, qs->q * sizeof(float4));
-  dev_free(qs->perm, qs->q * sizeof(int));
-  dev_free(qs->occ_of_dense, nd * sizeof(int));
-  dev_free(qs->occ_dense, qs->ncells * sizeof(int));
-  dev_free(qs->occ_bits, ((nd + 31) / 32) * 4);
-  dev_free(qs->tiles, qs->ntiles * sizeof(TileInfo));
-  dev_free(qs->tile_lo, qs->ntiles * sizeof(float4));
-  dev_free(qs->tile_hi, qs->ntiles * sizeof(float4));
-  dev_free(qs->groups, qs->ngroups * sizeof(GroupInfo));
-  dev_free(qs->group_lo, qs->ngroups * sizeof(float4));
-  dev_free(qs->group_hi, qs->ngroups * sizeof(float4));
+  release_bin_outputs(qs);
+  release_bin_scratch(qs);
   delete qs;
 }
 
@@ -152,6 +159,7 @@ gpf_status gpf_build_grid(const gpf_field* f, float cutoff, const gpf_queries* q
   if (!qs) return set_error(GPF_ERR_INVALID_ARGUMENT, "query set is NULL");
   if (!(cutoff > 0.f) || !(cutoff <= 16.f))
     return set_error(GPF_ERR_INVALID_ARGUMENT, "cutoff must lie in (0, 16]");
+  if (qs->q < 1) return set_error(GPF_ERR_INVALID_ARGUMENT, "query set holds no binning");
   gpf_grid* g = *grid;
   bool fresh = (g == nullptr);
   if (!fresh && g->qs != qs)
@@ -172,17 +180,17 @@ gpf_status gpf_build_grid(const gpf_field* f, float cutoff, const gpf_queries* q
     else g->n = -1;  // poison: the handle no longer matches any field
     return st;
   }
+  g->qs_gen = qs->gen;
   *grid = g;
   return GPF_OK;
 }
 
 void gpf_grid_destroy(gpf_grid* g) {
   if (!g) return;
-  int64_t nc = g->qs ? g->qs->ncells + 1 : 0;
   dev_free(g->rec, g->rec_cap * sizeof(PrimRec));
   dev_free(g->ext, g->rec_cap * sizeof(float4));
   dev_free(g->prim_off, (2 * g->rec_cap + 3) * sizeof(int));
-  dev_free(g->cell_start, nc * sizeof(int));
+  dev_free(g->cell_start, g->cell_start_cap * sizeof(int));
   dev_free(g->keys, g->cap * sizeof(int));
   dev_free(g->vals, g->cap * sizeof(int));
   dev_free(g->keys_sorted, g->cap * sizeof(int));
@@ -236,6 +244,7 @@ gpf_status gpf_build_grid_hybrid(const gpf_field* f, float r, int k_min, const g
   if (!qs) return set_error(GPF_ERR_INVALID_ARGUMENT, "query set is NULL");
   if (!(r > 0.f) || !std::isfinite(r)) return set_error(GPF_ERR_INVALID_ARGUMENT, "r must be positive and finite");
   if (k_min < 1 || k_min > 8) return set_error(GPF_ERR_INVALID_ARGUMENT, "k_min must lie in [1, 8]");
+  if (qs->q < 1) return set_error(GPF_ERR_INVALID_ARGUMENT, "query set holds no binning");
   gpf_grid* g = *grid;
   bool fresh = (g == nullptr);
   if (!fresh && g->qs != qs)
@@ -258,6 +267,7 @@ gpf_status gpf_build_grid_hybrid(const gpf_field* f, float r, int k_min, const g
     else g->n = -1;  // poison: the handle no longer matches any field
     return st;
   }
+  g->qs_gen = qs->gen;
   *grid = g;
   return GPF_OK;
 }
@@ -374,6 +384,7 @@ gpf_status gpf_photon_map_gather_binned(const gpf_photon_map* map, const gpf_que
                                         float* L, int* count, void* stream) {
   if (!map || !queries || !x_surface || !L) return set_error(GPF_ERR_INVALID_ARGUMENT, "NULL argument");
   if (!std::isfinite(weight)) return set_error(GPF_ERR_INVALID_ARGUMENT, "weight must be finite");
+  if (queries->q < 1) return set_error(GPF_ERR_INVALID_ARGUMENT, "query set holds no binning");
   return photon_map_gather_binned(map, queries, x_surface, weight, accumulate != 0, L, count,
                                   (hipStream_t)stream);
 }

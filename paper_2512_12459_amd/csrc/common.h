@@ -50,6 +50,7 @@ struct gpf_queries {
   int dims[3] = {0, 0, 0};
   int64_t ncells = 0;   // occupied cells
   int64_t ntiles = 0;
+  uint64_t gen = 0;     // bumped by every (re)binning; grids record the value they were built on
   float4* xs = nullptr;          // [q] sorted points (w unused)
   int* perm = nullptr;           // [q] sorted position -> caller index
   int* occ_of_dense = nullptr;   // [dims product] dense cell -> occupied slot or -1
@@ -63,6 +64,18 @@ struct gpf_queries {
   float4* group_lo = nullptr;        // [ngroups] box of the group's points
   float4* group_hi = nullptr;
   size_t bytes = 0;
+  // allocated bytes of each array above, so that a rebin reuses them
+  size_t xs_cap = 0, perm_cap = 0, occ_of_dense_cap = 0, occ_dense_cap = 0, occ_bits_cap = 0,
+         tiles_cap = 0, tile_lo_cap = 0, tile_hi_cap = 0, groups_cap = 0, group_lo_cap = 0,
+         group_hi_cap = 0;
+  // binning scratch, kept between rebins (released after a one-off binning)
+  uint64_t *keys = nullptr, *keys_s = nullptr;
+  int *idx = nullptr, *flag = nullptr, *flag_s = nullptr, *cell_first = nullptr,
+      *ntile = nullptr, *cell_first_g = nullptr;
+  float* part = nullptr;
+  void* tmp = nullptr;
+  size_t keys_cap = 0, keys_s_cap = 0, idx_cap = 0, flag_cap = 0, flag_s_cap = 0,
+         cell_first_cap = 0, ntile_cap = 0, cell_first_g_cap = 0, part_cap = 0, tmp_cap = 0;
 };
 
 struct gpf_grid {
@@ -75,6 +88,8 @@ struct gpf_grid {
   int64_t rec_cap = 0;
   int* prim_off = nullptr;      // [n + 1] per-primitive entry counts, scanned in place
   int* cell_start = nullptr;    // [ncells + 1]
+  int64_t cell_start_cap = 0;   // allocated entries of cell_start
+  uint64_t qs_gen = 0;          // query-set binning this grid was built on
   int* keys = nullptr;          // [cap] cell slot per entry (primitive-major)
   int* vals = nullptr;          // [cap] primitive per entry (primitive-major)
   int* keys_sorted = nullptr;   // [cap]
@@ -129,7 +144,9 @@ gpf_status dev_alloc(void** p, size_t bytes, const char* what);
 void dev_free(void* p, size_t bytes);
 
 // Launchers implemented in the .hip files.  They only enqueue work.
-gpf_status launch_bin_queries(const float* x, int64_t q, float cell, hipStream_t s,
+void release_bin_scratch(gpf_queries* qs);
+void release_bin_outputs(gpf_queries* qs);
+gpf_status launch_bin_queries(const float* x, int64_t q, float cell, bool keep_scratch, hipStream_t s,
                               gpf_queries* out);
 gpf_status launch_build_grid(gpf_grid* g, hipStream_t s);
 gpf_status launch_eval_fwd(const gpf_grid* g, float* L, hipStream_t s);

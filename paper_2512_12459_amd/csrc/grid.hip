@@ -235,9 +235,13 @@ gpf_status launch_build_grid(gpf_grid* g, hipStream_t s) {
     }
     g->rec_cap = n;
   }
-  if (!g->cell_start) {
+  if (g->cell_start_cap < nc + 1) {  // the query set may have been re-binned into more cells
+    dev_free(g->cell_start, g->cell_start_cap * sizeof(int));
+    g->cell_start = nullptr;
+    g->cell_start_cap = 0;
     gpf_status st = dev_alloc((void**)&g->cell_start, (size_t)(nc + 1) * sizeof(int), "cell starts");
     if (st != GPF_OK) return st;
+    g->cell_start_cap = nc + 1;
   }
   Geom geo{qs->origin[0], qs->origin[1], qs->origin[2], qs->cell, qs->dims[0], qs->dims[1],
            qs->dims[2]};

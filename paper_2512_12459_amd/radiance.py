@@ -41,8 +41,10 @@ def field_struct(mu, quat, log_scale, rgb) -> C.Field:
 
 
 class QuerySet:
-    """Visible points x [q,3] (device, float32) binned once into cells of edge
-    ``cell_size``; keeps a reference to x, which must not change afterwards."""
+    """Visible points x [q,3] (device, float32) binned into cells of edge
+    ``cell_size``; keeps a reference to x, which must not change afterwards.
+    ``rebin`` re-uses the handle (and its device buffers) for new points;
+    grids built on it must then be rebuilt."""
 
     def __init__(self, x: torch.Tensor, cell_size: float = 0.025):
         _need(x, "x", 3)
@@ -52,6 +54,15 @@ class QuerySet:
         C.check(C.lib().gpf_bin_queries(C.ptr(x), x.shape[0], self.cell_size, _stream(),
                                         ctypes.byref(h)))
         self.handle = h
+
+    def rebin(self, x: torch.Tensor, cell_size: float | None = None) -> "QuerySet":
+        _need(x, "x", 3)
+        if cell_size is not None:
+            self.cell_size = float(cell_size)
+        self.x = x
+        C.check(C.lib().gpf_rebin_queries(self.handle, C.ptr(x), x.shape[0], self.cell_size,
+                                          _stream()))
+        return self
 
     def info(self) -> dict:
         q, c, t = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()

@@ -206,3 +206,47 @@ def test_fitting_with_the_hybrid_query_raises_psnr(rad):
     p1 = res["history"][-1][1]
     say(f"after 60 steps {p1:.2f} dB")
     assert p1 > p0 + 3.0
+
+
+def test_rebinned_query_set_matches_a_fresh_one(rad):
+    """gpf_rebin_queries: one handle re-binned to a larger, then a smaller point
+    set (another cell size) gives the binning of a fresh handle; grids built
+    before a rebin are refused until rebuilt in place on it."""
+    from paper_2512_12459_amd._lib import GPFError
+    f = _field(30, 1500, 0.3)
+    dev = to_dev(*f)
+    xs = [_points(31, 3000, 0.3), _points(32, 12000, 0.35), _points(33, 700, 0.25)]
+    cells = [0.025, 0.025, 0.05]
+    (x0,) = to_dev(xs[0])
+    qs = rad.QuerySet(x0, cells[0])
+    hg = rad.HybridGrid(qs).build(*dev)
+    tg = rad.Grid(qs).build(*dev)
+    for i, (x, cell) in enumerate(zip(xs[1:], cells[1:]), 1):
+        say(f"case: rebin to {len(x)} points, cell {cell}")
+        (xd,) = to_dev(x)
+        qs.rebin(xd, cell)
+        for g, ev in ((hg, rad.eval_hybrid), (tg, rad.eval_radiance)):
+            with pytest.raises(GPFError) as e:
+                ev(g, *dev)
+            assert e.value.status == 5
+        fresh = rad.QuerySet(xd, cell)
+        assert qs.info()["q"] == len(x)
+        assert {k: v for k, v in qs.info().items() if k != "device_bytes"} == \
+            {k: v for k, v in fresh.info().items() if k != "device_bytes"}
+        got = rad.eval_hybrid(hg.build(*dev), *dev)
+        want = rad.eval_hybrid(rad.HybridGrid(fresh).build(*dev), *dev)
+        for a, b in zip(got, want):
+            assert torch.equal(a, b)
+        Lt = rad.eval_radiance(tg.build(*dev), *dev)
+        assert torch.equal(Lt, rad.eval_radiance(rad.Grid(fresh).build(*dev), *dev))
+        if i == 2:  # the smaller set against the oracle, backward included
+            ref = H.radiance(*f, x, R_Q, 3, 1e-6)
+            L, Z, cnt = got
+            check_hybrid_forward(L.cpu().numpy(), Z.cpu().numpy(), cnt.cpu().numpy(), ref)
+            dL = np.random.default_rng(34).normal(size=(len(x), 3)).astype(np.float32)
+            (dLd,) = to_dev(dL)
+            gg = rad.eval_hybrid_backward(hg, *dev, L, Z, cnt, dLd)
+            gref = H.radiance_backward(*f, x, dL, R_Q, 3, 1e-6, sets=ref["sets"])
+            check_grads({k: v.cpu().numpy() for k, v in gg.items()}, gref)
+        fresh.close()
+    torch.cuda.synchronize()
