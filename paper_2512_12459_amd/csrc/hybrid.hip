@@ -200,34 +200,46 @@ __device__ void nearest_centres(float px, float py, float pz, const PGrid& cg,
   // no centre in any cell the rings below would visit: nothing to find
   if (!near[(c.z * cg.dy + c.y) * cg.dx + c.x]) return;
   const int maxr = min(max_rings, max(cg.dx, max(cg.dy, cg.dz)));
-  for (int rr = 0; rr <= maxr; ++rr) {
-    for (int zc = c.z - rr; zc <= c.z + rr; ++zc) {
-      if (zc < 0 || zc >= cg.dz) continue;
-      for (int yc = c.y - rr; yc <= c.y + rr; ++yc) {
-        if (yc < 0 || yc >= cg.dy) continue;
-        for (int xc = c.x - rr; xc <= c.x + rr; ++xc) {
-          if (xc < 0 || xc >= cg.dx) continue;
-          if (max(abs(xc - c.x), max(abs(yc - c.y), abs(zc - c.z))) != rr) continue;
-          const int cell = (zc * cg.dy + yc) * cg.dx + xc;
-          for (int s = cstart[cell]; s < cstart[cell + 1]; ++s) {
-            const int j = csorted[s];
-            const float4 m = recs[j].r0;
-            const float d = sq_len(px - m.x, py - m.y, pz - m.z);
-            if (d > reach2 || !nearer(d, j, bd[K - 1], bi[K - 1])) continue;
-            bd[K - 1] = d;
-            bi[K - 1] = j;
+  // one centre: the usual insertion into the (d2, index)-ordered list
+  auto visit = [&](int s) {
+    const int j = csorted[s];
+    const float4 m = recs[j].r0;
+    const float d = sq_len(px - m.x, py - m.y, pz - m.z);
+    if (d > reach2 || !nearer(d, j, bd[K - 1], bi[K - 1])) return;
+    bd[K - 1] = d;
+    bi[K - 1] = j;
 #pragma unroll
-            for (int a = K - 1; a > 0; --a) {
-              if (nearer(bd[a], bi[a], bd[a - 1], bi[a - 1])) {
-                const float td = bd[a];
-                bd[a] = bd[a - 1];
-                bd[a - 1] = td;
-                const int ti = bi[a];
-                bi[a] = bi[a - 1];
-                bi[a - 1] = ti;
-              }
-            }
-          }
+    for (int a = K - 1; a > 0; --a) {
+      if (nearer(bd[a], bi[a], bd[a - 1], bi[a - 1])) {
+        const float td = bd[a];
+        bd[a] = bd[a - 1];
+        bd[a - 1] = td;
+        const int ti = bi[a];
+        bi[a] = bi[a - 1];
+        bi[a - 1] = ti;
+      }
+    }
+  };
+  for (int rr = 0; rr <= maxr; ++rr) {
+    // the shell of Chebyshev radius rr around c: rows of the two z faces and
+    // the two y faces are whole x runs (contiguous in the cell-sorted order);
+    // every other row contributes its two end cells
+    const int x0 = max(c.x - rr, 0), x1 = min(c.x + rr, cg.dx - 1);
+    for (int zc = max(c.z - rr, 0); zc <= min(c.z + rr, cg.dz - 1); ++zc) {
+      const bool zface = abs(zc - c.z) == rr;
+      for (int yc = max(c.y - rr, 0); yc <= min(c.y + rr, cg.dy - 1); ++yc) {
+        const int row = (zc * cg.dy + yc) * cg.dx;
+        const bool whole = zface || abs(yc - c.y) == rr;
+        // at most two cell runs of this row: [a0, a1] and [b0, b1] (empty if b0 > b1)
+        const int a0 = whole ? x0 : (c.x - rr >= 0 ? c.x - rr : c.x + rr);
+        const int a1 = whole ? x1 : a0;
+        const int b0 = whole || c.x - rr < 0 ? 1 : c.x + rr, b1 = whole || c.x - rr < 0 ? 0 : b0;
+#pragma unroll 1
+        for (int run = 0; run < 2; ++run) {
+          const int lo = run ? b0 : a0, hi = run ? b1 : a1;
+          if (lo > hi || hi >= cg.dx) continue;
+#pragma unroll 1
+          for (int s = cstart[row + lo], e = cstart[row + hi + 1]; s < e; ++s) visit(s);
         }
       }
     }
@@ -522,9 +534,11 @@ __global__ void __launch_bounds__(256) hybrid_topup_bwd_kernel(
 // Distance beyond which a single-precision weight is exactly zero (falloff
 // below 2^-212), and the rings of centre-grid cells that cover it.
 double topup_reach(float rb) { return (double)rb + 7.0 * std::fmax((double)rb, 1e-6); }
-// Cells have edge at least (1 + 1e-4) D / 2, so a centre within D of a point
+// Cells have edge at least (1 + 1e-4) D / 4, so a centre within D of a point
 // lies at most ceil(D / h) cells away along each axis, with room for the
-// single-precision rounding of cell indices.
+// single-precision rounding of cell indices.  (A quarter of the reach keeps
+// the rings that a typical top-up point scans, those within a few ball radii,
+// to a few dozen centres on surface-like fields.)
 int topup_rings(const gpf_grid* g) {
   return (int)std::ceil(topup_reach(g->ball) / (double)g->cg_h);
 }
@@ -570,7 +584,7 @@ gpf_status build_centre_grid(gpf_grid* g, hipStream_t s) {
   GPF_HIP(hipStreamSynchronize(s));
   PGrid pg;
   gpf_status st =
-      point_grid_geometry(hp, n, kCentreDim, &pg, 0.5 * (1.0 + 1e-4) * topup_reach(g->ball));
+      point_grid_geometry(hp, n, kCentreDim, &pg, 0.25 * (1.0 + 1e-4) * topup_reach(g->ball));
   if (st != GPF_OK) return st;
   const int64_t cells = (int64_t)pg.dx * pg.dy * pg.dz;
   if (g->cg_cells_cap < cells || g->cg_n_cap < n) {
@@ -634,10 +648,11 @@ gpf_status launch_hybrid_fwd(const gpf_grid* gc, float eps, float* L, float* Z, 
                      qs->tile_lo, qs->tile_hi, g->cell_start, g->cell_prims, g->rec, r2, r2pad,
                      eps, L, Z, count, g->surv, g->surv ? g->surv_count : nullptr);
   const unsigned blocks = (unsigned)((qs->q + 255) / 256);
-  hipLaunchKernelGGL(hybrid_topup_fwd_kernel<kTopUpMax>, dim3(blocks), dim3(256), 0, s,
-                     qs->x_user, qs->q, centre_geom(g), g->cg_start, g->cg_sorted, g->cg_near,
-                     g->rec, g->k_min, g->ball, topup_reach2(g->ball), topup_rings(g), eps, L, Z,
-                     count);
+  // the nearest-centre list only needs k_min slots: 4 covers k_min <= 4
+  auto topup = g->k_min <= 4 ? hybrid_topup_fwd_kernel<4> : hybrid_topup_fwd_kernel<kTopUpMax>;
+  hipLaunchKernelGGL(topup, dim3(blocks), dim3(256), 0, s, qs->x_user, qs->q, centre_geom(g),
+                     g->cg_start, g->cg_sorted, g->cg_near, g->rec, g->k_min, g->ball,
+                     topup_reach2(g->ball), topup_rings(g), eps, L, Z, count);
   GPF_HIP(hipGetLastError());
   g->surv_ready = g->surv != nullptr;
   return GPF_OK;
@@ -658,10 +673,10 @@ gpf_status launch_hybrid_bwd(const gpf_grid* gc, float eps, const float* L, cons
                      eps, g->k_min, L, Z, count, dL, (float*)g->grad_rows,
                      g->surv_ready ? g->surv : nullptr, g->surv_ready ? g->surv_count : nullptr);
   const unsigned blocks = (unsigned)((qs->q + 255) / 256);
-  hipLaunchKernelGGL(hybrid_topup_bwd_kernel<kTopUpMax>, dim3(blocks), dim3(256), 0, s,
-                     qs->x_user, qs->q, centre_geom(g), g->cg_start, g->cg_sorted, g->cg_near,
-                     g->rec, g->k_min, g->ball, topup_reach2(g->ball), topup_rings(g), eps, L, Z,
-                     count, dL,
+  auto topup = g->k_min <= 4 ? hybrid_topup_bwd_kernel<4> : hybrid_topup_bwd_kernel<kTopUpMax>;
+  hipLaunchKernelGGL(topup, dim3(blocks), dim3(256), 0, s, qs->x_user, qs->q, centre_geom(g),
+                     g->cg_start, g->cg_sorted, g->cg_near, g->rec, g->k_min, g->ball,
+                     topup_reach2(g->ball), topup_rings(g), eps, L, Z, count, dL,
                      (float*)g->grad_rows);
   GPF_HIP(hipGetLastError());
   return launch_grad_finalize(g, grad, s);
