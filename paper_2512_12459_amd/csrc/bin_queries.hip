@@ -31,6 +31,11 @@ __device__ __forceinline__ uint64_t morton3(uint32_t a, uint32_t b, uint32_t c) 
   return spread3(a) | (spread3(b) << 1) | (spread3(c) << 2);
 }
 
+// min / max that keep a NaN once seen (fminf / fmaxf would drop it), so a
+// non-finite point always reaches the host check of the box
+__device__ __forceinline__ float min_keep_nan(float a, float b) { return (b < a || b != b) ? b : a; }
+__device__ __forceinline__ float max_keep_nan(float a, float b) { return (b > a || b != b) ? b : a; }
+
 __global__ void bbox_partial_kernel(const float* __restrict__ x, int64_t q, float* part) {
   float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < q;
@@ -38,8 +43,8 @@ __global__ void bbox_partial_kernel(const float* __restrict__ x, int64_t q, floa
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       float v = x[i * 3 + a];
-      lo[a] = fminf(lo[a], v);
-      hi[a] = fmaxf(hi[a], v);
+      lo[a] = min_keep_nan(lo[a], v);
+      hi[a] = max_keep_nan(hi[a], v);
     }
   }
   __shared__ float s[6][256];
@@ -53,8 +58,8 @@ __global__ void bbox_partial_kernel(const float* __restrict__ x, int64_t q, floa
     if (threadIdx.x < st) {
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
-        s[a][threadIdx.x] = fminf(s[a][threadIdx.x], s[a][threadIdx.x + st]);
-        s[3 + a][threadIdx.x] = fmaxf(s[3 + a][threadIdx.x], s[3 + a][threadIdx.x + st]);
+        s[a][threadIdx.x] = min_keep_nan(s[a][threadIdx.x], s[a][threadIdx.x + st]);
+        s[3 + a][threadIdx.x] = max_keep_nan(s[3 + a][threadIdx.x], s[3 + a][threadIdx.x + st]);
       }
     }
     __syncthreads();
@@ -62,12 +67,28 @@ __global__ void bbox_partial_kernel(const float* __restrict__ x, int64_t q, floa
   if (threadIdx.x < 6) part[blockIdx.x * 6 + threadIdx.x] = s[threadIdx.x][0];
 }
 
-__global__ void bbox_final_kernel(const float* part, int nparts, float* out) {
-  int a = threadIdx.x;
-  if (a >= 6) return;
-  float v = part[a];
-  for (int b = 1; b < nparts; ++b) v = a < 3 ? fminf(v, part[b * 6 + a]) : fmaxf(v, part[b * 6 + a]);
-  out[a] = v;
+// One wave: lane l folds partials l, l + 64, ... (independent loads), then a
+// butterfly over the wave.
+__global__ void __launch_bounds__(64) bbox_final_kernel(const float* part, int nparts, float* out) {
+  const int lane = threadIdx.x;
+  float v[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+  for (int b = lane; b < nparts; b += 64) {
+#pragma unroll
+    for (int a = 0; a < 6; ++a)
+      v[a] = a < 3 ? min_keep_nan(v[a], part[b * 6 + a]) : max_keep_nan(v[a], part[b * 6 + a]);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+    for (int a = 0; a < 6; ++a) {
+      const float o = __shfl_xor(v[a], off, 64);
+      v[a] = a < 3 ? min_keep_nan(v[a], o) : max_keep_nan(v[a], o);
+    }
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int a = 0; a < 6; ++a) out[a] = v[a];
+  }
 }
 
 struct GridGeom {
@@ -146,21 +167,32 @@ __global__ void tiles_per_cell_kernel(const int* __restrict__ cell_first, int nc
   ntile[s] = (cnt + kTile - 1) / kTile;
 }
 
-__global__ void tiles_fill_kernel(const int* __restrict__ cell_first, const int* __restrict__ toff,
-                                  int ncells, int q, TileInfo* tiles) {
-  int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= ncells) return;
-  int start = cell_first[s];
-  int end = (s + 1 < ncells) ? cell_first[s + 1] : q;
-  int t = toff[s];
-  for (int a = start; a < end; a += kTile, ++t) {
-    TileInfo ti;
-    ti.start = a;
-    ti.count = min(kTile, end - a);
-    ti.cell = s;
-    ti.pad = 0;
-    tiles[t] = ti;
+// Largest s in [0, n) with off[s] <= i, for strictly increasing offsets
+// (every occupied cell has at least one tile and one group).
+__device__ __forceinline__ int owner_of(const int* __restrict__ off, int n, int i) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= i) lo = mid;
+    else hi = mid - 1;
   }
+  return lo;
+}
+
+// One thread per tile: tile t - toff[s] of cell s covers kTile points from
+// the cell's first point on (the last one of a cell may be ragged).
+__global__ void tiles_fill_kernel(const int* __restrict__ cell_first, const int* __restrict__ toff,
+                                  int ncells, int ntiles, int q, TileInfo* tiles) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ntiles) return;
+  const int s = owner_of(toff, ncells, t);
+  const int end = (s + 1 < ncells) ? cell_first[s + 1] : q;
+  TileInfo ti;
+  ti.start = cell_first[s] + (t - toff[s]) * kTile;
+  ti.count = min(kTile, end - ti.start);
+  ti.cell = s;
+  ti.pad = 0;
+  tiles[t] = ti;
 }
 
 // One wave per tile: tight box of its points.
@@ -194,22 +226,22 @@ __global__ void groups_per_cell_kernel(const int* __restrict__ toff, int ncells,
   ngroup[s] = (nt + kGroupTiles - 1) / kGroupTiles;
 }
 
+// One thread per group: group g - goff[s] of cell s takes the next
+// kGroupTiles tiles of the cell (fewer at the cell's end).
 __global__ void groups_fill_kernel(const int* __restrict__ toff, const int* __restrict__ goff,
-                                   const TileInfo* __restrict__ tiles, int ncells,
+                                   const TileInfo* __restrict__ tiles, int ncells, int ngroups,
                                    GroupInfo* groups) {
-  int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= ncells) return;
-  int t0 = toff[s], t1 = toff[s + 1];
-  int g = goff[s];
-  for (int t = t0; t < t1; t += kGroupTiles, ++g) {
-    int tl = min(t + kGroupTiles, t1) - 1;
-    GroupInfo gi;
-    gi.start = tiles[t].start;
-    gi.count = tiles[tl].start + tiles[tl].count - gi.start;
-    gi.cell = s;
-    gi.first_tile = t;
-    groups[g] = gi;
-  }
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= ngroups) return;
+  const int s = owner_of(goff, ncells, g);
+  const int t = toff[s] + (g - goff[s]) * kGroupTiles;
+  const int tl = min(t + kGroupTiles, toff[s + 1]) - 1;
+  GroupInfo gi;
+  gi.start = tiles[t].start;
+  gi.count = tiles[tl].start + tiles[tl].count - gi.start;
+  gi.cell = s;
+  gi.first_tile = t;
+  groups[g] = gi;
 }
 
 __global__ void group_box_kernel(const GroupInfo* __restrict__ groups, int ngroups,
@@ -387,8 +419,8 @@ gpf_status launch_bin_queries(const float* x, int64_t q, float cell, bool keep_s
   TRY(grow(out->tiles, out->tiles_cap, (int64_t)ntiles * sizeof(TileInfo), "tiles"));
   TRY(grow(out->tile_lo, out->tile_lo_cap, (int64_t)ntiles * sizeof(float4), "tile_lo"));
   TRY(grow(out->tile_hi, out->tile_hi_cap, (int64_t)ntiles * sizeof(float4), "tile_hi"));
-  hipLaunchKernelGGL(tiles_fill_kernel, dim3(cb), dim3(256), 0, s, out->cell_first, out->ntile,
-                     ncells, (int)q, out->tiles);
+  hipLaunchKernelGGL(tiles_fill_kernel, dim3((ntiles + 255) / 256), dim3(256), 0, s,
+                     out->cell_first, out->ntile, ncells, ntiles, (int)q, out->tiles);
   hipLaunchKernelGGL(tile_box_kernel, dim3((ntiles + 3) / 4), dim3(256), 0, s, out->xs, out->tiles,
                      ntiles, out->tile_lo, out->tile_hi);
   // groups of consecutive tiles per cell (ntile[] now holds the tile offsets)
@@ -404,8 +436,8 @@ gpf_status launch_bin_queries(const float* x, int64_t q, float cell, bool keep_s
   TRY(grow(out->groups, out->groups_cap, (int64_t)ngroups * sizeof(GroupInfo), "groups"));
   TRY(grow(out->group_lo, out->group_lo_cap, (int64_t)ngroups * sizeof(float4), "group_lo"));
   TRY(grow(out->group_hi, out->group_hi_cap, (int64_t)ngroups * sizeof(float4), "group_hi"));
-  hipLaunchKernelGGL(groups_fill_kernel, dim3(cb), dim3(256), 0, s, out->ntile, out->cell_first_g,
-                     out->tiles, ncells, out->groups);
+  hipLaunchKernelGGL(groups_fill_kernel, dim3((ngroups + 255) / 256), dim3(256), 0, s, out->ntile,
+                     out->cell_first_g, out->tiles, ncells, ngroups, out->groups);
   hipLaunchKernelGGL(group_box_kernel, dim3((ngroups + 255) / 256), dim3(256), 0, s, out->groups,
                      ngroups, out->tile_lo, out->tile_hi, out->group_lo, out->group_hi);
   TRYH(hipGetLastError(), "bin_queries launch");

@@ -122,6 +122,28 @@ def test_errors_are_reported(rad):
     assert e.value.status == 1
     with pytest.raises(GPFError):
         rad.QuerySet(x, -1.0)
+    say("case: NaN / Inf query point -> invalid argument; a failed rebin leaves no binning")
+    for bad in (float("nan"), float("inf")):
+        xb = x.clone()
+        xb[37, 1] = bad
+        with pytest.raises(GPFError) as e:
+            rad.QuerySet(xb, 0.1)
+        assert e.value.status == 1
+    qs2 = rad.QuerySet(x.clone(), 0.1)
+    xb = x.clone()
+    xb[5, 2] = float("nan")
+    with pytest.raises(GPFError) as e:
+        qs2.rebin(xb)
+    assert e.value.status == 1 and qs2.info()["q"] == 0
+    q1 = torch.zeros_like(q)
+    q1[:, 0] = 1.0
+    with pytest.raises(GPFError) as e:
+        rad.Grid(qs2).build(mu, q1, ls, rgb)
+    assert e.value.status == 1
+    qs2.rebin(x)
+    assert qs2.info()["q"] == x.shape[0]
+    rad.Grid(qs2).build(mu, q1, ls, rgb)
+    qs2.close()
     q2 = q.clone()
     q2[:, 0] = 1.0
     g = rad.Grid(qs).build(mu, q2, ls, rgb)
