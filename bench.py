@@ -104,6 +104,27 @@ def cpu_baseline(field, x, sample: int, seed: int = 11, hybrid: bool = False):
                        + ("neighbourhood" if hybrid else "contributing") + f" pairs; {dt:.1f} s wall")
 
 
+def cpu_exact_cull_baseline(field, x, sample: int, seed: int = 12):
+    """The oracle's exact-cull FP64 forward (its own CPU grid over the
+    primitives, OpenMP over query points) on a bounded random sample: the
+    algorithmic CPU baseline for the forward, without brute force's all-pairs
+    tests."""
+    import numpy as np
+
+    from oracle import exact_cull as E
+    rng = np.random.default_rng(seed)
+    sel = np.sort(rng.choice(x.shape[0], min(sample, x.shape[0]), replace=False))
+    E.radiance(*field.arrays(), x[sel[:64]])  # loads (and if needed builds) the C code
+    t0 = time.perf_counter()
+    ref = E.radiance(*field.arrays(), x[sel])
+    dt = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", 0)) or (os.cpu_count() or 1)
+    return dict(value=len(sel) / dt, unit="queries/s", cores=threads, kind="oracle",
+                sample=f"{len(sel)} random query points of the same workload, FP64 exact-cull "
+                       f"forward (CPU grid over all {field.n} primitives), {threads} OpenMP "
+                       f"threads; {int(ref['count'].sum())} contributing pairs; {dt:.1f} s wall")
+
+
 def cpu_sppm_baseline(x, xs, n_paths, r, seed, sample: int):
     """The FP64 oracle's photon tracing (all n_paths paths) and density
     estimate at a bounded random sample of the points, single process."""
@@ -336,6 +357,9 @@ def main():
     ap.add_argument("--paths", type=int, default=100_000,
                     help="photon paths per iteration of the sppm workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-exact-cull", type=int, default=0, metavar="POINTS",
+                    help="also time the oracle's exact-cull FP64 forward on this many sampled "
+                         "points (truncated query)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MB",
                     help="only run a plain device-to-device copy of MB megabytes (5 times), "
                          "to scale hardware byte counters")
@@ -485,7 +509,7 @@ def main():
     flops = pairs * (fl_bwd if dom == "bwd" else fl_fwd)
     achieved = flops / (ms[dom] * 1e-3)
     result = {
-        "metric": "fwd+bwd radiance queries/s @1M Gaussians"
+        "metric": f"fwd+bwd radiance queries/s @{n / 1e6:g}M Gaussians"
                   + (", hybrid query (ball r, top-up to 3 nearest, normalised)" if hybrid else ""),
         "value": value,
         "unit": "queries/s",
@@ -526,6 +550,9 @@ def main():
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         result["cpu_baseline"] = cpu_baseline(field, x, args.cpu_sample, hybrid=hybrid)
+    if args.cpu_exact_cull and not hybrid:
+        log("cpu exact-cull forward (oracle) ...")
+        result["cpu_exact_cull_forward"] = cpu_exact_cull_baseline(field, x, args.cpu_exact_cull)
     print(json.dumps(result), flush=True)
 
 
