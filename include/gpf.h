@@ -217,7 +217,7 @@ gpf_status gpf_compact_photons(const float *pos, const float *power, const int *
 
 /* Photon map for the density estimate: the photons ppos[np][3],
  * ppower[np][3], psurface[np] (device; copied, so the caller may free them
- * afterwards) binned into a uniform grid of cells of edge >= r in cell order.
+ * afterwards) binned into a uniform grid of cells of edge >= r/2 in cell order.
  * 1 <= np < 2^31; r > 0 finite; non-finite positions are
  * GPF_ERR_INVALID_ARGUMENT.  Synchronises.  Release with
  * gpf_photon_map_destroy. */

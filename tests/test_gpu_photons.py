@@ -268,6 +268,14 @@ def test_binned_gather_at_camera_hits_equals_the_plain_gather(ph):
     L2 = pm.gather(dx, dxs, 0.5, out=L1.clone(), accumulate=True, queries=qs)
     L3 = pm.gather(dx, dxs, 0.5, out=L0.clone(), accumulate=True)
     assert torch.equal(L2, L3)
+    # the same query set re-binned to every third point (another cell size)
+    say("  rebinned query set: every third point, cell 0.05")
+    dx3, dxs3 = dx[::3].contiguous(), dxs[::3].contiguous()
+    qs.rebin(dx3, 0.05)
+    L4 = pm.gather(dx3, dxs3, queries=qs)
+    L5 = pm.gather(dx3, dxs3)
+    torch.cuda.synchronize()
+    assert torch.equal(L4, L5) and torch.equal(L5, L0[::3])
 
 
 def test_density_full_size_sampled(ph):
