@@ -92,6 +92,8 @@ def main():
                     help="query used for the targets and both fits (the training data always "
                          "uses the truncated fits)")
     ap.add_argument("--save-weights", default=None)
+    ap.add_argument("--check-every", type=int, default=1,
+                    help="PSNR check cadence in steps (each check reads the step's loss back)")
     a = ap.parse_args()
     torch.cuda.set_device(0)
     t0 = time.perf_counter()
@@ -112,7 +114,7 @@ def main():
         if a.save_weights:
             LI.save(net, a.save_weights)
     res = compare(net, a.workload, views=a.views, res=a.res, target_psnr=a.target,
-                  max_steps=a.max_steps, query=a.query)
+                  max_steps=a.max_steps, check_every=a.check_every, query=a.query)
     res["training"] = train_info
     print(json.dumps(res))
 

@@ -121,7 +121,7 @@ def build_traced_dataset(seeds, n_paths, x, xs, T, fit_steps=200, r0=0.02, query
 
 def compare_traced(n_paths=100_000, train_maps=64, train_views=6, views=8, res=256, ref_iters=64,
                    fit_steps=200, epochs=20, max_steps=600, target=60.0, r0=0.02, query="hybrid",
-                   cell=0.025, eval_seed=1, train_res=None, log=log):
+                   cell=0.025, eval_seed=1, train_res=None, check_every=10, log=log):
     dev = "cuda"
     t0 = time.perf_counter()
     # training data: other photon maps fitted to the reference of another ring
@@ -148,7 +148,7 @@ def compare_traced(n_paths=100_000, train_maps=64, train_views=6, views=8, res=2
         t_init = time.perf_counter() - t1
         fitter = Fitter(f, qs, T, query=query)
         p0 = fitter.current_psnr()
-        r_ = fitter.run(max_steps, target, 10, log=lambda m: log(f"[{name}] {m}"))
+        r_ = fitter.run(max_steps, target, check_every, log=lambda m: log(f"[{name}] {m}"))
         h = r_["history"]
         levels = {}
         for lv in sorted(set(LEVELS + (target,))):
@@ -180,11 +180,14 @@ def main():
     ap.add_argument("--train-res", type=int, default=None)
     ap.add_argument("--fit-steps", type=int, default=200)
     ap.add_argument("--target", type=float, default=60.0)
+    ap.add_argument("--check-every", type=int, default=10,
+                    help="PSNR check cadence of --compare, in steps")
     a = ap.parse_args()
     if a.compare:
         out = compare_traced(a.paths, a.train_maps, a.train_views, views=a.views, res=a.res,
                              ref_iters=a.ref_iters, fit_steps=a.fit_steps, max_steps=a.steps,
-                             target=a.target, r0=a.r0, query=a.query, train_res=a.train_res)
+                             target=a.target, r0=a.r0, query=a.query, train_res=a.train_res,
+                             check_every=a.check_every)
     else:
         out = run(a.paths, a.ref_iters, a.ref_paths, a.views, a.res, a.steps, a.query, a.r0)
     print(json.dumps(out))
