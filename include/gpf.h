@@ -90,9 +90,12 @@ gpf_status gpf_bin_queries(const float *x, int64_t q, float cell_size, void *str
  * handle.  On failure the handle holds no binning (q = 0) until the next
  * successful rebin; it must still be destroyed.  Same limits on q and
  * cell_size as gpf_bin_queries; the current device must be the one `qs` was
- * created on.  Synchronises `stream`. */
+ * created on.  Synchronises `stream`; work queued on other streams that reads
+ * `qs` or a grid built on it must have finished before the call. */
 gpf_status gpf_rebin_queries(gpf_queries *qs, const float *x, int64_t q, float cell_size,
                              void *stream);
+/* Releases the query set.  Grids built on it keep a pointer to it: destroy
+ * them first (or at least never use them afterwards). */
 void gpf_queries_destroy(gpf_queries *qs);
 /* Host-side facts about a query set: number of points, of occupied cells and
  * of tiles, and the device bytes the handle holds. */
