@@ -328,3 +328,45 @@ def test_loss_and_adam_kernels(rad):
         rad.adam_step(pd, gd, md, vd, t, 5e-4)
         pr, m, v = O.adam_step(pr, g, m, v, t, 5e-4)
     np.testing.assert_allclose(pd.cpu().numpy(), pr, rtol=0, atol=1e-6)
+
+
+def test_device_byte_budget(rad):
+    """GPF_DEVICE_BYTES_LIMIT: an allocation over the budget is
+    GPF_ERR_OUT_OF_MEMORY; a forward whose survivor lists the budget refuses
+    keeps none (same bits), and the backward then culls (oracle-matched)."""
+    import os
+    from paper_2512_12459_amd._lib import GPFError
+    mu, q, ls, rgb, x = _grad_problem(23, 500, 3000, 0.2)
+    ref = O.radiance(mu, q, ls, rgb, x)
+    _, dL = O.mse_loss(ref["L"], np.random.default_rng(24).random((len(x), 3)).astype(np.float32))
+    dL = _mask_ambiguous(ref, dL).astype(np.float32)
+    gref = O.radiance_backward(mu, q, ls, rgb, x, dL)
+    dev = to_dev(mu, q, ls, rgb)
+    (xd,) = to_dev(x)
+    (dLd,) = to_dev(dL)
+    key = "GPF_DEVICE_BYTES_LIMIT"
+    try:
+        say("case: byte budget of 1 -> out of memory")
+        os.environ[key] = "1"
+        with pytest.raises(GPFError) as e:
+            rad.QuerySet(xd, 0.025)
+        assert e.value.status == 2
+        del os.environ[key]
+        qs = rad.QuerySet(xd, 0.025)
+        g = rad.Grid(qs).build(*dev)
+        rad.eval_radiance_backward(g, *dev, dLd)   # allocates the gradient rows
+        g.build(*dev)
+        say("case: survivor lists refused by the budget")
+        os.environ[key] = "1"
+        L = rad.eval_radiance(g, *dev)
+        grads = rad.eval_radiance_backward(g, *dev, dLd)
+        torch.cuda.synchronize()
+        del os.environ[key]
+        g_ref = rad.Grid(qs).build(*dev)
+        L_ref = rad.eval_radiance(g_ref, *dev)
+        torch.cuda.synchronize()
+        assert torch.equal(L, L_ref)
+        assert g.info()["device_bytes"] < g_ref.info()["device_bytes"]  # g keeps no lists
+        check_grads({k: v.cpu().numpy() for k, v in grads.items()}, gref)
+    finally:
+        os.environ.pop(key, None)
