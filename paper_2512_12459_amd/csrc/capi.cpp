@@ -189,7 +189,7 @@ void gpf_grid_destroy(gpf_grid* g) {
   if (!g) return;
   dev_free(g->rec, g->rec_cap * sizeof(PrimRec));
   dev_free(g->ext, g->rec_cap * sizeof(float4));
-  dev_free(g->prim_off, (2 * g->rec_cap + 3) * sizeof(int));
+  dev_free(g->prim_off, (size_t)g->prim_off_len * sizeof(int));
   dev_free(g->cell_start, g->cell_start_cap * sizeof(int));
   dev_free(g->keys, g->cap * sizeof(int));
   dev_free(g->vals, g->cap * sizeof(int));

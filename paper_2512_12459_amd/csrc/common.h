@@ -86,7 +86,8 @@ struct gpf_grid {
   gpf::PrimRec* rec = nullptr;  // [n]
   float4* ext = nullptr;        // [n] half-extents of the cutoff box; w = 1 if valid
   int64_t rec_cap = 0;
-  int* prim_off = nullptr;      // [n + 1] per-primitive entry counts, scanned in place
+  int* prim_off = nullptr;      // per-(primitive, sub-thread) entry counts and their scan
+  int64_t prim_off_len = 0;     // allocated entries of prim_off
   int* cell_start = nullptr;    // [ncells + 1]
   int64_t cell_start_cap = 0;   // allocated entries of cell_start
   uint64_t qs_gen = 0;          // query-set binning this grid was built on

@@ -18,6 +18,16 @@ struct Geom {
   int dx, dy, dz;
 };
 
+// Threads per primitive in the count and emit passes: a primitive's box spans
+// tens to hundreds of query cells, so one thread each leaves the launch
+// latency-bound when n is a few hundred thousand.  Eight up to 2^24
+// primitives, then fewer so that the per-thread counts stay under 2^27.
+int sub_threads(int64_t n) {
+  int S = 8;
+  while (S > 1 && n * S > ((int64_t)1 << 27) && n > ((int64_t)1 << 24)) S >>= 1;
+  return S;
+}
+
 // Frame of primitive i in FP64 (Sec. 4.1): qhat = q/|q|, R(qhat) with the local
 // axes as columns, s = exp(log_scale), W = diag(1/s) R^T.  Writes the FP32
 // record and returns the half-extents of the cutoff ellipsoid's box; returns
@@ -102,14 +112,16 @@ __device__ __forceinline__ bool ball_may_touch(const PrimRec& r, float bx, float
 
 // Visits the occupied cells of the primitive's cutoff box (or, with ball > 0,
 // of the box of its ball) that pass the whitened-frame (or ball) test; counts
-// them, or (kEmit) writes (cell slot, primitive)
-// entries from `base` on.  Both passes read the same stored record and
-// extents, so they make identical decisions.
+// them, or (kEmit) writes (cell slot, primitive) entries from `base` on.  The
+// box's cells are taken in (z, y, x) order by linear index, and sub-thread
+// `sub` of S takes indices sub, sub + S, ...; count and emit read the
+// same stored record and extents with the same split, so they make identical
+// decisions.
 template <bool kEmit>
 __device__ __forceinline__ int visit_cells(const PrimRec& r, const float ext[3], const Geom& g,
                                            const uint32_t* __restrict__ bits,
                                            const int* __restrict__ occ_of_dense, float c2,
-                                           float ball, int pid, int* __restrict__ keys,
+                                           float ball, int pid, int sub, int S, int* __restrict__ keys,
                                            int* __restrict__ vals, int base, int limit) {
   const float inv = 1.f / g.h;
   const float m[3] = {r.r0.x, r.r0.y, r.r0.z};
@@ -124,19 +136,19 @@ __device__ __forceinline__ int visit_cells(const PrimRec& r, const float ext[3],
     lo[a] = max(0, (int)floorf(a0 - 1e-3f));
     hi[a] = min(d[a] - 1, (int)floorf(a1 + 1e-3f));
   }
+  const int nx = hi[0] - lo[0] + 1, ny = hi[1] - lo[1] + 1;
+  // first index of this sub-thread, then steps of S along x with carries
+  int cx = lo[0] + sub % nx, cy = lo[1] + (sub / nx) % ny, cz = lo[2] + sub / (nx * ny);
   const float hh = 0.5f * g.h;
   int cnt = 0;
-  for (int cz = lo[2]; cz <= hi[2]; ++cz)
-    for (int cy = lo[1]; cy <= hi[1]; ++cy) {
-      const int row = (cz * g.dy + cy) * g.dx;
-      for (int cx = lo[0]; cx <= hi[0]; ++cx) {
-        const int dc = row + cx;
-        if (!((bits[dc >> 5] >> (dc & 31)) & 1u)) continue;
-        const float bx = o[0] + (cx + 0.5f) * g.h, by = o[1] + (cy + 0.5f) * g.h,
-                    bz = o[2] + (cz + 0.5f) * g.h;
-        if (ball > 0.f ? !ball_may_touch(r, bx, by, bz, hh, ball)
-                       : !box_may_touch(r, bx, by, bz, hh, c2))
-          continue;
+  while (cz <= hi[2]) {
+    const int dc = (cz * g.dy + cy) * g.dx + cx;
+    if ((bits[dc >> 5] >> (dc & 31)) & 1u) {
+      const float bx = o[0] + (cx + 0.5f) * g.h, by = o[1] + (cy + 0.5f) * g.h,
+                  bz = o[2] + (cz + 0.5f) * g.h;
+      const bool touch = ball > 0.f ? ball_may_touch(r, bx, by, bz, hh, ball)
+                                    : box_may_touch(r, bx, by, bz, hh, c2);
+      if (touch) {
         if (kEmit && cnt < limit) {
           keys[base + cnt] = occ_of_dense[dc];
           vals[base + cnt] = pid;
@@ -144,17 +156,24 @@ __device__ __forceinline__ int visit_cells(const PrimRec& r, const float ext[3],
         ++cnt;
       }
     }
+    cx += S;
+    while (cx > hi[0]) {
+      cx -= nx;
+      if (++cy > hi[1]) {
+        cy = lo[1];
+        ++cz;
+      }
+    }
+  }
   return cnt;
 }
 
-// Pass 1: frame of every primitive (FP64 -> FP32 record, cutoff box) and the
-// number of cells it registers in; `bad` counts degenerate primitives.
-__global__ void __launch_bounds__(256) count_kernel(
+// Pass 1: frame of every primitive (FP64 -> FP32 record, cutoff box);
+// `bad` counts degenerate primitives.
+__global__ void __launch_bounds__(256) frame_kernel(
     const float* __restrict__ mu, const float* __restrict__ quat, const float* __restrict__ ls,
-    const float* __restrict__ rgb, int n, float cutoff, float ball, Geom g,
-    const uint32_t* __restrict__ bits,
-    const int* __restrict__ occ_of_dense, PrimRec* __restrict__ recs, float4* __restrict__ exts,
-    int* __restrict__ prim_cnt, int* __restrict__ bad) {
+    const float* __restrict__ rgb, int n, float cutoff, float ball, PrimRec* __restrict__ recs,
+    float4* __restrict__ exts, int* __restrict__ bad) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   PrimRec r;
@@ -163,34 +182,50 @@ __global__ void __launch_bounds__(256) count_kernel(
   if (ball > 0.f) ext[0] = ext[1] = ext[2] = ball * (1.f + 1e-5f);
   recs[i] = r;
   exts[i] = make_float4(ext[0], ext[1], ext[2], ok ? 1.f : 0.f);
-  if (!ok) {
-    prim_cnt[i] = 0;
-    atomicAdd(bad, 1);
-    return;
-  }
-  const float c2 = (float)(kKappa2 * cutoff * cutoff);
-  prim_cnt[i] =
-      visit_cells<false>(r, ext, g, bits, occ_of_dense, c2, ball, i, nullptr, nullptr, 0, 0);
+  if (!ok) atomicAdd(bad, 1);
 }
 
-// Pass 2: entries in primitive-major order at the scanned offsets.
-__global__ void __launch_bounds__(256) emit_kernel(int n, float cutoff, float ball, Geom g,
+// Pass 2: per (primitive, sub-thread) the number of cells it registers in.
+__global__ void __launch_bounds__(256) count_kernel(int n, int S, float cutoff, float ball, Geom g,
+                                                    const uint32_t* __restrict__ bits,
+                                                    const int* __restrict__ occ_of_dense,
+                                                    const PrimRec* __restrict__ recs,
+                                                    const float4* __restrict__ exts,
+                                                    int* __restrict__ cnt) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= (int64_t)n * S) return;
+  const int i = (int)(t / S), sub = (int)(t % S);
+  const float4 e = exts[i];
+  if (e.w == 0.f) {
+    cnt[t] = 0;
+    return;
+  }
+  const float ext[3] = {e.x, e.y, e.z};
+  const float c2 = (float)(kKappa2 * cutoff * cutoff);
+  cnt[t] = visit_cells<false>(recs[i], ext, g, bits, occ_of_dense, c2, ball, i, sub, S,
+                              nullptr, nullptr, 0, 0);
+}
+
+// Pass 3: entries at the scanned offsets, primitive-major (and sub-thread
+// order within a primitive).
+__global__ void __launch_bounds__(256) emit_kernel(int n, int S, float cutoff, float ball, Geom g,
                                                    const uint32_t* __restrict__ bits,
                                                    const int* __restrict__ occ_of_dense,
                                                    const PrimRec* __restrict__ recs,
                                                    const float4* __restrict__ exts,
-                                                   const int* __restrict__ prim_off,
+                                                   const int* __restrict__ off,
                                                    int* __restrict__ keys, int* __restrict__ vals) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= (int64_t)n * S) return;
+  const int i = (int)(t / S), sub = (int)(t % S);
   const float4 e = exts[i];
   if (e.w == 0.f) return;
   const float ext[3] = {e.x, e.y, e.z};
   const float c2 = (float)(kKappa2 * cutoff * cutoff);
-  const int base = prim_off[i];
-  // never write past this primitive's range, whatever the visit decides
-  visit_cells<true>(recs[i], ext, g, bits, occ_of_dense, c2, ball, i, keys, vals, base,
-                    prim_off[i + 1] - base);
+  const int base = off[t];
+  // never write past this sub-thread's range, whatever the visit decides
+  visit_cells<true>(recs[i], ext, g, bits, occ_of_dense, c2, ball, i, sub, S, keys, vals, base,
+                    off[t + 1] - base);
 }
 
 // cell_start[c] = first sorted entry with key >= c (binary search).
@@ -214,26 +249,31 @@ gpf_status launch_build_grid(gpf_grid* g, hipStream_t s) {
   const gpf_queries* qs = g->qs;
   const int n = (int)g->n;
   const int nc = (int)qs->ncells;
+  const int S = sub_threads(n);
+  const int64_t m = (int64_t)n * S;  // (primitive, sub-thread) pairs
   if (g->rec_cap < n) {
     dev_free(g->rec, g->rec_cap * sizeof(PrimRec));
     dev_free(g->ext, g->rec_cap * sizeof(float4));
-    dev_free(g->prim_off, (2 * g->rec_cap + 3) * sizeof(int));
     g->rec = nullptr;
     g->ext = nullptr;
-    g->prim_off = nullptr;
     g->rec_cap = 0;
     gpf_status st;
     if ((st = dev_alloc((void**)&g->rec, (size_t)n * sizeof(PrimRec), "grid records")) != GPF_OK ||
-        (st = dev_alloc((void**)&g->ext, (size_t)n * sizeof(float4), "grid extents")) != GPF_OK ||
-        (st = dev_alloc((void**)&g->prim_off, (size_t)(2 * n + 3) * sizeof(int), "grid counts")) !=
-            GPF_OK) {
+        (st = dev_alloc((void**)&g->ext, (size_t)n * sizeof(float4), "grid extents")) != GPF_OK) {
       dev_free(g->rec, (size_t)n * sizeof(PrimRec));
-      dev_free(g->ext, (size_t)n * sizeof(float4));
       g->rec = nullptr;
-      g->ext = nullptr;
       return st;
     }
     g->rec_cap = n;
+  }
+  if (g->prim_off_len < 2 * m + 3) {
+    dev_free(g->prim_off, (size_t)g->prim_off_len * sizeof(int));
+    g->prim_off = nullptr;
+    g->prim_off_len = 0;
+    gpf_status st =
+        dev_alloc((void**)&g->prim_off, (size_t)(2 * m + 3) * sizeof(int), "grid counts");
+    if (st != GPF_OK) return st;
+    g->prim_off_len = 2 * m + 3;
   }
   if (g->cell_start_cap < nc + 1) {  // the query set may have been re-binned into more cells
     dev_free(g->cell_start, g->cell_start_cap * sizeof(int));
@@ -246,16 +286,18 @@ gpf_status launch_build_grid(gpf_grid* g, hipStream_t s) {
   Geom geo{qs->origin[0], qs->origin[1], qs->origin[2], qs->cell, qs->dims[0], qs->dims[1],
            qs->dims[2]};
   const int nb = (n + 255) / 256;
-  // counts: prim_off[0 .. n] (entry n stays 0), degenerate counter at n + 1;
-  // offsets: prim_off[n + 2 .. 2n + 2]
+  const unsigned mb = (unsigned)((m + 255) / 256);
+  // counts: prim_off[0 .. m] (entry m stays 0), degenerate counter at m + 1;
+  // offsets: prim_off[m + 2 .. 2m + 2]
   int* cnt = g->prim_off;
-  int* off = g->prim_off + n + 2;
-  GPF_HIP(hipMemsetAsync(cnt + n, 0, 2 * sizeof(int), s));
-  hipLaunchKernelGGL(count_kernel, dim3(nb), dim3(256), 0, s, g->mu, g->quat, g->log_scale, g->rgb,
-                     n, g->cutoff, g->ball, geo, qs->occ_bits, qs->occ_of_dense, g->rec, g->ext, cnt,
-                     cnt + n + 1);
+  int* off = g->prim_off + m + 2;
+  GPF_HIP(hipMemsetAsync(cnt + m, 0, 2 * sizeof(int), s));
+  hipLaunchKernelGGL(frame_kernel, dim3(nb), dim3(256), 0, s, g->mu, g->quat, g->log_scale, g->rgb,
+                     n, g->cutoff, g->ball, g->rec, g->ext, cnt + m + 1);
+  hipLaunchKernelGGL(count_kernel, dim3(mb), dim3(256), 0, s, n, S, g->cutoff, g->ball, geo,
+                     qs->occ_bits, qs->occ_of_dense, g->rec, g->ext, cnt);
   size_t scan_bytes = 0;
-  GPF_HIP(rocprim::exclusive_scan(nullptr, scan_bytes, cnt, off, 0, (size_t)(n + 1),
+  GPF_HIP(rocprim::exclusive_scan(nullptr, scan_bytes, cnt, off, 0, (size_t)(m + 1),
                                   rocprim::plus<int>(), s));
   if (g->sort_tmp_bytes < scan_bytes) {
     dev_free(g->sort_tmp, g->sort_tmp_bytes);
@@ -267,10 +309,10 @@ gpf_status launch_build_grid(gpf_grid* g, hipStream_t s) {
   }
   int host[2] = {0, 0};
   size_t tb = g->sort_tmp_bytes;
-  GPF_HIP(rocprim::exclusive_scan(g->sort_tmp, tb, cnt, off, 0, (size_t)(n + 1),
+  GPF_HIP(rocprim::exclusive_scan(g->sort_tmp, tb, cnt, off, 0, (size_t)(m + 1),
                                   rocprim::plus<int>(), s));
-  GPF_HIP(hipMemcpyAsync(&host[1], cnt + n + 1, sizeof(int), hipMemcpyDeviceToHost, s));
-  GPF_HIP(hipMemcpyAsync(&host[0], off + n, sizeof(int), hipMemcpyDeviceToHost, s));
+  GPF_HIP(hipMemcpyAsync(&host[1], cnt + m + 1, sizeof(int), hipMemcpyDeviceToHost, s));
+  GPF_HIP(hipMemcpyAsync(&host[0], off + m, sizeof(int), hipMemcpyDeviceToHost, s));
   GPF_HIP(hipStreamSynchronize(s));
   if (host[1] > 0)
     return set_error(GPF_ERR_INVALID_ARGUMENT,
@@ -292,8 +334,8 @@ gpf_status launch_build_grid(gpf_grid* g, hipStream_t s) {
     g->cap = want;
   }
   g->entries = E;
-  hipLaunchKernelGGL(emit_kernel, dim3(nb), dim3(256), 0, s, n, g->cutoff, g->ball, geo, qs->occ_bits,
-                     qs->occ_of_dense, g->rec, g->ext, off, g->keys, g->vals);
+  hipLaunchKernelGGL(emit_kernel, dim3(mb), dim3(256), 0, s, n, S, g->cutoff, g->ball, geo,
+                     qs->occ_bits, qs->occ_of_dense, g->rec, g->ext, off, g->keys, g->vals);
   // stable sort by cell slot: each cell's primitives end up in ascending order
   int bits_needed = 1;
   while ((1 << bits_needed) <= nc) ++bits_needed;
@@ -314,8 +356,8 @@ gpf_status launch_build_grid(gpf_grid* g, hipStream_t s) {
   hipLaunchKernelGGL(cell_start_kernel, dim3((nc + 256) / 256), dim3(256), 0, s, g->keys_sorted,
                      (int)E, nc, g->cell_start);
   GPF_HIP(hipGetLastError());
-  g->bytes = g->rec_cap * (sizeof(PrimRec) + sizeof(float4) + 2 * sizeof(int)) +
-             (size_t)(nc + 1) * sizeof(int) + 4 * g->cap * sizeof(int) + g->sort_tmp_bytes;
+  g->bytes = g->rec_cap * (sizeof(PrimRec) + sizeof(float4)) + g->prim_off_len * sizeof(int) +
+             (size_t)g->cell_start_cap * sizeof(int) + 4 * g->cap * sizeof(int) + g->sort_tmp_bytes;
   if (g->ball > 0.f) {
     gpf_status st = build_centre_grid(g, s);
     if (st != GPF_OK) return st;
