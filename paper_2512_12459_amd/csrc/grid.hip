@@ -18,12 +18,18 @@ struct Geom {
   int dx, dy, dz;
 };
 
-// Threads per primitive in the count and emit passes: a primitive's box spans
+// Threads per primitive in the count and emit passes: a cutoff box spans
 // tens to hundreds of query cells, so one thread each leaves the launch
-// latency-bound when n is a few hundred thousand.  Eight up to 2^24
-// primitives, then fewer so that the per-thread counts stay under 2^27.
-int sub_threads(int64_t n) {
+// latency-bound when n is a few hundred thousand.  Eight for cutoff boxes; for
+// the hybrid query's ball boxes (whose cell span is known) about 16 cells per
+// thread; fewer beyond 2^24 primitives so that the counts stay under 2^27.
+int sub_threads(int64_t n, float ball, float cell) {
   int S = 8;
+  if (ball > 0.f) {
+    const double span = 2.0 * ball / cell + 2.0;  // cells per axis, at most
+    S = 1;
+    while (S < 8 && span * span * span >= 32.0 * S) S <<= 1;
+  }
   while (S > 1 && n * S > ((int64_t)1 << 27) && n > ((int64_t)1 << 24)) S >>= 1;
   return S;
 }
@@ -249,7 +255,7 @@ gpf_status launch_build_grid(gpf_grid* g, hipStream_t s) {
   const gpf_queries* qs = g->qs;
   const int n = (int)g->n;
   const int nc = (int)qs->ncells;
-  const int S = sub_threads(n);
+  const int S = sub_threads(n, g->ball, qs->cell);
   const int64_t m = (int64_t)n * S;  // (primitive, sub-thread) pairs
   if (g->rec_cap < n) {
     dev_free(g->rec, g->rec_cap * sizeof(PrimRec));
