@@ -57,8 +57,11 @@ constexpr int kFwdSurvCap = 256;   // staged survivors per wave
 // {index | tile mask << 30, b'} with b' = W' (mu - centre), centre = the group
 // box centre.  Every lane then evaluates each survivor for the tiles it may
 // touch (a wave-uniform branch per tile), reading W' and the flux with
-// wave-uniform scalar loads: u' = W' (x - centre) - b'.
-__global__ void __launch_bounds__(kWaves * 64) eval_fwd_kernel(
+// wave-uniform scalar loads: u' = W' (x - centre) - b'.  The survivor loop is
+// bound by the latency of its scalar loads, so the kernel is held to 64 VGPRs
+// (8 waves per SIMD instead of 7).
+__global__ void __launch_bounds__(kWaves * 64) __attribute__((amdgpu_waves_per_eu(8, 8)))
+eval_fwd_kernel(
     const float4* __restrict__ xs, const int* __restrict__ perm,
     const GroupInfo* __restrict__ groups, const float4* __restrict__ glo,
     const float4* __restrict__ ghi, int ngroups, const float4* __restrict__ tlo,
