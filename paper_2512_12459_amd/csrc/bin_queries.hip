@@ -158,13 +158,17 @@ __global__ void occ_table_kernel(const int* __restrict__ occ_dense, int ncells, 
   atomicOr(occ_bits + (d >> 5), 1u << (d & 31));
 }
 
+// Tiles of kTile points and groups of kGroupTiles tiles per occupied cell,
+// both from the cell's point count (so both scans run before one read-back).
 __global__ void tiles_per_cell_kernel(const int* __restrict__ cell_first, int ncells, int q,
-                                      int* ntile) {
+                                      int* ntile, int* ngroup) {
   int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= ncells) return;
   int end = (s + 1 < ncells) ? cell_first[s + 1] : q;
   int cnt = end - cell_first[s];
-  ntile[s] = (cnt + kTile - 1) / kTile;
+  const int nt = (cnt + kTile - 1) / kTile;
+  ntile[s] = nt;
+  ngroup[s] = (nt + kGroupTiles - 1) / kGroupTiles;
 }
 
 // Largest s in [0, n) with off[s] <= i, for strictly increasing offsets
@@ -217,13 +221,6 @@ __global__ void __launch_bounds__(256) tile_box_kernel(const float4* __restrict_
     lo[t] = make_float4(l[0], l[1], l[2], 0.f);
     hi[t] = make_float4(h[0], h[1], h[2], 0.f);
   }
-}
-
-__global__ void groups_per_cell_kernel(const int* __restrict__ toff, int ncells, int* ngroup) {
-  int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= ncells) return;
-  int nt = toff[s + 1] - toff[s];
-  ngroup[s] = (nt + kGroupTiles - 1) / kGroupTiles;
 }
 
 // One thread per group: group g - goff[s] of cell s takes the next
@@ -409,13 +406,20 @@ gpf_status launch_bin_queries(const float* x, int64_t q, float cell, bool keep_s
   hipLaunchKernelGGL(occ_table_kernel, dim3(cb), dim3(256), 0, s, out->occ_dense, ncells,
                      out->occ_of_dense, out->occ_bits);
   TRY(grow(out->ntile, out->ntile_cap, (int64_t)(ncells + 1) * 4, "ntile"));
+  TRY(grow(out->cell_first_g, out->cell_first_g_cap, (int64_t)(ncells + 1) * 4, "group offsets"));
   hipLaunchKernelGGL(tiles_per_cell_kernel, dim3(cb), dim3(256), 0, s, out->cell_first, ncells,
-                     (int)q, out->ntile);
+                     (int)q, out->ntile, out->cell_first_g);
   hipLaunchKernelGGL(scan_exclusive_kernel, dim3(1), dim3(kScanThreads), 0, s, out->ntile,
                      out->ntile, ncells);
-  int ntiles = 0;
-  TRYH(hipMemcpyAsync(&ntiles, out->ntile + ncells, 4, hipMemcpyDeviceToHost, s), "ntiles readback");
-  TRYH(hipStreamSynchronize(s), "ntiles sync");
+  hipLaunchKernelGGL(scan_exclusive_kernel, dim3(1), dim3(kScanThreads), 0, s, out->cell_first_g,
+                     out->cell_first_g, ncells);
+  int counts[2] = {0, 0};  // tiles, groups
+  TRYH(hipMemcpyAsync(&counts[0], out->ntile + ncells, 4, hipMemcpyDeviceToHost, s),
+       "ntiles readback");
+  TRYH(hipMemcpyAsync(&counts[1], out->cell_first_g + ncells, 4, hipMemcpyDeviceToHost, s),
+       "ngroups readback");
+  TRYH(hipStreamSynchronize(s), "tile and group counts sync");
+  const int ntiles = counts[0], ngroups = counts[1];
   TRY(grow(out->tiles, out->tiles_cap, (int64_t)ntiles * sizeof(TileInfo), "tiles"));
   TRY(grow(out->tile_lo, out->tile_lo_cap, (int64_t)ntiles * sizeof(float4), "tile_lo"));
   TRY(grow(out->tile_hi, out->tile_hi_cap, (int64_t)ntiles * sizeof(float4), "tile_hi"));
@@ -424,15 +428,6 @@ gpf_status launch_bin_queries(const float* x, int64_t q, float cell, bool keep_s
   hipLaunchKernelGGL(tile_box_kernel, dim3((ntiles + 3) / 4), dim3(256), 0, s, out->xs, out->tiles,
                      ntiles, out->tile_lo, out->tile_hi);
   // groups of consecutive tiles per cell (ntile[] now holds the tile offsets)
-  TRY(grow(out->cell_first_g, out->cell_first_g_cap, (q + 1) * 4, "group offsets"));
-  hipLaunchKernelGGL(groups_per_cell_kernel, dim3(cb), dim3(256), 0, s, out->ntile, ncells,
-                     out->cell_first_g);
-  hipLaunchKernelGGL(scan_exclusive_kernel, dim3(1), dim3(kScanThreads), 0, s, out->cell_first_g,
-                     out->cell_first_g, ncells);
-  int ngroups = 0;
-  TRYH(hipMemcpyAsync(&ngroups, out->cell_first_g + ncells, 4, hipMemcpyDeviceToHost, s),
-       "ngroups readback");
-  TRYH(hipStreamSynchronize(s), "ngroups sync");
   TRY(grow(out->groups, out->groups_cap, (int64_t)ngroups * sizeof(GroupInfo), "groups"));
   TRY(grow(out->group_lo, out->group_lo_cap, (int64_t)ngroups * sizeof(float4), "group_lo"));
   TRY(grow(out->group_hi, out->group_hi_cap, (int64_t)ngroups * sizeof(float4), "group_hi"));
