@@ -370,3 +370,51 @@ def test_device_byte_budget(rad):
         check_grads({k: v.cpu().numpy() for k, v in grads.items()}, gref)
     finally:
         os.environ.pop(key, None)
+
+
+def test_registration_box_sizes(rad):
+    """Grid registration splits each Gaussian's box over several threads:
+    boxes of fewer cells than threads, boxes spanning the whole query grid,
+    boxes hanging over its edge and boxes entirely outside it, in one field;
+    pair count, forward and backward against the oracle."""
+    rng = np.random.default_rng(41)
+    x = rng.random((2500, 3)) * 0.3 + 0.1
+    x[:, 2] = np.round(x[:, 2] * 10) / 10          # points on a few planes
+    parts = []
+    for n, centre, spread, scale in ((300, 0.25, 0.15, 0.002),    # inside one cell
+                                     (6, 0.25, 0.05, 0.15),       # over the whole grid
+                                     (60, 0.05, 0.03, 0.02),      # over the low edge
+                                     (40, 0.45, 0.03, 0.02),      # over the high edge
+                                     (20, 2.0, 0.1, 0.01)):       # far outside
+        mu = centre + rng.normal(0, spread, (n, 3))
+        q = rng.normal(size=(n, 4))
+        ls = np.log(scale) + rng.normal(0, 0.2, (n, 3))
+        rgb = np.exp(rng.normal(0, 1, (n, 3)))
+        parts.append((mu, q, ls, rgb))
+    mu, q, ls, rgb = (np.concatenate([p[k] for p in parts]) for k in range(4))
+    mu, q, ls, rgb, x = (a.astype(np.float32) for a in (mu, q, ls, rgb, x))
+    ref = O.radiance(mu, q, ls, rgb, x)
+    assert ref["count"].max() > 5
+    say("case: registration of boxes from within one cell to beyond the grid")
+    L, g, dev, qs = _eval(rad, (mu, q, ls, rgb), x, cell=0.025)
+    check_forward(L, ref)
+    n = g.count_pairs()
+    assert int(np.sum(ref["count"]) - np.sum(ref["n_amb"])) <= n <= \
+        int(np.sum(ref["count"]) + np.sum(ref["n_amb"]))
+    T = np.random.default_rng(42).random((len(x), 3)).astype(np.float32)
+    _, dL = O.mse_loss(ref["L"], T)
+    dL = _mask_ambiguous(ref, dL).astype(np.float32)
+    gref = O.radiance_backward(mu, q, ls, rgb, x, dL)
+    (dLd,) = to_dev(dL)
+    grads = rad.eval_radiance_backward(g, *dev, dLd)
+    torch.cuda.synchronize()
+    check_grads({k: v.cpu().numpy() for k, v in grads.items()}, gref)
+    # the hybrid query's ball boxes (two threads per Gaussian at these sizes)
+    from oracle import hybrid_oracle as H
+    from oracle.tolerances import check_hybrid_forward
+    say("case: the same field through the hybrid query")
+    href = H.radiance(mu, q, ls, rgb, x, 0.02, 3, 1e-6)
+    hg = rad.HybridGrid(qs).build(*dev)
+    Lh, Z, cnt = rad.eval_hybrid(hg, *dev)
+    torch.cuda.synchronize()
+    check_hybrid_forward(Lh.cpu().numpy(), Z.cpu().numpy(), cnt.cpu().numpy(), href)
