@@ -109,7 +109,10 @@ gpf_status gpf_queries_info(const gpf_queries *qs, int64_t *q, int64_t *cells, i
  * primitive in every occupied cell of `qs` whose box its `cutoff`-sigma
  * ellipsoid may touch (a conservative separating-axis test in the whitened
  * frame).  The grid keeps FP32 records {mu, W, Phi} of the field as it is now:
- * rebuild after any parameter change.  `cutoff` in (0, 16].  If *grid is
+ * rebuild after any parameter change.  `cutoff` in (0, 16]; a zero-norm
+ * quaternion or a non-finite position, quaternion, log-scale or flux is
+ * GPF_ERR_INVALID_ARGUMENT (found on the device, reported after the one
+ * synchronisation).  If *grid is
  * non-NULL it must come from an earlier call with the same `qs` and is
  * rebuilt in place (its buffers grow as needed); otherwise a new handle is
  * returned.  Synchronises `stream` once (reads back the number of

@@ -37,7 +37,8 @@ int sub_threads(int64_t n, float ball, float cell) {
 // Frame of primitive i in FP64 (Sec. 4.1): qhat = q/|q|, R(qhat) with the local
 // axes as columns, s = exp(log_scale), W = diag(1/s) R^T.  Writes the FP32
 // record and returns the half-extents of the cutoff ellipsoid's box; returns
-// false for a degenerate primitive (zero or non-finite quaternion/scale).
+// false for a degenerate primitive (zero or non-finite quaternion, non-finite
+// scale, position or flux).
 __device__ bool prim_frame(const float* __restrict__ mu, const float* __restrict__ quat,
                            const float* __restrict__ ls, const float* __restrict__ rgb, int i,
                            float cutoff, PrimRec* rec, float ext[3]) {
@@ -46,6 +47,8 @@ __device__ bool prim_frame(const float* __restrict__ mu, const float* __restrict
   double s[3] = {exp((double)ls[i * 3]), exp((double)ls[i * 3 + 1]), exp((double)ls[i * 3 + 2])};
   bool ok = nrm > 0.0 && isfinite(nrm) && isfinite(s[0]) && isfinite(s[1]) && isfinite(s[2]) &&
             s[0] > 0.0 && s[1] > 0.0 && s[2] > 0.0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) ok = ok && isfinite(mu[i * 3 + a]) && isfinite(rgb[i * 3 + a]);
   if (!ok) {
     PrimRec z;
     z.r0 = make_float4(mu[i * 3], mu[i * 3 + 1], mu[i * 3 + 2], 0.f);
@@ -141,6 +144,9 @@ __device__ __forceinline__ int visit_cells(const PrimRec& r, const float ext[3],
     if (a1 < -1e-3f || a0 > (float)d[a] + 1e-3f) return 0;  // box misses the grid
     lo[a] = max(0, (int)floorf(a0 - 1e-3f));
     hi[a] = min(d[a] - 1, (int)floorf(a1 + 1e-3f));
+    // clamping can leave an empty range (a box starting on the grid's far
+    // face); the stepping below needs at least one cell per axis
+    if (!(lo[a] <= hi[a])) return 0;
   }
   const int nx = hi[0] - lo[0] + 1, ny = hi[1] - lo[1] + 1;
   // first index of this sub-thread, then steps of S along x with carries

@@ -146,6 +146,15 @@ def test_errors_are_reported(rad):
     qs2.close()
     q2 = q.clone()
     q2[:, 0] = 1.0
+    say("case: non-finite position or flux -> invalid argument")
+    for arr, idx in ((mu, (2, 1)), (rgb, (3, 0))):
+        for bad in (float("nan"), float("inf")):
+            a2 = arr.clone()
+            a2[idx] = bad
+            args = (a2, q2, ls, rgb) if arr is mu else (mu, q2, ls, a2)
+            with pytest.raises(GPFError) as e:
+                rad.Grid(qs).build(*args)
+            assert e.value.status == 1
     g = rad.Grid(qs).build(mu, q2, ls, rgb)
     other = rgb.clone()
     with pytest.raises(GPFError) as e:
