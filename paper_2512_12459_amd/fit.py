@@ -127,7 +127,11 @@ class Fitter:
         for i in range(1, max_steps + 1):
             self.step()
             if i % check_every == 0 or i == max_steps:
-                p = psnr_from_mse(self.mse(), self.peak)
+                mse = self.mse()
+                if not math.isfinite(mse):
+                    raise FloatingPointError(f"non-finite loss at step {self.t}; "
+                                             "restore the last checkpoint (Fitter.load)")
+                p = psnr_from_mse(mse, self.peak)
                 el = time.perf_counter() - t0
                 hist.append((i, p, el))
                 if log and (i % log_every == 0 or i == max_steps):
@@ -137,3 +141,33 @@ class Fitter:
                     break
         torch.cuda.synchronize()
         return dict(history=hist, reached=reached, seconds=time.perf_counter() - t0)
+
+    # ---- checkpoint / resume ------------------------------------------------
+    # The parameters, both Adam moments, the step count and the learning rates
+    # go into one .npz (plain arrays, nothing pickled); the grid is derived
+    # and rebuilt by the next step.
+
+    def save(self, path: str):
+        f = self.f
+        torch.cuda.synchronize()
+        np.savez(path, n=np.int64(f.n), step=np.int64(self.t),
+                 query=np.array("hybrid" if self.hybrid else "truncated"),
+                 lr_keys=np.array([k for k, _ in Field.GROUPS]),
+                 lr_vals=np.array([self.lr[k] for k, _ in Field.GROUPS], np.float64),
+                 P=f.P.cpu().numpy(), M=f.M.cpu().numpy(), V=f.V.cpu().numpy())
+
+    def load(self, path: str):
+        """Restores a checkpoint written by save() for a field of the same size
+        and the same query mode."""
+        with np.load(path, allow_pickle=False) as z:
+            f = self.f
+            if int(z["n"]) != f.n:
+                raise ValueError(f"checkpoint holds {int(z['n'])} Gaussians, the field {f.n}")
+            if str(z["query"]) != ("hybrid" if self.hybrid else "truncated"):
+                raise ValueError(f"checkpoint was written with the {z['query']} query")
+            for buf, key in ((f.P, "P"), (f.M, "M"), (f.V, "V")):
+                buf.copy_(torch.from_numpy(z[key]).to(buf.device))
+            f.G.zero_()
+            self.t = int(z["step"])
+            self.lr = {str(k): float(v) for k, v in zip(z["lr_keys"], z["lr_vals"])}
+        return self

@@ -427,3 +427,39 @@ def test_registration_box_sizes(rad):
     Lh, Z, cnt = rad.eval_hybrid(hg, *dev)
     torch.cuda.synchronize()
     check_hybrid_forward(Lh.cpu().numpy(), Z.cpu().numpy(), cnt.cpu().numpy(), href)
+
+
+def test_fit_checkpoint_resume(rad, tmp_path):
+    """Fitter.save / Fitter.load: a fit resumed from a checkpoint taken after
+    10 steps follows the uninterrupted fit (same losses per step up to the
+    backward's atomic summation order); a checkpoint of another size or
+    query mode is refused; a non-finite loss stops the run."""
+    from paper_2512_12459_amd.fit import Field, Fitter
+    gt, x = S.workload("plain4k")
+    start = S.perturb_field(gt, 2)
+    (xd,) = to_dev(x)
+    qs = rad.QuerySet(xd, 0.025)
+    gdev = to_dev(*gt.arrays())
+    T = rad.eval_radiance(rad.Grid(qs).build(*gdev), *gdev)
+    say("case: fit 10 steps, checkpoint, 10 more; resume from the checkpoint")
+    a = Fitter(Field(*start.arrays()), qs, T)
+    a.run(10, check_every=10)
+    ck = str(tmp_path / "fit.npz")
+    a.save(ck)
+    ha = a.run(10, check_every=1)["history"]
+    b = Fitter(Field(*start.arrays()), qs, T).load(ck)
+    assert b.t == 10
+    hb = b.run(10, check_every=1)["history"]
+    for (sa, pa, _), (sb, pb, _) in zip(ha, hb):
+        assert sa == sb and abs(pa - pb) < 1e-3, (sa, pa, pb)
+    for k in a.f.p:
+        assert torch.allclose(a.f.p[k], b.f.p[k], rtol=1e-4, atol=1e-6), k
+    small = Field(*[v[:100] for v in start.arrays()])
+    with pytest.raises(ValueError):
+        Fitter(small, qs, T).load(ck)
+    with pytest.raises(ValueError):
+        Fitter(Field(*start.arrays()), qs, T, query="hybrid").load(ck)
+    Tn = T.clone()
+    Tn[7, 1] = float("nan")
+    with pytest.raises(FloatingPointError):
+        Fitter(Field(*start.arrays()), qs, Tn).run(3, check_every=1)
