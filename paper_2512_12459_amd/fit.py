@@ -7,6 +7,7 @@ updates each parameter group with Adam.  All of it runs in libgpf.so.
 """
 from __future__ import annotations
 
+import json
 import math
 import time
 
@@ -115,30 +116,41 @@ class Fitter:
         return psnr_from_mse(self.mse(), self.peak)
 
     def run(self, max_steps: int, target_psnr: float | None = None, check_every: int = 10,
-            log=None, log_every: int = 100):
+            log=None, log_every: int = 100, jsonl: str | None = None):
         """Runs until ``target_psnr`` (checked every ``check_every`` steps, on
         the loss of the step's forward pass) or ``max_steps``.  Returns a dict
         with the PSNR history [(step, psnr, seconds)] and the step reaching the
-        target (None if never)."""
+        target (None if never).  With ``jsonl``, appends one JSON object per
+        check to that file: step (the optimiser's count), mse, psnr, wall
+        seconds since the run started, and query points per second so far."""
         hist = []
+        sink = open(jsonl, "a") if jsonl else None
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         reached = None
-        for i in range(1, max_steps + 1):
-            self.step()
-            if i % check_every == 0 or i == max_steps:
-                mse = self.mse()
-                if not math.isfinite(mse):
-                    raise FloatingPointError(f"non-finite loss at step {self.t}; "
-                                             "restore the last checkpoint (Fitter.load)")
-                p = psnr_from_mse(mse, self.peak)
-                el = time.perf_counter() - t0
-                hist.append((i, p, el))
-                if log and (i % log_every == 0 or i == max_steps):
-                    log(f"step {i}: psnr {p:.2f} dB ({el:.2f} s)")
-                if target_psnr is not None and p >= target_psnr:
-                    reached = i
-                    break
+        try:
+            for i in range(1, max_steps + 1):
+                self.step()
+                if i % check_every == 0 or i == max_steps:
+                    mse = self.mse()
+                    if not math.isfinite(mse):
+                        raise FloatingPointError(f"non-finite loss at step {self.t}; "
+                                                 "restore the last checkpoint (Fitter.load)")
+                    p = psnr_from_mse(mse, self.peak)
+                    el = time.perf_counter() - t0
+                    hist.append((i, p, el))
+                    if sink:   # the loss of step t's forward pass
+                        sink.write(json.dumps(dict(step=self.t, mse=mse, psnr=p, seconds=el,
+                                                   queries_per_s=i * self.q / max(el, 1e-12)))
+                                   + "\n")
+                    if log and (i % log_every == 0 or i == max_steps):
+                        log(f"step {i}: psnr {p:.2f} dB ({el:.2f} s)")
+                    if target_psnr is not None and p >= target_psnr:
+                        reached = i
+                        break
+        finally:
+            if sink:
+                sink.close()
         torch.cuda.synchronize()
         return dict(history=hist, reached=reached, seconds=time.perf_counter() - t0)
 

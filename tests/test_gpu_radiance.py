@@ -449,7 +449,12 @@ def test_fit_checkpoint_resume(rad, tmp_path):
     ha = a.run(10, check_every=1)["history"]
     b = Fitter(Field(*start.arrays()), qs, T).load(ck)
     assert b.t == 10
-    hb = b.run(10, check_every=1)["history"]
+    log = tmp_path / "fit.jsonl"
+    hb = b.run(10, check_every=1, jsonl=str(log))["history"]
+    import json
+    recs = [json.loads(line) for line in log.read_text().splitlines()]
+    assert [r["step"] for r in recs] == list(range(11, 21))
+    assert all(r["queries_per_s"] > 0 and abs(r["psnr"] - h[1]) < 1e-9 for r, h in zip(recs, hb))
     for (sa, pa, _), (sb, pb, _) in zip(ha, hb):
         assert sa == sb and abs(pa - pb) < 1e-3, (sa, pa, pb)
     for k in a.f.p:
