@@ -338,9 +338,13 @@ gpf_status gpf_mse_loss(const float *L, const float *T, int64_t q, double *loss_
 /* ---- optimiser (Adam, Kingma & Ba 2015; the paper trains with Adam) ------
  * One fused Adam update of n FP32 values: m = b1 m + (1-b1) g,
  * v = b2 v + (1-b2) g^2, p -= lr * (m / (1-b1^t)) / (sqrt(v / (1-b2^t)) + eps).
- * `step` is the 1-based step count t.  p, g, m, v are distinct buffers of n. */
+ * `step` is the 1-based step count t.  p, g, m, v are distinct buffers of n.
+ * `guard` (device, FP64, may be NULL), e.g. the loss sum of gpf_mse_loss:
+ * when it is not finite the update is skipped on the device and p, m, v keep
+ * their values, so a non-finite loss never reaches the parameters. */
 gpf_status gpf_adam_step(float *p, const float *g, float *m, float *v, int64_t n, float lr,
-                         float beta1, float beta2, float eps, int64_t step, void *stream);
+                         float beta1, float beta2, float eps, int64_t step, const double *guard,
+                         void *stream);
 
 /* ---- photon-to-Gaussian initialisation (Sec. 4.1 physically-inspired
  * initialisation: one Gaussian per photon, centre = photon position, flux =

@@ -107,6 +107,18 @@ def _chunks(q, n, budget=2_000_000):
         yield a, min(q, a + step)
 
 
+def rounding_scale(W, d):
+    """eta[..., k] = sum_j |W_kj d_j| for pairs (W [...,3,3], d [...,3]).
+
+    Evaluating u_k = W_k . d in a working precision with unit roundoff e
+    (W rounded once, d = x - mu rounded once, a three-term dot product) leaves
+    an absolute error in u_k of order e * eta_k, whatever the size of u_k: for
+    a thin primitive and a point near one of its planes the dot product
+    cancels, so eta_k can exceed |u_k| by orders of magnitude.  The ``_cond``
+    outputs are the first-order effect of such errors."""
+    return np.sum(np.abs(W * d[..., None, :]), axis=-1)
+
+
 def _pair_terms(x, mu, W):
     """d [qc,n,3], u [qc,n,3], m2 [qc,n] for a query chunk."""
     d = x[:, None, :] - mu[None, :, :]
@@ -160,7 +172,7 @@ def radiance(mu, quat, log_scale, rgb, x, cutoff=3.0, truncate=True, amb_rel=1e-
         qi, pi = np.nonzero(inc | amb)
         w = np.exp(-0.5 * m2[qi, pi])
         contrib = w[:, None] * rgb[pi]
-        eta = np.sum(np.abs(W[pi] * d[qi, pi][:, None, :]), axis=2)
+        eta = rounding_scale(W[pi], d[qi, pi])
         sens = np.sum(np.abs(u[qi, pi]) * eta, axis=1)
         np.add.at(L_cond, a + qi[inc[qi, pi]], (np.abs(contrib) * sens[:, None])[inc[qi, pi]])
         is_inc = inc[qi, pi]
@@ -286,7 +298,7 @@ def radiance_backward(mu, quat, log_scale, rgb, x, g, cutoff=3.0):
         # sensitivity of each contribution to the whitened coordinates u_l
         # (w, c carry exp(-|u|^2/2), so dc/du_l = -c u_l), weighted by eta_l
         Wp = W[pi]
-        eta = np.sum(np.abs(Wp * dd[:, None, :]), axis=2)                 # [p,l]
+        eta = rounding_scale(Wp, dd)                                       # [p,l]
         J_m = c[:, None, None] * Wp - t_m[:, None, :] * uu[:, :, None]     # [p,l,j]
         np.add.at(cm, pi, np.einsum("plj,pl->pj", np.abs(J_m), eta))
         eye = np.eye(3)

@@ -10,8 +10,7 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-# GPF_LIBRARY may point at another build of the same library (e.g. a tuning variant)
-LIB_PATH = os.environ.get("GPF_LIBRARY") or os.path.join(HERE, "libgpf.so")
+LIB_PATH = os.path.join(HERE, "libgpf.so")
 
 GPF_OK = 0
 STATUS = {0: "OK", 1: "INVALID_ARGUMENT", 2: "OUT_OF_MEMORY", 3: "CAPACITY", 4: "HIP", 5: "STALE"}
@@ -82,7 +81,7 @@ _SIG = {
     "gpf_photon_density": (ctypes.c_int, [_P, _P, _I64, _P, _P, _P, _I64, _F, _F, ctypes.c_int,
                                             _P, _P, _P]),
     "gpf_mse_loss": (ctypes.c_int, [_P, _P, _I64, _P, _P, _P]),
-    "gpf_adam_step": (ctypes.c_int, [_P, _P, _P, _P, _I64, _F, _F, _F, _F, _I64, _P]),
+    "gpf_adam_step": (ctypes.c_int, [_P, _P, _P, _P, _I64, _F, _F, _F, _F, _I64, _P, _P]),
     "gpf_photon_knn": (ctypes.c_int, [_P, _I64, ctypes.c_int, _P, _P, _P]),
     "gpf_photon_features": (ctypes.c_int, [_P, _P, _I64, _P, _P, _P, _P]),
     "gpf_init_from_photons": (ctypes.c_int, [_P, _P, _I64, ctypes.c_int, _P,

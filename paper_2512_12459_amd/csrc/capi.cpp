@@ -474,14 +474,15 @@ gpf_status gpf_mse_loss(const float* L, const float* T, int64_t q, double* loss_
 }
 
 gpf_status gpf_adam_step(float* p, const float* g, float* m, float* v, int64_t n, float lr,
-                         float beta1, float beta2, float eps, int64_t step, void* stream) {
+                         float beta1, float beta2, float eps, int64_t step, const double* guard,
+                         void* stream) {
   if (!p || !g || !m || !v) return set_error(GPF_ERR_INVALID_ARGUMENT, "NULL argument");
   if (n < 0) return set_error(GPF_ERR_INVALID_ARGUMENT, "n must be >= 0");
   if (step < 1) return set_error(GPF_ERR_INVALID_ARGUMENT, "step must be >= 1");
   if (!(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps >= 0.f))
     return set_error(GPF_ERR_INVALID_ARGUMENT, "bad Adam hyper-parameters");
   if (n == 0) return GPF_OK;
-  return launch_adam(p, g, m, v, n, lr, beta1, beta2, eps, step, (hipStream_t)stream);
+  return launch_adam(p, g, m, v, n, lr, beta1, beta2, eps, step, guard, (hipStream_t)stream);
 }
 
 }  // extern "C"

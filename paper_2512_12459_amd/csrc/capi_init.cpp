@@ -121,7 +121,8 @@ gpf_status gpf_mlp_train_step(gpf_mlp* m, const uint16_t* X, const float* T, int
   gpf_status st = mlp_grad(X, T, b, m->w, m->params, m->grad, loss_sum, s);
   if (st != GPF_OK) return st;
   m->step += 1;
-  st = launch_adam(m->params, m->grad, m->m, m->v, kParams, lr, 0.9f, 0.999f, 1e-8f, m->step, s);
+  st = launch_adam(m->params, m->grad, m->m, m->v, kParams, lr, 0.9f, 0.999f, 1e-8f, m->step,
+                   nullptr, s);
   if (st != GPF_OK) return st;
   return mlp_convert(m->params, m->w, s);
 }

@@ -192,7 +192,8 @@ gpf_status launch_valu_probe(float* out, int blocks, int iters, hipStream_t s);
 gpf_status launch_mse(const float* L, const float* T, int64_t q, double* loss, float* dL,
                       hipStream_t s);
 gpf_status launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr,
-                       float b1, float b2, float eps, int64_t step, hipStream_t s);
+                       float b1, float b2, float eps, int64_t step, const double* guard,
+                       hipStream_t s);
 
 // Workgroup -> work-item remap.  Workgroups are dealt round-robin over the 8
 // XCDs; this mapping hands each XCD whole chunks of kXcdChunk consecutive

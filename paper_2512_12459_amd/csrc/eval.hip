@@ -54,27 +54,25 @@ constexpr int kFwdSurvCap = 256;   // staged survivors per wave
 // One wave per group of two consecutive tiles of one cell: lane l owns point l
 // of the first tile and point l of the second.  Lane = candidate culls the
 // cell's list against both tile boxes; a survivor is staged in LDS as
-// {index | tile mask << 30, b'} with b' = W' (mu - centre), centre = the group
-// box centre.  Every lane then evaluates each survivor for the tiles it may
-// touch (a wave-uniform branch per tile), reading W' and the flux with
-// wave-uniform scalar loads: u' = W' (x - centre) - b'.  The survivor loop is
-// bound by the latency of its scalar loads, so the kernel is held to 64 VGPRs
-// (8 waves per SIMD instead of 7).
+// index | tile mask << 30.  Every lane then evaluates each survivor for the
+// tiles it may touch (a wave-uniform branch per tile), reading mu, W' and the
+// flux with wave-uniform scalar loads: d = x - mu, u' = W' d (the local frame
+// of Alg. S3), w = 2^-|u'|^2 inside the cut.  The survivor loop is bound by the
+// latency of its scalar loads, so the kernel is held to 64 VGPRs (8 waves per
+// SIMD instead of 7).
 __global__ void __launch_bounds__(kWaves * 64) __attribute__((amdgpu_waves_per_eu(8, 8)))
 eval_fwd_kernel(
     const float4* __restrict__ xs, const int* __restrict__ perm,
-    const GroupInfo* __restrict__ groups, const float4* __restrict__ glo,
-    const float4* __restrict__ ghi, int ngroups, const float4* __restrict__ tlo,
+    const GroupInfo* __restrict__ groups, int ngroups, const float4* __restrict__ tlo,
     const float4* __restrict__ thi, const int* __restrict__ cell_start,
     const int* __restrict__ cell_prims, const PrimRec* __restrict__ recs, float c2,
     float* __restrict__ L, int* __restrict__ keep, int* __restrict__ keep_count) {
   static_assert(kGroupTiles == 2, "the forward pairs the two tiles of a group");
-  __shared__ int4 surv[kWaves][kFwdSurvCap];
+  __shared__ int surv[kWaves][kFwdSurvCap];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int g = xcd_remap(blockIdx.x) * kWaves + wave;
   if (g >= ngroups) return;
   const GroupInfo gi = groups[g];
-  const TileCtx gc = tile_ctx(glo, ghi, g);
   const TileCtx ta = tile_ctx(tlo, thi, gi.first_tile);
   const bool has_b = gi.count > kTile;
   const TileCtx tb = has_b ? tile_ctx(tlo, thi, gi.first_tile + 1) : ta;
@@ -82,60 +80,51 @@ eval_fwd_kernel(
 #pragma unroll
   for (int i = 0; i < 2; ++i) {
     const float4 p = xs[gi.start + min(lane + 64 * i, gi.count - 1)];
-    px[i] = p.x - gc.cx;
-    py[i] = p.y - gc.cy;
-    pz[i] = p.z - gc.cz;
+    px[i] = p.x;
+    py[i] = p.y;
+    pz[i] = p.z;
     acc[i][0] = acc[i][1] = acc[i][2] = 0.f;
   }
   const int cs = cell_start[gi.cell], ce = cell_start[gi.cell + 1];
-  int4* sv = surv[wave];
+  int* sv = surv[wave];
   int ns = 0, kept = 0;  // kept: survivors so far (all of them, also past the list's capacity)
   int* kl = keep ? keep + (int64_t)g * kSurvPerGroup : nullptr;
   for (int base = cs; base < ce; base += 64) {
     const int j = base + lane;
     int mask = 0, pid = 0;
-    float b0 = 0.f, b1 = 0.f, b2 = 0.f;
     if (j < ce) {
       pid = cell_prims[j];
       const PrimRec r = recs[pid];
       mask = (tile_may_touch(r, ta, c2) ? 1 : 0) | ((has_b && tile_may_touch(r, tb, c2)) ? 2 : 0);
-      if (mask) {
-        const float mx = r.r0.x - gc.cx, my = r.r0.y - gc.cy, mz = r.r0.z - gc.cz;
-        b0 = r.r1.x * mx + r.r1.y * my + r.r1.z * mz;
-        b1 = r.r2.x * mx + r.r2.y * my + r.r2.z * mz;
-        b2 = r.r3.x * mx + r.r3.y * my + r.r3.z * mz;
-      }
     }
     const uint64_t bal = __ballot(mask != 0);
     if (mask) {
       const uint64_t below = bal & ((lane == 0) ? 0ull : (~0ull >> (64 - lane)));
-      sv[ns + __popcll(below)] =
-          make_int4(pid | (mask << 30), __float_as_int(b0), __float_as_int(b1), __float_as_int(b2));
+      sv[ns + __popcll(below)] = pid | (mask << 30);
     }
     ns += __popcll(bal);
     if (ns > kFwdSurvCap - 64 || base + 64 >= ce) {
       wave_sync_lds();
       const int nsu = __builtin_amdgcn_readfirstlane(ns);  // wave-uniform trip count
       if (kl) {  // keep the survivors (cell-list order) for the backward
-        for (int s = lane; s < nsu && kept + s < kSurvPerGroup; s += 64) kl[kept + s] = sv[s].x;
+        for (int s = lane; s < nsu && kept + s < kSurvPerGroup; s += 64) kl[kept + s] = sv[s];
         kept += nsu;
       }
       for (int s = 0; s < nsu; ++s) {
-        const int4 e = sv[s];
-        const int head = __builtin_amdgcn_readfirstlane(e.x);
+        const int head = __builtin_amdgcn_readfirstlane(sv[s]);
         const PrimRec r = recs[head & 0x3fffffff];
-        const float nb0 = -__int_as_float(e.y), nb1 = -__int_as_float(e.z), nb2 = -__int_as_float(e.w);
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
           if (!((head >> (30 + i)) & 1)) continue;   // wave-uniform
-          const float u0 = fmaf(r.r1.z, pz[i], fmaf(r.r1.y, py[i], fmaf(r.r1.x, px[i], nb0)));
-          const float u1 = fmaf(r.r2.z, pz[i], fmaf(r.r2.y, py[i], fmaf(r.r2.x, px[i], nb1)));
-          const float u2 = fmaf(r.r3.z, pz[i], fmaf(r.r3.y, py[i], fmaf(r.r3.x, px[i], nb2)));
-          const float m2 = u0 * u0 + u1 * u1 + u2 * u2;
+          const float dx = px[i] - r.r0.x, dy = py[i] - r.r0.y, dz = pz[i] - r.r0.z;
+          const float u0 = fmaf(r.r1.z, dz, fmaf(r.r1.y, dy, r.r1.x * dx));
+          const float u1 = fmaf(r.r2.z, dz, fmaf(r.r2.y, dy, r.r2.x * dx));
+          const float u2 = fmaf(r.r3.z, dz, fmaf(r.r3.y, dy, r.r3.x * dx));
+          const float m2 = fmaf(u2, u2, fmaf(u1, u1, u0 * u0));
           const float w = (m2 <= c2) ? __builtin_amdgcn_exp2f(-m2) : 0.f;
-          acc[i][0] += w * r.r0.w;
-          acc[i][1] += w * r.r1.w;
-          acc[i][2] += w * r.r2.w;
+          acc[i][0] = fmaf(w, r.r0.w, acc[i][0]);
+          acc[i][1] = fmaf(w, r.r1.w, acc[i][1]);
+          acc[i][2] = fmaf(w, r.r2.w, acc[i][2]);
         }
       }
       ns = 0;
@@ -190,10 +179,10 @@ __global__ void __launch_bounds__(kWaves * 64) count_pairs_kernel(
         const int id = __builtin_amdgcn_readfirstlane(sv[s]);
         const PrimRec r = recs[id];
         const float dx = p.x - r.r0.x, dy = p.y - r.r0.y, dz = p.z - r.r0.z;
-        const float u0 = r.r1.x * dx + r.r1.y * dy + r.r1.z * dz;
-        const float u1 = r.r2.x * dx + r.r2.y * dy + r.r2.z * dz;
-        const float u2 = r.r3.x * dx + r.r3.y * dy + r.r3.z * dz;
-        const float m2 = u0 * u0 + u1 * u1 + u2 * u2;
+        const float u0 = fmaf(r.r1.z, dz, fmaf(r.r1.y, dy, r.r1.x * dx));
+        const float u1 = fmaf(r.r2.z, dz, fmaf(r.r2.y, dy, r.r2.x * dx));
+        const float u2 = fmaf(r.r3.z, dz, fmaf(r.r3.y, dy, r.r3.x * dx));
+        const float m2 = fmaf(u2, u2, fmaf(u1, u1, u0 * u0));
         cnt += (active && m2 <= c2) ? 1u : 0u;
       }
       ns = 0;
@@ -217,19 +206,15 @@ constexpr int kListCap = 128;                 // survivor slots per list and wav
 constexpr int kRowStride = 14;                // transpose row stride (12 sums, pad, row id)
 
 // 64 survivors (lane = primitive) against the points [qb, qe) of the wave's
-// group, held in LDS relative to the group centre (points past the group's
-// count carry a zero upstream gradient).  The 12 per-primitive sums are added
-// to the padded per-primitive buffer with row-coalesced atomics: after an LDS
-// transpose, 16 lanes update one 64-byte row per instruction.
-__device__ __forceinline__ void bwd_chunk(int id, bool valid, int qb, int qe, const TileCtx& tc,
+// group, held in LDS (points past the group's count carry a zero upstream
+// gradient).  The 12 per-primitive sums are added to the padded per-primitive
+// buffer with row-coalesced atomics: after an LDS transpose, 16 lanes update
+// one 64-byte row per instruction.
+__device__ __forceinline__ void bwd_chunk(int id, bool valid, int qb, int qe,
                                           const PrimRec* __restrict__ recs, float c2,
                                           const float4* qx, const float4* qg, float* rw,
                                           float* __restrict__ grad_rows, int lane) {
   const PrimRec r = recs[id];
-  const float mx = r.r0.x - tc.cx, my = r.r0.y - tc.cy, mz = r.r0.z - tc.cz;
-  const float b0 = r.r1.x * mx + r.r1.y * my + r.r1.z * mz;
-  const float b1 = r.r2.x * mx + r.r2.y * my + r.r2.z * mz;
-  const float b2 = r.r3.x * mx + r.r3.y * my + r.r3.z * mz;
   float GP[3] = {0.f, 0.f, 0.f}, A[3] = {0.f, 0.f, 0.f};
   float U[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   bool any = false;
@@ -242,33 +227,33 @@ __device__ __forceinline__ void bwd_chunk(int id, bool valid, int qb, int qe, co
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const float u0 = fmaf(r.r1.z, xq[i].z, fmaf(r.r1.y, xq[i].y, fmaf(r.r1.x, xq[i].x, -b0)));
-      const float u1 = fmaf(r.r2.z, xq[i].z, fmaf(r.r2.y, xq[i].y, fmaf(r.r2.x, xq[i].x, -b1)));
-      const float u2 = fmaf(r.r3.z, xq[i].z, fmaf(r.r3.y, xq[i].y, fmaf(r.r3.x, xq[i].x, -b2)));
-      const float m2 = u0 * u0 + u1 * u1 + u2 * u2;
+      const float dx = xq[i].x - r.r0.x, dy = xq[i].y - r.r0.y, dz = xq[i].z - r.r0.z;
+      const float u0 = fmaf(r.r1.z, dz, fmaf(r.r1.y, dy, r.r1.x * dx));
+      const float u1 = fmaf(r.r2.z, dz, fmaf(r.r2.y, dy, r.r2.x * dx));
+      const float u2 = fmaf(r.r3.z, dz, fmaf(r.r3.y, dy, r.r3.x * dx));
+      const float m2 = fmaf(u2, u2, fmaf(u1, u1, u0 * u0));
       const bool in = m2 <= c2;
       const float w = in ? __builtin_amdgcn_exp2f(-m2) : 0.f;
       any |= in;
-      const float a = gq[i].x * r.r0.w + gq[i].y * r.r1.w + gq[i].z * r.r2.w;
+      const float a = fmaf(gq[i].z, r.r2.w, fmaf(gq[i].y, r.r1.w, gq[i].x * r.r0.w));
       const float c = a * w;
-      GP[0] += w * gq[i].x;
-      GP[1] += w * gq[i].y;
-      GP[2] += w * gq[i].z;
+      GP[0] = fmaf(w, gq[i].x, GP[0]);
+      GP[1] = fmaf(w, gq[i].y, GP[1]);
+      GP[2] = fmaf(w, gq[i].z, GP[2]);
       const float cu0 = c * u0, cu1 = c * u1, cu2 = c * u2;
       A[0] += cu0;
       A[1] += cu1;
       A[2] += cu2;
-      U[0] += cu0 * u0;
-      U[1] += cu0 * u1;
-      U[2] += cu0 * u2;
-      U[3] += cu1 * u1;
-      U[4] += cu1 * u2;
-      U[5] += cu2 * u2;
+      U[0] = fmaf(cu0, u0, U[0]);
+      U[1] = fmaf(cu0, u1, U[1]);
+      U[2] = fmaf(cu0, u2, U[2]);
+      U[3] = fmaf(cu1, u1, U[3]);
+      U[4] = fmaf(cu1, u2, U[4]);
+      U[5] = fmaf(cu2, u2, U[5]);
     }
   }
-  // the sums do not depend on the group centre (u' = W'(x - mu)), so they
-  // are added over groups as they are and mapped to parameter gradients once
-  // per primitive by the finalize pass
+  // the sums are added over groups as they are and mapped to parameter
+  // gradients once per primitive by the finalize pass
   const bool write = valid && any;
   const float sums[12] = {GP[0], GP[1], GP[2], A[0], A[1], A[2], U[0], U[1], U[2], U[3], U[4], U[5]};
 #pragma unroll
@@ -296,8 +281,7 @@ __device__ __forceinline__ void bwd_chunk(int id, bool valid, int qb, int qe, co
 // tile only if one of its survivors may touch it, and over the first likewise.
 __global__ void __launch_bounds__(kBwdThreads) eval_bwd_kernel(
     const float4* __restrict__ xs, const int* __restrict__ perm,
-    const GroupInfo* __restrict__ groups, const float4* __restrict__ glo,
-    const float4* __restrict__ ghi, int ngroups, const float4* __restrict__ tlo,
+    const GroupInfo* __restrict__ groups, int ngroups, const float4* __restrict__ tlo,
     const float4* __restrict__ thi, const int* __restrict__ cell_start,
     const int* __restrict__ cell_prims, const PrimRec* __restrict__ recs, float c2,
     const float* __restrict__ dL, float* __restrict__ grad_rows, const int* __restrict__ keep,
@@ -311,7 +295,6 @@ __global__ void __launch_bounds__(kBwdThreads) eval_bwd_kernel(
   const int g = xcd_remap(blockIdx.x) * kBwdWaves + wave;
   if (g >= ngroups) return;  // per wave: no workgroup barrier follows
   const GroupInfo gi = groups[g];
-  const TileCtx tc = tile_ctx(glo, ghi, g);
   const TileCtx ta = tile_ctx(tlo, thi, gi.first_tile);
   const bool has_b = gi.count > kTile;
   const TileCtx tb = has_b ? tile_ctx(tlo, thi, gi.first_tile + 1) : ta;
@@ -325,10 +308,10 @@ __global__ void __launch_bounds__(kBwdThreads) eval_bwd_kernel(
     if (k < gi.count) {
       const int o = perm[gi.start + k];
       const float4 p = xs[gi.start + k];
-      qx[k] = make_float4(p.x - tc.cx, p.y - tc.cy, p.z - tc.cz, 0.f);
+      qx[k] = make_float4(p.x, p.y, p.z, 0.f);
       qg[k] = make_float4(dL[(int64_t)o * 3], dL[(int64_t)o * 3 + 1], dL[(int64_t)o * 3 + 2], 0.f);
     } else {
-      qx[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+      qx[k] = make_float4(ta.cx, ta.cy, ta.cz, 0.f);   // any finite point; g = 0
       qg[k] = make_float4(0.f, 0.f, 0.f, 0.f);
     }
   }
@@ -359,15 +342,15 @@ __global__ void __launch_bounds__(kBwdThreads) eval_bwd_kernel(
       wave_sync_lds();
       if (n0 >= 64) {
         n0 -= 64;
-        bwd_chunk(sv0[n0 + lane], true, 0, qe_a, tc, recs, c2, qx, qg, rw, grad_rows, lane);
+        bwd_chunk(sv0[n0 + lane], true, 0, qe_a, recs, c2, qx, qg, rw, grad_rows, lane);
       }
       if (n1 >= 64) {
         n1 -= 64;
-        bwd_chunk(sv1[n1 + lane], true, kTile, qe_all, tc, recs, c2, qx, qg, rw, grad_rows, lane);
+        bwd_chunk(sv1[n1 + lane], true, kTile, qe_all, recs, c2, qx, qg, rw, grad_rows, lane);
       }
       if (n2 >= 64) {
         n2 -= 64;
-        bwd_chunk(sv2[n2 + lane], true, 0, qe_all, tc, recs, c2, qx, qg, rw, grad_rows, lane);
+        bwd_chunk(sv2[n2 + lane], true, 0, qe_all, recs, c2, qx, qg, rw, grad_rows, lane);
       }
     }
   } else {
@@ -401,15 +384,15 @@ __global__ void __launch_bounds__(kBwdThreads) eval_bwd_kernel(
     wave_sync_lds();
     if (n0 >= 64) {
       n0 -= 64;
-      bwd_chunk(sv0[n0 + lane], true, 0, qe_a, tc, recs, c2, qx, qg, rw, grad_rows, lane);
+      bwd_chunk(sv0[n0 + lane], true, 0, qe_a, recs, c2, qx, qg, rw, grad_rows, lane);
     }
     if (n1 >= 64) {
       n1 -= 64;
-      bwd_chunk(sv1[n1 + lane], true, kTile, qe_all, tc, recs, c2, qx, qg, rw, grad_rows, lane);
+      bwd_chunk(sv1[n1 + lane], true, kTile, qe_all, recs, c2, qx, qg, rw, grad_rows, lane);
     }
     if (n2 >= 64) {
       n2 -= 64;
-      bwd_chunk(sv2[n2 + lane], true, 0, qe_all, tc, recs, c2, qx, qg, rw, grad_rows, lane);
+      bwd_chunk(sv2[n2 + lane], true, 0, qe_all, recs, c2, qx, qg, rw, grad_rows, lane);
     }
     pid_c = pid_n;
     rec_c = rec_n;
@@ -431,7 +414,7 @@ __global__ void __launch_bounds__(kBwdThreads) eval_bwd_kernel(
       cat = 2;
     }
     const bool use_a = __ballot(cat & 1) != 0, use_b = __ballot(cat & 2) != 0;
-    bwd_chunk(id, cat != 0, use_a ? 0 : kTile, use_b ? qe_all : qe_a, tc, recs, c2, qx, qg,
+    bwd_chunk(id, cat != 0, use_a ? 0 : kTile, use_b ? qe_all : qe_a, recs, c2, qx, qg,
               rw, grad_rows, lane);
   }
 }
@@ -467,7 +450,7 @@ gpf_status launch_eval_fwd(const gpf_grid* gc, float* L, hipStream_t s) {
   const float c2 = (float)(kKappa2 * g->cutoff * g->cutoff);
   ensure_survivor_lists(g);
   hipLaunchKernelGGL(eval_fwd_kernel, dim3(xcd_grid(fwd_blocks(qs->ngroups))), dim3(kWaves * 64), 0, s,
-                     qs->xs, qs->perm, qs->groups, qs->group_lo, qs->group_hi, (int)qs->ngroups,
+                     qs->xs, qs->perm, qs->groups, (int)qs->ngroups,
                      qs->tile_lo, qs->tile_hi, g->cell_start, g->cell_prims, g->rec, c2, L, g->surv,
                      g->surv ? g->surv_count : nullptr);
   GPF_HIP(hipGetLastError());
@@ -509,7 +492,7 @@ gpf_status launch_eval_bwd(const gpf_grid* gc, const float* dL, gpf_field_grad* 
   if (st != GPF_OK) return st;
   hipLaunchKernelGGL(eval_bwd_kernel, dim3(xcd_grid((qs->ngroups + kBwdWaves - 1) / kBwdWaves)),
                      dim3(kBwdThreads), 0, s, qs->xs,
-                     qs->perm, qs->groups, qs->group_lo, qs->group_hi, (int)qs->ngroups,
+                     qs->perm, qs->groups, (int)qs->ngroups,
                      qs->tile_lo, qs->tile_hi, g->cell_start, g->cell_prims, g->rec, c2, dL,
                      (float*)g->grad_rows, g->surv_ready ? g->surv : nullptr,
                      g->surv_ready ? g->surv_count : nullptr);

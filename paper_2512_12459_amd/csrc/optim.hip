@@ -29,7 +29,9 @@ __global__ void __launch_bounds__(256) adam_kernel(float* __restrict__ p,
                                                    const float* __restrict__ g,
                                                    float* __restrict__ m, float* __restrict__ v,
                                                    int64_t n, float lr, float b1, float b2,
-                                                   float eps, float bc1, float bc2) {
+                                                   float eps, float bc1, float bc2,
+                                                   const double* __restrict__ guard) {
+  if (guard && !isfinite(*guard)) return;   // a non-finite loss leaves the state as it was
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
     const float gi = g[i];
@@ -56,11 +58,11 @@ gpf_status launch_mse(const float* L, const float* T, int64_t q, double* loss, f
 }
 
 gpf_status launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1,
-                       float b2, float eps, int64_t step, hipStream_t s) {
+                       float b2, float eps, int64_t step, const double* guard, hipStream_t s) {
   const float bc1 = (float)(1.0 - std::pow((double)b1, (double)step));
   const float bc2 = (float)(1.0 - std::pow((double)b2, (double)step));
   hipLaunchKernelGGL(adam_kernel, dim3(blocks_for(n)), dim3(256), 0, s, p, g, m, v, n, lr, b1, b2,
-                     eps, bc1, bc2);
+                     eps, bc1, bc2, guard);
   GPF_HIP(hipGetLastError());
   return GPF_OK;
 }

@@ -103,8 +103,10 @@ class Fitter:
         else:
             R.eval_radiance_backward(self.grid, *f.arrays(), self.dL, f.g)
         self.t += 1
+        # a non-finite loss skips the update on the device: the parameters keep
+        # the last state whose loss was finite until the next check stops the run
         for k, _ in Field.GROUPS:
-            R.adam_step(f.p[k], f.g[k], f.m[k], f.v[k], self.t, self.lr[k])
+            R.adam_step(f.p[k], f.g[k], f.m[k], f.v[k], self.t, self.lr[k], guard=self.loss)
 
     def mse(self) -> float:
         """Per-element mean squared error of the radiance before the last step."""
@@ -134,8 +136,10 @@ class Fitter:
                 if i % check_every == 0 or i == max_steps:
                     mse = self.mse()
                     if not math.isfinite(mse):
-                        raise FloatingPointError(f"non-finite loss at step {self.t}; "
-                                                 "restore the last checkpoint (Fitter.load)")
+                        raise FloatingPointError(
+                            f"non-finite loss at step {self.t}; updates of steps with a "
+                            "non-finite loss were skipped, so the parameters are those of the "
+                            "last step whose loss was finite (Fitter.load restores a checkpoint)")
                     p = psnr_from_mse(mse, self.peak)
                     el = time.perf_counter() - t0
                     hist.append((i, p, el))

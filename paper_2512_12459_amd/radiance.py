@@ -191,10 +191,6 @@ class HybridGrid(Grid):
         self._field = (mu, quat, log_scale, rgb)
         return self
 
-    def count_pairs(self) -> int:
-        raise NotImplementedError("the hybrid query's pair count is sum(max(count, k_min)) "
-                                  "over eval_hybrid's count output")
-
 
 def eval_hybrid(grid: HybridGrid, mu, quat, log_scale, rgb):
     """(L [q,3], Z [q], count [q] int32) at the grid's query points."""
@@ -266,14 +262,19 @@ def mse_loss(L: torch.Tensor, T: torch.Tensor, dL: torch.Tensor | None = None,
     return loss_sum, dL
 
 
-def adam_step(p, g, m, v, step: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-15):
+def adam_step(p, g, m, v, step: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-15, guard=None):
+    """One Adam update; with ``guard`` (a float64 device tensor, e.g. the loss
+    sum) the update is skipped on the device when guard[0] is not finite."""
+    if guard is not None and (guard.dtype != torch.float64 or guard.device.type != "cuda"):
+        raise ValueError("guard must be a float64 device tensor")
     for t in (p, g, m, v):
         if t.dtype != torch.float32 or not t.is_contiguous() or t.device.type != "cuda":
             raise ValueError("adam_step needs contiguous float32 device tensors")
     if not (p.numel() == g.numel() == m.numel() == v.numel()):
         raise ValueError("adam_step tensors differ in size")
     C.check(C.lib().gpf_adam_step(C.ptr(p), C.ptr(g), C.ptr(m), C.ptr(v), p.numel(), float(lr),
-                                  float(beta1), float(beta2), float(eps), int(step), _stream()))
+                                  float(beta1), float(beta2), float(eps), int(step),
+                                  C.ptr(guard), _stream()))
 
 
 def valu_probe(blocks: int = 4096, iters: int = 2000, reps: int = 5) -> float:

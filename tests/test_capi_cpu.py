@@ -47,9 +47,9 @@ def test_host_validation_without_device_work():
     assert L.gpf_build_grid(ctypes.byref(f), 0.0, fake, None, ctypes.byref(h)) == 1
     assert L.gpf_build_grid(ctypes.byref(f), 3.0, None, None, ctypes.byref(h)) == 1
     assert L.gpf_eval_radiance(None, ctypes.byref(f), fake, 5, fake, None) == 1
-    assert L.gpf_adam_step(None, fake, fake, fake, 5, 1e-3, 0.9, 0.999, 1e-8, 1, None) == 1
-    assert L.gpf_adam_step(fake, fake, fake, fake, 5, 1e-3, 1.5, 0.999, 1e-8, 1, None) == 1
-    assert L.gpf_adam_step(fake, fake, fake, fake, 5, 1e-3, 0.9, 0.999, 1e-8, 0, None) == 1
+    assert L.gpf_adam_step(None, fake, fake, fake, 5, 1e-3, 0.9, 0.999, 1e-8, 1, None, None) == 1
+    assert L.gpf_adam_step(fake, fake, fake, fake, 5, 1e-3, 1.5, 0.999, 1e-8, 1, None, None) == 1
+    assert L.gpf_adam_step(fake, fake, fake, fake, 5, 1e-3, 0.9, 0.999, 1e-8, 0, None, None) == 1
     assert L.gpf_mse_loss(None, fake, 5, fake, fake, None) == 1
     assert L.gpf_rebin_queries(None, fake, 10, 0.1, None) == 1
     q = ctypes.c_int64()

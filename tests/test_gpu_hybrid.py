@@ -10,7 +10,7 @@ import pytest
 import torch
 
 from oracle import hybrid_oracle as H
-from oracle.tolerances import check_grads, check_hybrid_forward
+from oracle.tolerances import HYBRID_COND_C, check_grads, check_hybrid_forward
 from paper_2512_12459_amd import scenes as S
 from tests.gpu_helpers import say, to_dev
 
@@ -64,7 +64,7 @@ def _check(rad, f, x, r=R_Q, k_min=3, eps=1e-6, cell=0.025, backward=True, seed=
     check_hybrid_forward(L, Z, cnt, ref)
     if backward:
         gref = H.radiance_backward(*f, x, dL, r, k_min, eps, sets=ref["sets"])
-        check_grads(grads, gref)
+        check_grads(grads, gref, cond_c=HYBRID_COND_C)
     return ref
 
 
@@ -247,6 +247,6 @@ def test_rebinned_query_set_matches_a_fresh_one(rad):
             (dLd,) = to_dev(dL)
             gg = rad.eval_hybrid_backward(hg, *dev, L, Z, cnt, dLd)
             gref = H.radiance_backward(*f, x, dL, R_Q, 3, 1e-6, sets=ref["sets"])
-            check_grads({k: v.cpu().numpy() for k, v in gg.items()}, gref)
+            check_grads({k: v.cpu().numpy() for k, v in gg.items()}, gref, cond_c=HYBRID_COND_C)
         fresh.close()
     torch.cuda.synchronize()

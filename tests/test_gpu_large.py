@@ -9,7 +9,9 @@ FP64 oracle evaluates one by one:
   of a 64-Gaussian subset against the oracle's analytic gradient and central
   differences of the FP64 loss.
 - 4,000,000 Gaussians (anisotropy up to 100:1, two clusters), 64 views at
-  1024x1024: forward on sampled points.
+  1024x1024: forward on sampled points (conditioned bar: single precision
+  cannot meet the plain 1e-5 bar for 100:1 primitives); backward rows of 64
+  primitives, a quarter of them at least 50:1.
 """
 import numpy as np
 import pytest
@@ -18,9 +20,9 @@ from scipy.spatial import cKDTree
 
 from oracle import exact_cull as E
 from oracle import gpf_oracle as O
-from oracle.tolerances import check_forward, check_grads
+from oracle.tolerances import EPS32, HYBRID_COND_C
 from paper_2512_12459_amd import scenes as S
-from tests.gpu_helpers import say
+from tests.gpu_helpers import check_forward, check_grads, say
 
 pytestmark = pytest.mark.gpu
 CELL = 0.025
@@ -67,6 +69,60 @@ def _pair_flags(f, rows, x, chunk=20000):
     return inc, amb
 
 
+class PointIndex:
+    """Points binned into cubic cells (a sort by cell key), to find the points
+    within a radius of a centre without a tree over tens of millions of
+    points."""
+
+    def __init__(self, x, h=0.02):
+        self.x = np.asarray(x, np.float64)
+        self.h = h
+        self.lo = self.x.min(0)
+        c = np.floor((self.x - self.lo) / h).astype(np.int64)
+        self.dims = c.max(0) + 1
+        key = (c[:, 2] * self.dims[1] + c[:, 1]) * self.dims[0] + c[:, 0]
+        self.order = np.argsort(key, kind="stable")
+        self.key = key[self.order]
+
+    def ball(self, centre, r):
+        a = np.maximum(np.floor((centre - r - self.lo) / self.h).astype(np.int64), 0)
+        b = np.minimum(np.floor((centre + r - self.lo) / self.h).astype(np.int64), self.dims - 1)
+        if np.any(b < a):
+            return np.zeros(0, np.int64)
+        zz, yy = np.meshgrid(np.arange(a[2], b[2] + 1), np.arange(a[1], b[1] + 1), indexing="ij")
+        row = (zz.ravel() * self.dims[1] + yy.ravel()) * self.dims[0]
+        s = np.searchsorted(self.key, row + a[0])
+        e = np.searchsorted(self.key, row + b[0], side="right")
+        idx = np.concatenate([self.order[i:j] for i, j in zip(s, e)] + [np.zeros(0, np.int64)])
+        keep = np.sum((self.x[idx] - centre) ** 2, axis=1) <= r * r
+        return np.sort(idx[keep])
+
+
+def _row_supports(index, f, rows):
+    rad = 3.0 * np.exp(f.log_scale[rows].astype(np.float64)).max(axis=1) * 1.001
+    return [index.ball(f.mu[i].astype(np.float64), r) for i, r in zip(rows, rad)]
+
+
+def _rows_gradient_ref(f, rows, sups, x, dL):
+    """The oracle's gradient of sum dL . L for each primitive of rows, from the
+    points of its own support (no other point has a pair with it)."""
+    parts = [O.radiance_backward(*(a[i:i + 1] for a in f.arrays()), x[sp], dL[sp])
+             for i, sp in zip(rows, sups)]
+    return {k: np.concatenate([p[k] for p in parts]) for k in parts[0]}
+
+
+def _zero_ambiguous(f, rows, sups, x, dL):
+    """Zeroes the upstream gradient at points that sit on a row primitive's
+    cutoff (either inclusion decision is valid there)."""
+    n = 0
+    for i, sp in zip(rows, sups):
+        if len(sp):
+            _, amb = _pair_flags(f, [i], x[sp])
+            dL[sp[amb]] = 0.0
+            n += int(amb.sum())
+    return n
+
+
 def test_caustic1m_full_size_forward_and_backward_rows(R):
     f, x = S.workload("caustic1m")
     q = x.shape[0]
@@ -79,25 +135,19 @@ def test_caustic1m_full_size_forward_and_backward_rows(R):
     assert ref["count"].mean() > 200
 
     # backward: seeded upstream gradient; rows of 64 primitives with support
-    tree = cKDTree(x.astype(np.float64))
+    index = PointIndex(x)
     cand = rng.choice(f.n, 400, replace=False)
-    rows = []
-    for i in cand:
-        if len(_support_queries(tree, f, [i])) > 0:
-            rows.append(int(i))
-        if len(rows) == 64:
-            break
-    rows = np.array(sorted(rows))
-    sq = _support_queries(tree, f, rows)
-    inc, amb = _pair_flags(f, rows, x[sq])
+    sups_c = _row_supports(index, f, cand)
+    rows = np.array(sorted(int(i) for i, sp in zip(cand, sups_c) if len(sp) > 0)[:64])
+    sups = _row_supports(index, f, rows)
     dL = rng.normal(size=(q, 3)).astype(np.float32)
-    dL[sq[amb]] = 0.0            # points on a subset primitive's cutoff: either decision is valid
-    say(f"case: caustic1m backward rows, {len(rows)} primitives, {len(sq)} support points")
+    n_amb = _zero_ambiguous(f, rows, sups, x, dL)
+    say(f"case: caustic1m backward rows, {len(rows)} primitives, "
+        f"{sum(len(sp) for sp in sups)} support points ({n_amb} on a cutoff)")
     grads = R.eval_radiance_backward(g, *dev, torch.from_numpy(dL).cuda())
     torch.cuda.synchronize()
     gg = {k: v.cpu().numpy()[rows] for k, v in grads.items()}
-    gref = O.radiance_backward(*(a[rows] for a in f.arrays()), x[sq], dL[sq])
-    check_grads(gg, gref)
+    check_grads(gg, _rows_gradient_ref(f, rows, sups, x, dL))
 
 
 def test_fit200k_subset_gradient_and_finite_differences(R):
@@ -170,7 +220,7 @@ def test_fit200k_subset_gradient_and_finite_differences(R):
     assert checked >= 40
 
 
-def test_stress4m_full_size_forward(R):
+def test_stress4m_full_size_forward_and_backward_rows(R):
     f, x = S.workload("stress4m")
     q = x.shape[0]
     say(f"case: stress4m forward, n={f.n} q={q}")
@@ -181,8 +231,48 @@ def test_stress4m_full_size_forward(R):
     rng = np.random.default_rng(21)
     sel = np.sort(rng.choice(q, 8000, replace=False))
     ref = E.radiance(*f.arrays(), x[sel])
-    check_forward(L.cpu().numpy()[sel], ref)
+    _, rel = check_forward(L.cpu().numpy()[sel], ref, cond=True, label="stress4m")
+    # attainable accuracy of one pair's weight in single precision: about
+    # 4.5 eps rho for anisotropy rho (here up to 100)
+    say(f"  stress4m forward: largest plain relative error {rel:.3g} against "
+        f"4.5 eps32 rho_max = {4.5 * EPS32 * 100:.3g}")
     assert ref["count"].mean() > 1000
+    del ref
+
+    # backward: rows of 64 primitives, 16 of them at least 50:1, each with
+    # a support of at most 200,000 points (to keep the oracle's work bounded)
+    s = np.exp(f.log_scale.astype(np.float64))
+    rho = s.max(1) / s.min(1)
+    index = PointIndex(x)
+    rows = []
+    for pool, want in ((np.flatnonzero(rho >= 50), 16), (np.arange(f.n), 64)):
+        for i in rng.permutation(pool)[:6000]:
+            if len(rows) >= want:
+                break
+            if int(i) in rows:
+                continue
+            sp = _row_supports(index, f, [int(i)])[0]
+            if 0 < len(sp) <= 200000:
+                inc, _ = _pair_flags(f, [int(i)], x[sp])
+                if inc.any():
+                    rows.append(int(i))
+    rows = np.array(sorted(rows))
+    assert len(rows) == 64 and np.sum(rho[rows] >= 50) >= 16
+    sups = _row_supports(index, f, rows)
+    dL = rng.normal(size=(q, 3)).astype(np.float32)
+    n_amb = _zero_ambiguous(f, rows, sups, x, dL)
+    say(f"case: stress4m backward rows, {len(rows)} primitives (max rho {rho[rows].max():.1f}), "
+        f"{sum(len(sp) for sp in sups)} support points ({n_amb} on a cutoff)")
+    grads = R.eval_radiance_backward(g, *dev, torch.from_numpy(dL).cuda())
+    torch.cuda.synchronize()
+    say(f"  torch peak after the backward {torch.cuda.max_memory_allocated()}, "
+        f"grid bytes {g.info()['device_bytes']}")
+    gg = {k: v.cpu().numpy()[rows] for k, v in grads.items()}
+    gref = _rows_gradient_ref(f, rows, sups, x, dL)
+    check_grads(gg, gref)
+    for k in gg:
+        err = np.linalg.norm(gg[k] - gref[k]) / np.linalg.norm(gref[k])
+        say(f"  stress4m {k}: group 2-norm relative error {err:.3g}")
 
 
 def test_caustic1m_hybrid_query_full_size(R):
@@ -214,4 +304,4 @@ def test_caustic1m_hybrid_query_full_size(R):
     torch.cuda.synchronize()
     gg = {k: v.cpu().numpy() for k, v in grads.items()}
     gref = H.radiance_backward(*f.arrays(), x[sel], dL[sel], 0.02, 3, sets=sets)
-    check_grads(gg, gref)
+    check_grads(gg, gref, cond_c=HYBRID_COND_C)

@@ -254,6 +254,44 @@ def test_backward_c1_all_points(rad, c1):
     check_grads(gg, gref)
 
 
+@pytest.mark.parametrize("case", ["plain4k", "crowded"])
+def test_permutation_invariance(rad, c1, case):
+    """Shuffling the primitives (Sec. 4.2: the aggregation is a sum over an
+    unordered neighbourhood) moves the GPU forward by at most 1e-5 of the
+    sum of |contributions| and its gradients by at most the gradient bar;
+    both orders match the oracle."""
+    rng = np.random.default_rng(31)
+    if case == "plain4k":
+        f, x, ref = c1
+        arrays, cell = f.arrays(), 0.025
+    else:
+        n = 3000
+        arrays = (0.5 + rng.normal(0, 0.002, (n, 3)), rng.normal(size=(n, 4)),
+                  np.log(0.01) + rng.normal(0, 0.2, (n, 3)), np.exp(rng.normal(0, 1, (n, 3))))
+        arrays = tuple(a.astype(np.float32) for a in arrays)
+        x = (0.5 + rng.normal(0, 0.01, (400, 3))).astype(np.float32)
+        ref = O.radiance(*arrays, x)
+        cell = 0.05
+    perm = rng.permutation(len(arrays[0]))
+    shuffled = tuple(np.ascontiguousarray(a[perm]) for a in arrays)
+    dL = _mask_ambiguous(ref, rng.normal(size=(len(x), 3))).astype(np.float32)
+    gref = O.radiance_backward(*arrays, x, dL)
+    say(f"case: permutation invariance, {case}")
+    L0, g0 = _gpu_grads(rad, arrays, x, dL, cell)
+    L1, g1 = _gpu_grads(rad, shuffled, x, dL, cell)
+    check_forward(L0, ref, label=f"{case} original order")
+    check_forward(L1, ref, label=f"{case} shuffled")
+    keep = ref["n_amb"] == 0
+    d = np.abs(L1.astype(np.float64) - L0)[keep]
+    assert np.all(d <= 1e-5 * ref["L_abs"][keep]), float(np.max(d / np.maximum(ref["L_abs"][keep], 1e-300)))
+    inv = np.argsort(perm)
+    g1 = {k: v[inv] for k, v in g1.items()}
+    check_grads(g0, gref)
+    check_grads(g1, gref)
+    for k in g0:
+        assert np.all(np.abs(g1[k] - g0[k]) <= 1e-4 * gref[k + "_abs"] + 1e-30 + 2 * 2.0 ** -24 * gref[k + "_cond"]), k
+
+
 def test_autograd_function_matches_direct_call(rad):
     mu, q, ls, rgb, x = _grad_problem(6, 200, 1000, 0.15)
     dev = [t.clone().requires_grad_(True) for t in to_dev(mu, q, ls, rgb)]
@@ -468,3 +506,14 @@ def test_fit_checkpoint_resume(rad, tmp_path):
     Tn[7, 1] = float("nan")
     with pytest.raises(FloatingPointError):
         Fitter(Field(*start.arrays()), qs, Tn).run(3, check_every=1)
+    # between checks a non-finite loss skips every update on the device: the
+    # run stops at the first check with the starting parameters intact
+    for bad in (float("nan"), float("inf")):
+        Tb = T.clone()
+        Tb[11, 2] = bad
+        fb = Fitter(Field(*start.arrays()), qs, Tb)
+        p0 = fb.f.P.clone()
+        say(f"case: target {bad} with checks every 5 steps")
+        with pytest.raises(FloatingPointError):
+            fb.run(7, check_every=5)
+        assert fb.t == 5 and torch.equal(fb.f.P, p0) and torch.all(fb.f.M == 0)
