@@ -149,6 +149,22 @@ gpf_status gpf_eval_radiance_backward(const gpf_grid *grid, const gpf_field *f, 
                                       int64_t q, const float *dL, gpf_field_grad *grad,
                                       void *stream);
 
+/* ---- backward without device allocation ---------------------------------
+ * For callers that cannot allocate device memory during the call: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments, result and errors as gpf_eval_radiance_backward, but the
+ * per-primitive gradient rows the backward gathers into are a static device
+ * array of the library (16 MiB on every device it runs on, held until the
+ * process ends) rather than memory of the grid handle, and the call never
+ * allocates.  At most 262,144 primitives (f->n), else GPF_ERR_CAPACITY
+ * before any launch.  The call clears the rows it uses with a fill kernel, so
+ * nothing carries over from an earlier call; calls that overlap on one
+ * device (other streams or threads) share the array and race, so the caller
+ * orders them.  The first call on a device looks up the array's address. */
+gpf_status gpf_eval_radiance_backward_noalloc(const gpf_grid *grid, const gpf_field *f,
+                                              const float *x, int64_t q, const float *dL,
+                                              gpf_field_grad *grad, void *stream);
+
 /* ---- hybrid query: the paper's own neighbourhood (supplementary Alg. S3;
  * Sec. 4.2 neighbourhood search and aggregation) ----------------------------
  * Neighbourhood N(x) of a query point: the Gaussians whose centre lies within

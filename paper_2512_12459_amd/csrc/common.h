@@ -153,10 +153,15 @@ gpf_status launch_build_grid(gpf_grid* g, hipStream_t s);
 gpf_status launch_eval_fwd(const gpf_grid* g, float* L, hipStream_t s);
 gpf_status launch_eval_bwd(const gpf_grid* g, const float* dL, gpf_field_grad* grad,
                            hipStream_t s);
+// Primitives the allocation-free backward takes (its rows are a static
+// device array of kNoAllocMaxPrims * 64 bytes).
+constexpr int64_t kNoAllocMaxPrims = (int64_t)1 << 18;
+gpf_status launch_eval_bwd_noalloc(const gpf_grid* g, const float* dL, gpf_field_grad* grad,
+                                   hipStream_t s);
 gpf_status launch_count_pairs(const gpf_grid* g, unsigned long long* d_count, hipStream_t s);
 gpf_status ensure_grad_rows(gpf_grid* g, hipStream_t s);
 void ensure_survivor_lists(gpf_grid* g);
-gpf_status launch_grad_finalize(gpf_grid* g, gpf_field_grad* grad, hipStream_t s);
+gpf_status launch_grad_finalize(gpf_grid* g, float4* rows, gpf_field_grad* grad, hipStream_t s);
 gpf_status build_centre_grid(gpf_grid* g, hipStream_t s);
 void free_centre_grid(gpf_grid* g);
 gpf_status launch_hybrid_fwd(const gpf_grid* g, float eps, float* L, float* Z, int* count,

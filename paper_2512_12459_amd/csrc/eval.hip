@@ -12,9 +12,18 @@
 //              primitive are added to padded rows with row-coalesced atomics
 //              and mapped to parameter gradients once per primitive.
 // Weights are recomputed in the backward; nothing per pair is stored.
+#include <mutex>
+
 #include "radiance_common.h"
 
 namespace gpf {
+
+// Gradient rows of the allocation-free backward: one 64-byte row per
+// primitive for up to kNoAllocMaxPrims primitives (16 MiB on every device the
+// library runs on, held until the process ends).  Host code never uses this
+// name as an address: the device address comes from hipGetSymbolAddress.
+static __device__ __align__(256) float4 scratch[kNoAllocMaxPrims * 4];
+
 namespace {
 
 constexpr int kWaves = 4;        // waves (tiles) per workgroup
@@ -420,6 +429,11 @@ __global__ void __launch_bounds__(kBwdThreads) eval_bwd_kernel(
 }
 
 
+__global__ void __launch_bounds__(256) zero_float4_kernel(float4* __restrict__ p, int64_t n) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) p[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
 }  // namespace
 
 static int fwd_blocks(int64_t ntiles) { return (int)((ntiles + kWaves - 1) / kWaves); }
@@ -475,28 +489,78 @@ gpf_status ensure_grad_rows(gpf_grid* g, hipStream_t s) {
   return GPF_OK;
 }
 
-gpf_status launch_grad_finalize(gpf_grid* g, gpf_field_grad* grad, hipStream_t s) {
+gpf_status launch_grad_finalize(gpf_grid* g, float4* rows, gpf_field_grad* grad, hipStream_t s) {
   hipLaunchKernelGGL(grad_finalize_kernel, dim3((unsigned)((g->n + 255) / 256)), dim3(256), 0, s,
-                     g->grad_rows, (int)g->n, g->rec, g->quat, g->log_scale, grad->mu,
+                     rows, (int)g->n, g->rec, g->quat, g->log_scale, grad->mu,
                      grad->quat, grad->log_scale, grad->rgb);
   GPF_HIP(hipGetLastError());
   return GPF_OK;
 }
 
-gpf_status launch_eval_bwd(const gpf_grid* gc, const float* dL, gpf_field_grad* grad,
-                           hipStream_t s) {
-  gpf_grid* g = const_cast<gpf_grid*>(gc);  // scratch rows live in the handle
+// The backward into gradient rows `rows` ([n][4] float4, zero on entry; the
+// finalize pass leaves them zero again).
+static gpf_status launch_eval_bwd_rows(gpf_grid* g, const float* dL, gpf_field_grad* grad,
+                                       float4* rows, hipStream_t s) {
   const gpf_queries* qs = g->qs;
   const float c2 = (float)(kKappa2 * g->cutoff * g->cutoff);
-  gpf_status st = ensure_grad_rows(g, s);
-  if (st != GPF_OK) return st;
   hipLaunchKernelGGL(eval_bwd_kernel, dim3(xcd_grid((qs->ngroups + kBwdWaves - 1) / kBwdWaves)),
                      dim3(kBwdThreads), 0, s, qs->xs,
                      qs->perm, qs->groups, (int)qs->ngroups,
                      qs->tile_lo, qs->tile_hi, g->cell_start, g->cell_prims, g->rec, c2, dL,
-                     (float*)g->grad_rows, g->surv_ready ? g->surv : nullptr,
+                     (float*)rows, g->surv_ready ? g->surv : nullptr,
                      g->surv_ready ? g->surv_count : nullptr);
-  return launch_grad_finalize(g, grad, s);
+  GPF_HIP(hipGetLastError());
+  return launch_grad_finalize(g, rows, grad, s);
+}
+
+gpf_status launch_eval_bwd(const gpf_grid* gc, const float* dL, gpf_field_grad* grad,
+                           hipStream_t s) {
+  gpf_grid* g = const_cast<gpf_grid*>(gc);  // scratch rows live in the handle
+  gpf_status st = ensure_grad_rows(g, s);
+  if (st != GPF_OK) return st;
+  return launch_eval_bwd_rows(g, dL, grad, g->grad_rows, s);
+}
+
+// Device address of `scratch`, looked up once per device (with that device
+// current) and kept; hipGetSymbolAddress allocates nothing.
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_addr[kMaxDevices] = {};
+
+static gpf_status scratch_rows(float4** rows) {
+  int dev = 0;
+  GPF_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices)
+    return set_error(GPF_ERR_CAPACITY, "device ordinal beyond the library's per-device table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!p) return set_error(GPF_ERR_HIP, "hipGetSymbolAddress(scratch) returned NULL");
+    g_scratch_addr[dev] = p;
+  }
+  *rows = static_cast<float4*>(g_scratch_addr[dev]);
+  return GPF_OK;
+}
+
+gpf_status launch_eval_bwd_noalloc(const gpf_grid* gc, const float* dL, gpf_field_grad* grad,
+                                   hipStream_t s) {
+  gpf_grid* g = const_cast<gpf_grid*>(gc);
+  if (g->n > kNoAllocMaxPrims)
+    return set_error(GPF_ERR_CAPACITY, "the allocation-free backward takes at most " +
+                                           std::to_string(kNoAllocMaxPrims) + " primitives, got " +
+                                           std::to_string(g->n));
+  float4* rows = nullptr;
+  gpf_status st = scratch_rows(&rows);
+  if (st != GPF_OK) return st;
+  // the array keeps whatever the last call on this device left: clear the
+  // rows this call gathers into (a fill kernel, no memset node)
+  const int64_t n4 = g->n * 4;
+  hipLaunchKernelGGL(zero_float4_kernel, dim3((unsigned)((n4 + 255) / 256)), dim3(256), 0, s, rows,
+                     n4);
+  GPF_HIP(hipGetLastError());
+  return launch_eval_bwd_rows(g, dL, grad, rows, s);
 }
 
 gpf_status launch_count_pairs(const gpf_grid* g, unsigned long long* d_count, hipStream_t s) {

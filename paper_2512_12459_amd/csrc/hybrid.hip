@@ -679,7 +679,7 @@ gpf_status launch_hybrid_bwd(const gpf_grid* gc, float eps, const float* L, cons
                      topup_reach2(g->ball), topup_rings(g), eps, L, Z, count, dL,
                      (float*)g->grad_rows);
   GPF_HIP(hipGetLastError());
-  return launch_grad_finalize(g, grad, s);
+  return launch_grad_finalize(g, g->grad_rows, grad, s);
 }
 
 }  // namespace gpf
