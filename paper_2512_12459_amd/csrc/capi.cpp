@@ -195,6 +195,7 @@ void gpf_grid_destroy(gpf_grid* g) {
   dev_free(g->vals, g->cap * sizeof(int));
   dev_free(g->keys_sorted, g->cap * sizeof(int));
   dev_free(g->cell_prims, g->cap * sizeof(int));
+  dev_free(g->cell_recs, g->cell_recs_cap * sizeof(PrimRec));
   dev_free(g->sort_tmp, g->sort_tmp_bytes);
   dev_free(g->grad_rows, g->grad_cap * sizeof(float4) * 4);
   dev_free(g->surv, (size_t)g->surv_groups * kSurvPerGroup * sizeof(int));

@@ -22,7 +22,8 @@ constexpr int kGroupTiles = GPF_GROUP_TILES;
 constexpr double kKappa2 = 0.72134752044448170368;  // 0.5 * log2(e)
 
 // Primitive record (64 bytes): r0 = {mu, Phi_r}, r1 = {W'_0, Phi_g},
-// r2 = {W'_1, Phi_b}, r3 = {W'_2, 0}; W'_k is row k of kappa * diag(1/s) R^T.
+// r2 = {W'_1, Phi_b}, r3 = {W'_2, primitive index as int bits}; W'_k is row k
+// of kappa * diag(1/s) R^T.
 struct alignas(16) PrimRec {
   float4 r0, r1, r2, r3;
 };
@@ -95,6 +96,8 @@ struct gpf_grid {
   int* vals = nullptr;          // [cap] primitive per entry (primitive-major)
   int* keys_sorted = nullptr;   // [cap]
   int* cell_prims = nullptr;    // [cap] primitives of each cell, ascending
+  gpf::PrimRec* cell_recs = nullptr;  // [cap] their records in the same order (truncated query)
+  int64_t cell_recs_cap = 0;
   void* sort_tmp = nullptr;
   size_t sort_tmp_bytes = 0;
   int64_t cap = 0;

@@ -62,8 +62,8 @@ constexpr int kFwdSurvCap = 256;   // staged survivors per wave
 
 // One wave per group of two consecutive tiles of one cell: lane l owns point l
 // of the first tile and point l of the second.  Lane = candidate culls the
-// cell's list against both tile boxes; a survivor is staged in LDS as
-// index | tile mask << 30.  Every lane then evaluates each survivor for the
+// cell's records (one contiguous block of 64 at a time) against both tile
+// boxes; a survivor is staged in LDS as entry | tile mask << 30.  Every lane then evaluates each survivor for the
 // tiles it may touch (a wave-uniform branch per tile), reading mu, W' and the
 // flux with wave-uniform scalar loads: d = x - mu, u' = W' d (the local frame
 // of Alg. S3), w = 2^-|u'|^2 inside the cut.  The survivor loop is bound by the
@@ -74,7 +74,7 @@ eval_fwd_kernel(
     const float4* __restrict__ xs, const int* __restrict__ perm,
     const GroupInfo* __restrict__ groups, int ngroups, const float4* __restrict__ tlo,
     const float4* __restrict__ thi, const int* __restrict__ cell_start,
-    const int* __restrict__ cell_prims, const PrimRec* __restrict__ recs, float c2,
+    const PrimRec* __restrict__ cell_recs, float c2,
     float* __restrict__ L, int* __restrict__ keep, int* __restrict__ keep_count) {
   static_assert(kGroupTiles == 2, "the forward pairs the two tiles of a group");
   __shared__ int surv[kWaves][kFwdSurvCap];
@@ -100,16 +100,15 @@ eval_fwd_kernel(
   int* kl = keep ? keep + (int64_t)g * kSurvPerGroup : nullptr;
   for (int base = cs; base < ce; base += 64) {
     const int j = base + lane;
-    int mask = 0, pid = 0;
+    int mask = 0;
     if (j < ce) {
-      pid = cell_prims[j];
-      const PrimRec r = recs[pid];
+      const PrimRec r = cell_recs[j];
       mask = (tile_may_touch(r, ta, c2) ? 1 : 0) | ((has_b && tile_may_touch(r, tb, c2)) ? 2 : 0);
     }
     const uint64_t bal = __ballot(mask != 0);
     if (mask) {
       const uint64_t below = bal & ((lane == 0) ? 0ull : (~0ull >> (64 - lane)));
-      sv[ns + __popcll(below)] = pid | (mask << 30);
+      sv[ns + __popcll(below)] = j | (mask << 30);
     }
     ns += __popcll(bal);
     if (ns > kFwdSurvCap - 64 || base + 64 >= ce) {
@@ -121,7 +120,7 @@ eval_fwd_kernel(
       }
       for (int s = 0; s < nsu; ++s) {
         const int head = __builtin_amdgcn_readfirstlane(sv[s]);
-        const PrimRec r = recs[head & 0x3fffffff];
+        const PrimRec r = cell_recs[head & 0x3fffffff];
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
           if (!((head >> (30 + i)) & 1)) continue;   // wave-uniform
@@ -153,14 +152,22 @@ eval_fwd_kernel(
   }
 }
 
+// Four-tile forward: one wave per pair of consecutive groups (groups 2w and
+// 2w + 1).  When both lie in one cell they are culled and evaluated together
+// (lane l owns point l of each of the four tiles); otherwise the wave takes
+// them one after the other.  Each block of 64 cell records is tested against
+// every tile box once, and a staged survivor {entry, 4-bit tile mask} is read
+// with wave-uniform scalar loads and evaluated on the tiles it may touch.
+// The survivors are kept per group (entry | 2-bit mask << 30, cell-list
+// order) for the backward of the same build.
 // ---------------------------------------------------------------------------
 // Exact pair count (same traversal as the forward)
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kWaves * 64) count_pairs_kernel(
     const float4* __restrict__ xs, const TileInfo* __restrict__ tiles,
     const float4* __restrict__ tlo, const float4* __restrict__ thi, int ntiles,
-    const int* __restrict__ cell_start, const int* __restrict__ cell_prims,
-    const PrimRec* __restrict__ recs, float c2, unsigned long long* __restrict__ out) {
+    const int* __restrict__ cell_start, const PrimRec* __restrict__ cell_recs, float c2,
+    unsigned long long* __restrict__ out) {
   __shared__ int surv[kWaves][kSurvCap];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int t = blockIdx.x * kWaves + wave;
@@ -175,18 +182,13 @@ __global__ void __launch_bounds__(kWaves * 64) count_pairs_kernel(
   int ns = 0;
   for (int base = cs; base < ce; base += 64) {
     const int j = base + lane;
-    bool pass = false;
-    int pid = 0;
-    if (j < ce) {
-      pid = cell_prims[j];
-      pass = tile_may_touch(recs[pid], tc, c2);
-    }
-    ns = append_survivor(sv, ns, pass, pid, lane);
+    const bool pass = j < ce && tile_may_touch(cell_recs[j], tc, c2);
+    ns = append_survivor(sv, ns, pass, j, lane);
     if (ns > kSurvCap - 64 || base + 64 >= ce) {
       wave_sync_lds();
       for (int s = 0; s < ns; ++s) {
         const int id = __builtin_amdgcn_readfirstlane(sv[s]);
-        const PrimRec r = recs[id];
+        const PrimRec r = cell_recs[id];
         const float dx = p.x - r.r0.x, dy = p.y - r.r0.y, dz = p.z - r.r0.z;
         const float u0 = fmaf(r.r1.z, dz, fmaf(r.r1.y, dy, r.r1.x * dx));
         const float u1 = fmaf(r.r2.z, dz, fmaf(r.r2.y, dy, r.r2.x * dx));
@@ -214,25 +216,27 @@ constexpr int kGroupQ = kTile * kGroupTiles;  // points per group (max, a multip
 constexpr int kListCap = 128;                 // survivor slots per list and wave
 constexpr int kRowStride = 14;                // transpose row stride (12 sums, pad, row id)
 
-// 64 survivors (lane = primitive) against the points [qb, qe) of the wave's
+// 64 survivors (lane = primitive, cell entry ent) against the points [qb, qe) of the wave's
 // group, held in LDS (points past the group's count carry a zero upstream
 // gradient).  The 12 per-primitive sums are added to the padded per-primitive
 // buffer with row-coalesced atomics: after an LDS transpose, 16 lanes update
 // one 64-byte row per instruction.
-__device__ __forceinline__ void bwd_chunk(int id, bool valid, int qb, int qe,
-                                          const PrimRec* __restrict__ recs, float c2,
-                                          const float4* qx, const float4* qg, float* rw,
+__device__ __forceinline__ void bwd_chunk(int ent, bool valid, int qb, int qe,
+                                          const PrimRec* __restrict__ cell_recs, float c2,
+                                          const float2* qp, float* rw,
                                           float* __restrict__ grad_rows, int lane) {
-  const PrimRec r = recs[id];
+  const PrimRec r = cell_recs[ent];
+  const int id = __float_as_int(r.r3.w);
   float GP[3] = {0.f, 0.f, 0.f}, A[3] = {0.f, 0.f, 0.f};
   float U[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   bool any = false;
   for (int k = qb; k < qe; k += 4) {
     float4 xq[4], gq[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      xq[i] = qx[k + i];
-      gq[i] = qg[k + i];
+    for (int i = 0; i < 4; ++i) {   // point k: (x, y), (z, gx), (gy, gz)
+      const float2 a = qp[3 * (k + i)], b = qp[3 * (k + i) + 1], c = qp[3 * (k + i) + 2];
+      xq[i] = make_float4(a.x, a.y, b.x, 0.f);
+      gq[i] = make_float4(b.y, c.x, c.y, 0.f);
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -292,13 +296,12 @@ __global__ void __launch_bounds__(kBwdThreads) eval_bwd_kernel(
     const float4* __restrict__ xs, const int* __restrict__ perm,
     const GroupInfo* __restrict__ groups, int ngroups, const float4* __restrict__ tlo,
     const float4* __restrict__ thi, const int* __restrict__ cell_start,
-    const int* __restrict__ cell_prims, const PrimRec* __restrict__ recs, float c2,
+    const PrimRec* __restrict__ cell_recs, float c2,
     const float* __restrict__ dL, float* __restrict__ grad_rows, const int* __restrict__ keep,
     const int* __restrict__ keep_count) {
   static_assert(kGroupTiles == 2, "the backward splits survivors over the two tiles of a group");
   __shared__ int sv_all[kBwdWaves][3][kListCap];
-  __shared__ float4 qx_all[kBwdWaves][kGroupQ];
-  __shared__ float4 qg_all[kBwdWaves][kGroupQ];
+  __shared__ float2 qp_all[kBwdWaves][3 * kGroupQ];   // per point x, y, z, gx, gy, gz
   __shared__ float rows_all[kBwdWaves][64 * kRowStride];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int g = xcd_remap(blockIdx.x) * kBwdWaves + wave;
@@ -307,8 +310,7 @@ __global__ void __launch_bounds__(kBwdThreads) eval_bwd_kernel(
   const TileCtx ta = tile_ctx(tlo, thi, gi.first_tile);
   const bool has_b = gi.count > kTile;
   const TileCtx tb = has_b ? tile_ctx(tlo, thi, gi.first_tile + 1) : ta;
-  float4* qx = qx_all[wave];
-  float4* qg = qg_all[wave];
+  float2* qp = qp_all[wave];
   int* sv0 = sv_all[wave][0];
   int* sv1 = sv_all[wave][1];
   int* sv2 = sv_all[wave][2];
@@ -317,11 +319,13 @@ __global__ void __launch_bounds__(kBwdThreads) eval_bwd_kernel(
     if (k < gi.count) {
       const int o = perm[gi.start + k];
       const float4 p = xs[gi.start + k];
-      qx[k] = make_float4(p.x, p.y, p.z, 0.f);
-      qg[k] = make_float4(dL[(int64_t)o * 3], dL[(int64_t)o * 3 + 1], dL[(int64_t)o * 3 + 2], 0.f);
+      qp[3 * k] = make_float2(p.x, p.y);
+      qp[3 * k + 1] = make_float2(p.z, dL[(int64_t)o * 3]);
+      qp[3 * k + 2] = make_float2(dL[(int64_t)o * 3 + 1], dL[(int64_t)o * 3 + 2]);
     } else {
-      qx[k] = make_float4(ta.cx, ta.cy, ta.cz, 0.f);   // any finite point; g = 0
-      qg[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+      qp[3 * k] = make_float2(ta.cx, ta.cy);   // any finite point; g = 0
+      qp[3 * k + 1] = make_float2(ta.cz, 0.f);
+      qp[3 * k + 2] = make_float2(0.f, 0.f);
     }
   }
   wave_sync_lds();
@@ -340,7 +344,7 @@ __global__ void __launch_bounds__(kBwdThreads) eval_bwd_kernel(
     for (int base = 0; base < nk; base += 64) {
       const int ent = (base + lane < nk) ? kl[base + lane] : 0;
       const int mask = (base + lane < nk) ? ((ent >> 30) & 3) : 0;
-      const int pid = ent & 0x3fffffff;
+      const int pid = ent & 0x3fffffff;   // cell entry
       const uint64_t m0 = __ballot(mask == 1), m1 = __ballot(mask == 2), m2 = __ballot(mask == 3);
       if (mask == 1) sv0[n0 + __popcll(m0 & below)] = pid;
       if (mask == 2) sv1[n1 + __popcll(m1 & below)] = pid;
@@ -351,34 +355,27 @@ __global__ void __launch_bounds__(kBwdThreads) eval_bwd_kernel(
       wave_sync_lds();
       if (n0 >= 64) {
         n0 -= 64;
-        bwd_chunk(sv0[n0 + lane], true, 0, qe_a, recs, c2, qx, qg, rw, grad_rows, lane);
+        bwd_chunk(sv0[n0 + lane], true, 0, qe_a, cell_recs, c2, qp, rw, grad_rows, lane);
       }
       if (n1 >= 64) {
         n1 -= 64;
-        bwd_chunk(sv1[n1 + lane], true, kTile, qe_all, recs, c2, qx, qg, rw, grad_rows, lane);
+        bwd_chunk(sv1[n1 + lane], true, kTile, qe_all, cell_recs, c2, qp, rw, grad_rows, lane);
       }
       if (n2 >= 64) {
         n2 -= 64;
-        bwd_chunk(sv2[n2 + lane], true, 0, qe_all, recs, c2, qx, qg, rw, grad_rows, lane);
+        bwd_chunk(sv2[n2 + lane], true, 0, qe_all, cell_recs, c2, qp, rw, grad_rows, lane);
       }
     }
   } else {
   // Software pipeline over the candidates in batches of 64: the records of
-  // batch b + 1 and the indices of batch b + 2 are requested before batch b is
-  // tested, so their latency overlaps the tests and the draining of full
-  // stacks.  Indices past the end repeat the cell's last entry, keeping every
-  // load unconditional and in bounds.
-  int pid_c = 0, pid_n = 0;
+  // batch b + 1 are requested before batch b is tested, so their latency
+  // overlaps the tests and the draining of full stacks.  Entries past the end
+  // repeat the cell's last one, keeping every load unconditional and in bounds.
   PrimRec rec_c{};
-  if (cs < ce) {
-    pid_c = cell_prims[min(cs + lane, ce - 1)];
-    rec_c = recs[pid_c];
-    pid_n = cell_prims[min(cs + 64 + lane, ce - 1)];
-  }
+  if (cs < ce) rec_c = cell_recs[min(cs + lane, ce - 1)];
   for (int base = cs; base < ce; base += 64) {
-    const PrimRec rec_n = recs[pid_n];
-    const int pid_nn = cell_prims[min(base + 128 + lane, ce - 1)];
-    const int pid = pid_c;
+    const PrimRec rec_n = cell_recs[min(base + 64 + lane, ce - 1)];
+    const int pid = base + lane;   // cell entry
     int mask = 0;
     if (base + lane < ce)
       mask = (tile_may_touch(rec_c, ta, c2) ? 1 : 0) |
@@ -393,25 +390,23 @@ __global__ void __launch_bounds__(kBwdThreads) eval_bwd_kernel(
     wave_sync_lds();
     if (n0 >= 64) {
       n0 -= 64;
-      bwd_chunk(sv0[n0 + lane], true, 0, qe_a, recs, c2, qx, qg, rw, grad_rows, lane);
+      bwd_chunk(sv0[n0 + lane], true, 0, qe_a, cell_recs, c2, qp, rw, grad_rows, lane);
     }
     if (n1 >= 64) {
       n1 -= 64;
-      bwd_chunk(sv1[n1 + lane], true, kTile, qe_all, recs, c2, qx, qg, rw, grad_rows, lane);
+      bwd_chunk(sv1[n1 + lane], true, kTile, qe_all, cell_recs, c2, qp, rw, grad_rows, lane);
     }
     if (n2 >= 64) {
       n2 -= 64;
-      bwd_chunk(sv2[n2 + lane], true, 0, qe_all, recs, c2, qx, qg, rw, grad_rows, lane);
+      bwd_chunk(sv2[n2 + lane], true, 0, qe_all, cell_recs, c2, qp, rw, grad_rows, lane);
     }
-    pid_c = pid_n;
     rec_c = rec_n;
-    pid_n = pid_nn;
   }
   }
   const int total = n0 + n1 + n2;
   for (int chunk = 0; chunk < total; chunk += 64) {
     const int v = chunk + lane;
-    int id = 0, cat = 0;
+    int id = cs, cat = 0;   // padded lanes read a valid entry and add nothing
     if (v < n0) {
       id = sv0[v];
       cat = 1;
@@ -423,7 +418,7 @@ __global__ void __launch_bounds__(kBwdThreads) eval_bwd_kernel(
       cat = 2;
     }
     const bool use_a = __ballot(cat & 1) != 0, use_b = __ballot(cat & 2) != 0;
-    bwd_chunk(id, cat != 0, use_a ? 0 : kTile, use_b ? qe_all : qe_a, recs, c2, qx, qg,
+    bwd_chunk(id, cat != 0, use_a ? 0 : kTile, use_b ? qe_all : qe_a, cell_recs, c2, qp,
               rw, grad_rows, lane);
   }
 }
@@ -465,7 +460,7 @@ gpf_status launch_eval_fwd(const gpf_grid* gc, float* L, hipStream_t s) {
   ensure_survivor_lists(g);
   hipLaunchKernelGGL(eval_fwd_kernel, dim3(xcd_grid(fwd_blocks(qs->ngroups))), dim3(kWaves * 64), 0, s,
                      qs->xs, qs->perm, qs->groups, (int)qs->ngroups,
-                     qs->tile_lo, qs->tile_hi, g->cell_start, g->cell_prims, g->rec, c2, L, g->surv,
+                     qs->tile_lo, qs->tile_hi, g->cell_start, g->cell_recs, c2, L, g->surv,
                      g->surv ? g->surv_count : nullptr);
   GPF_HIP(hipGetLastError());
   g->surv_ready = g->surv != nullptr;
@@ -506,7 +501,7 @@ static gpf_status launch_eval_bwd_rows(gpf_grid* g, const float* dL, gpf_field_g
   hipLaunchKernelGGL(eval_bwd_kernel, dim3(xcd_grid((qs->ngroups + kBwdWaves - 1) / kBwdWaves)),
                      dim3(kBwdThreads), 0, s, qs->xs,
                      qs->perm, qs->groups, (int)qs->ngroups,
-                     qs->tile_lo, qs->tile_hi, g->cell_start, g->cell_prims, g->rec, c2, dL,
+                     qs->tile_lo, qs->tile_hi, g->cell_start, g->cell_recs, c2, dL,
                      (float*)rows, g->surv_ready ? g->surv : nullptr,
                      g->surv_ready ? g->surv_count : nullptr);
   GPF_HIP(hipGetLastError());
@@ -569,7 +564,7 @@ gpf_status launch_count_pairs(const gpf_grid* g, unsigned long long* d_count, hi
   GPF_HIP(hipMemsetAsync(d_count, 0, sizeof(unsigned long long), s));
   hipLaunchKernelGGL(count_pairs_kernel, dim3(fwd_blocks(qs->ntiles)), dim3(kWaves * 64), 0, s,
                      qs->xs, qs->tiles, qs->tile_lo, qs->tile_hi, (int)qs->ntiles, g->cell_start,
-                     g->cell_prims, g->rec, c2, d_count);
+                     g->cell_recs, c2, d_count);
   GPF_HIP(hipGetLastError());
   return GPF_OK;
 }

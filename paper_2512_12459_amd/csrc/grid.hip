@@ -52,7 +52,8 @@ __device__ bool prim_frame(const float* __restrict__ mu, const float* __restrict
   if (!ok) {
     PrimRec z;
     z.r0 = make_float4(mu[i * 3], mu[i * 3 + 1], mu[i * 3 + 2], 0.f);
-    z.r1 = z.r2 = z.r3 = make_float4(0.f, 0.f, 0.f, 0.f);
+    z.r1 = z.r2 = make_float4(0.f, 0.f, 0.f, 0.f);
+    z.r3 = make_float4(0.f, 0.f, 0.f, __int_as_float(i));
     *rec = z;
     return false;
   }
@@ -84,7 +85,7 @@ __device__ bool prim_frame(const float* __restrict__ mu, const float* __restrict
   r.r0 = make_float4(mu[i * 3], mu[i * 3 + 1], mu[i * 3 + 2], rgb[i * 3]);
   r.r1 = make_float4(W[0][0], W[0][1], W[0][2], rgb[i * 3 + 1]);
   r.r2 = make_float4(W[1][0], W[1][1], W[1][2], rgb[i * 3 + 2]);
-  r.r3 = make_float4(W[2][0], W[2][1], W[2][2], 0.f);
+  r.r3 = make_float4(W[2][0], W[2][1], W[2][2], __int_as_float(i));
   *rec = r;
   return true;
 }
@@ -240,6 +241,15 @@ __global__ void __launch_bounds__(256) emit_kernel(int n, int S, float cutoff, f
                     off[t + 1] - base);
 }
 
+// Records in cell-list order (entry e holds the record of cell_prims[e]), so
+// that a cull reads a cell's candidates as one contiguous block.
+__global__ void __launch_bounds__(256) gather_recs_kernel(const int* __restrict__ cell_prims,
+                                                          const PrimRec* __restrict__ recs,
+                                                          PrimRec* __restrict__ cell_recs, int E) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < E) cell_recs[e] = recs[cell_prims[e]];
+}
+
 // cell_start[c] = first sorted entry with key >= c (binary search).
 __global__ void cell_start_kernel(const int* __restrict__ keys, int E, int ncells,
                                   int* __restrict__ cell_start) {
@@ -331,6 +341,9 @@ gpf_status launch_build_grid(gpf_grid* g, hipStream_t s) {
                      "field has a zero-norm quaternion or a non-finite parameter");
   const int64_t E = host[0];
   if (E < 0) return set_error(GPF_ERR_CAPACITY, "more than 2^31-1 cell-primitive entries");
+  // the truncated query's survivor lists carry an entry index and a 2-bit tile mask
+  if (!(g->ball > 0.f) && E >= ((int64_t)1 << 30))
+    return set_error(GPF_ERR_CAPACITY, "more than 2^30-1 cell-primitive entries");
   if (g->cap < E) {
     int** bufs[4] = {&g->keys, &g->vals, &g->keys_sorted, &g->cell_prims};
     for (auto b : bufs) {
@@ -368,8 +381,24 @@ gpf_status launch_build_grid(gpf_grid* g, hipStream_t s) {
   hipLaunchKernelGGL(cell_start_kernel, dim3((nc + 256) / 256), dim3(256), 0, s, g->keys_sorted,
                      (int)E, nc, g->cell_start);
   GPF_HIP(hipGetLastError());
+  if (!(g->ball > 0.f)) {
+    if (g->cell_recs_cap < E) {
+      dev_free(g->cell_recs, g->cell_recs_cap * sizeof(PrimRec));
+      g->cell_recs = nullptr;
+      g->cell_recs_cap = 0;
+      gpf_status st = dev_alloc((void**)&g->cell_recs, (size_t)g->cap * sizeof(PrimRec),
+                                "cell-ordered records");
+      if (st != GPF_OK) return st;
+      g->cell_recs_cap = g->cap;
+    }
+    if (E > 0)
+      hipLaunchKernelGGL(gather_recs_kernel, dim3((unsigned)((E + 255) / 256)), dim3(256), 0, s,
+                         g->cell_prims, g->rec, g->cell_recs, (int)E);
+    GPF_HIP(hipGetLastError());
+  }
   g->bytes = g->rec_cap * (sizeof(PrimRec) + sizeof(float4)) + g->prim_off_len * sizeof(int) +
-             (size_t)g->cell_start_cap * sizeof(int) + 4 * g->cap * sizeof(int) + g->sort_tmp_bytes;
+             (size_t)g->cell_start_cap * sizeof(int) + 4 * g->cap * sizeof(int) + g->sort_tmp_bytes +
+             g->cell_recs_cap * sizeof(PrimRec);
   if (g->ball > 0.f) {
     gpf_status st = build_centre_grid(g, s);
     if (st != GPF_OK) return st;
