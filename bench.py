@@ -7,7 +7,9 @@ radiance query (gradients to every primitive parameter) and an Adam update.
 Default workload: 1,000,000 Gaussians (20% in one caustic cluster under the
 sphere, the rest on the five walls), 32 views at 800x800 = 20,480,000 query
 points, FP32.  Targets are the radiance of a second field (seed 1) rendered
-once before timing.  Prints one JSON line.
+once before timing.  ``--workload fit200k`` fits the seed-2 perturbation of a
+200,000-Gaussian seed-1 field to that field's radiance at 8 views of 512x512.
+Prints one JSON line.
 
 ``--workload sppm`` instead times one progressive photon-mapping iteration per
 step: trace 100,000 photon paths, compact the stored photons, bin them, and
@@ -398,7 +400,13 @@ def main():
     torch.cuda.set_device(0)
     t0 = time.perf_counter()
     field, x = S.workload(args.workload, views=args.views, res=args.res)
-    gt, _ = S.workload(args.workload, views=1, res=8, seed=1)
+    if args.workload == "fit200k":
+        # the fitting step as configured: targets from the hidden seed-1 field,
+        # parameters starting from its seed-2 perturbation
+        gt = field
+        field = S.perturb_field(gt, 2)
+    else:
+        gt, _ = S.workload(args.workload, views=1, res=8, seed=1)
     log(f"workload {args.workload}: n={field.n} q={x.shape[0]} ({time.perf_counter() - t0:.1f} s)")
     q = x.shape[0]
     n = field.n

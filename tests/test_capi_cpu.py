@@ -32,8 +32,8 @@ def test_library_exports_every_declared_symbol():
     assert set(names) <= set(C.exported_symbols())
 
 
-def test_host_validation_without_device_work():
-    L = C.lib()
+def check_host_validation(L):
+    """Bad arguments of the radiance entry points are rejected on the host."""
     h = ctypes.c_void_p()
     assert L.gpf_bin_queries(None, 10, 0.1, None, ctypes.byref(h)) == 1
     assert b"NULL" in L.gpf_last_error()
@@ -54,13 +54,41 @@ def test_host_validation_without_device_work():
     assert L.gpf_rebin_queries(None, fake, 10, 0.1, None) == 1
     q = ctypes.c_int64()
     assert L.gpf_queries_info(None, ctypes.byref(q), None, None, None) == 1
+    assert L.gpf_eval_radiance_backward_noalloc(None, ctypes.byref(f), fake, 5, fake, None,
+                                                None) == 1
     L.gpf_queries_destroy(None)
     L.gpf_grid_destroy(None)
     assert L.gpf_version().startswith(b"gpf")
 
 
-def test_photon_and_camera_validation_without_device_work():
-    L = C.lib()
+def check_init_validation(L):
+    """Bad arguments of the photon kNN, the network and the initialisation are
+    rejected on the host."""
+    fake = ctypes.c_void_p(0x1000)
+    assert L.gpf_photon_knn(None, 100, 16, fake, fake, None) == 1
+    assert L.gpf_photon_knn(fake, 100, 2, fake, fake, None) == 1
+    assert L.gpf_photon_knn(fake, 100, 33, fake, fake, None) == 1
+    assert L.gpf_photon_knn(fake, 10, 16, fake, fake, None) == 1
+    assert L.gpf_photon_knn(fake, (1 << 28) + 1, 16, fake, fake, None) == 3
+    assert L.gpf_mlp_create(None) == 1
+    assert L.gpf_mlp_set_params(None, fake) == 1
+    assert L.gpf_mlp_get_params(None, fake) == 1
+    assert L.gpf_mlp_forward(None, fake, 8, fake, None) == 1
+    assert L.gpf_mlp_forward(fake, fake, 0, fake, None) == 1
+    assert L.gpf_mlp_gradient(None, fake, fake, 8, fake, None, None) == 1
+    assert L.gpf_mlp_train_step(None, fake, fake, 8, 1e-3, None, None) == 1
+    assert L.gpf_mlp_num_params() == 96 * 128 + 128 + 128 * 128 + 128 + 128 * 10 + 10
+    L.gpf_mlp_destroy(None)
+
+
+def test_host_validation_without_device_work():
+    check_host_validation(C.lib())
+    check_init_validation(C.lib())
+
+
+def check_photon_camera_validation(L):
+    """Bad arguments of the photon, photon-map and camera entry points are
+    rejected on the host."""
     fake = ctypes.c_void_p(0x1000)
     # photon tracing: path count, event count, light square, sphere kind, outputs
     for args in ((0, 1, 4, 0.4, 0.6, 1), (10, 1, 0, 0.4, 0.6, 1), (10, 1, 17, 0.4, 0.6, 1),
@@ -116,3 +144,7 @@ def test_photon_and_camera_validation_without_device_work():
     assert L.gpf_camera_compose(fake, 5, 1, None, fake, fake, 3, fake, None) == 1
     assert L.gpf_camera_compose_backward(fake, 0, 1, fake, fake, 3, fake, None) == 1
     assert L.gpf_camera_compose_backward(None, 5, 1, fake, fake, 3, fake, None) == 1
+
+
+def test_photon_and_camera_validation_without_device_work():
+    check_photon_camera_validation(C.lib())
