@@ -178,6 +178,108 @@ def mlp_backward(p, cache, dY, bf16=False):
     return g
 
 
+# ----------------------------------------------------------------------------
+# Error bounds of a bfloat16 / FP32 evaluation of the network, per element
+# ----------------------------------------------------------------------------
+EPS32 = 2.0 ** -24
+# GELU and its derivative evaluated in single precision (erf, exp to a few
+# units in the last place): absolute error at most this times (1 + |z|)
+GELU_EVAL = 8 * EPS32
+GELU2_MAX = 0.8     # max |gelu''(z)| (at z = 0: 2 phi(0) = 0.798)
+
+
+def _gamma(k):
+    """Worst-case relative error of a k-term FP32 sum (any order)."""
+    return k * EPS32 / (1.0 - k * EPS32)
+
+
+def bf16_spread(v, delta):
+    """Largest |bf16(v') - bf16(v)| over |v' - v| <= delta, per element: the
+    change of a rounded value when its unrounded value may move by delta
+    (a step to the neighbouring bfloat16 number, or more for large delta)."""
+    v = np.asarray(v, F64)
+    r0 = bf16_round(v)
+    return np.maximum(np.abs(bf16_round(v + delta) - r0), np.abs(bf16_round(v - delta) - r0))
+
+
+def _product_bound(A, dA, B, dB, k):
+    """Bound on |A'B' - AB| for matrices with |A' - A| <= dA, |B' - B| <= dB,
+    the product summed in FP32 over k terms."""
+    aA, aB = np.abs(A), np.abs(B)
+    return dA @ (aB + dB) + aA @ dB + _gamma(k) * ((aA + dA) @ (aB + dB))
+
+
+def mlp_forward_bounds(p, X, dX=None):
+    """(Y, dY, state): the network's output on bfloat16-rounded operands (as
+    mlp_forward with bf16=True) and, per output element, a bound on how far an
+    evaluation can land from it that uses the same bfloat16 inputs and
+    weights, sums each product in FP32 in any order, adds the FP32 biases,
+    evaluates GELU in FP32 and rounds the hidden activations to bfloat16 from
+    its own FP32 values (so a hidden value near a rounding boundary may take
+    the neighbouring bfloat16 number).  With dX, the evaluation's inputs are
+    its own roundings of values within dX of X (so an input may also take the
+    neighbouring bfloat16 number).  `state` holds the intermediate values and
+    bounds that mlp_gradient_bounds propagates."""
+    r = bf16_round
+    D0 = 0 * np.asarray(X, F64) if dX is None else bf16_spread(X, dX)
+    X = r(X)
+    W = [r(p["W1"]), r(p["W2"]), r(p["W3"])]
+    b = [np.asarray(p[k], F64) for k in ("b1", "b2", "b3")]
+    Z1 = X @ W[0] + b[0]
+    dZ1 = _product_bound(X, D0, W[0], 0 * W[0], X.shape[1] + 1) + _gamma(1) * np.abs(b[0])
+    H1 = gelu(Z1)
+    dH1 = np.abs(gelu_grad(Z1)) * dZ1 + 0.5 * GELU2_MAX * dZ1 ** 2 + GELU_EVAL * (1 + np.abs(Z1))
+    R1, D1 = r(H1), bf16_spread(H1, dH1)
+    Z2 = R1 @ W[1] + b[1]
+    dZ2 = _product_bound(R1, D1, W[1], 0 * W[1], W[1].shape[0] + 1) + _gamma(1) * np.abs(b[1])
+    H2 = gelu(Z2)
+    dH2 = np.abs(gelu_grad(Z2)) * dZ2 + 0.5 * GELU2_MAX * dZ2 ** 2 + GELU_EVAL * (1 + np.abs(Z2))
+    R2, D2 = r(H2), bf16_spread(H2, dH2)
+    Y = R2 @ W[2] + b[2]
+    dY = _product_bound(R2, D2, W[2], 0 * W[2], W[2].shape[0] + 1) + _gamma(1) * np.abs(Y)
+    state = dict(X=X, D0=D0, W=W, Z1=Z1, dZ1=dZ1, R1=R1, D1=D1, Z2=Z2, dZ2=dZ2, R2=R2, D2=D2)
+    return Y, dY, state
+
+
+def mlp_gradient_bounds(p, X, T):
+    """(g, dg): the gradient of mean((Y - T)^2) on bfloat16-rounded operands
+    (as mlp_backward with bf16=True: upstream gradients rounded to bfloat16
+    where they enter a product, bias gradients summed unrounded) and, per
+    parameter element, a bound on how far an evaluation of the kind described
+    in mlp_forward_bounds lands from it, its upstream gradient computed from
+    its own forward output."""
+    r = bf16_round
+    Y, dYb, st = mlp_forward_bounds(p, X)
+    T = np.asarray(T, F64)
+    n = Y.size
+    G = 2.0 * (Y - T) / n
+    dG = 2.0 / n * dYb + 4 * EPS32 * np.abs(G)
+    Gr, DG = r(G), bf16_spread(G, dG)
+    W1, W2, W3 = st["W"]
+    B = Y.shape[0]
+    g, dg = {}, {}
+    g["W3"] = st["R2"].T @ Gr
+    dg["W3"] = _product_bound(st["R2"].T, st["D2"].T, Gr, DG, B)
+    g["b3"] = G.sum(0)
+    dg["b3"] = dG.sum(0) + _gamma(B) * np.abs(G).sum(0)
+    back = (("2", W3, st["Z2"], st["dZ2"], st["R1"], st["D1"]),
+            ("1", W2, st["Z1"], st["dZ1"], st["X"], st["D0"]))
+    R, D = Gr, DG
+    for lay, Wn, Z, dZ, A, dA in back:
+        dH = R @ Wn.T
+        ddH = _product_bound(R, D, Wn.T, 0 * Wn.T, Wn.shape[1])
+        gp = gelu_grad(Z)
+        dgp = GELU2_MAX * dZ + GELU_EVAL * (1 + np.abs(Z))
+        dZu = dH * gp
+        ddZu = np.abs(gp) * ddH + (np.abs(dH) + ddH) * dgp + EPS32 * np.abs(dZu)
+        R, D = r(dZu), bf16_spread(dZu, ddZu)
+        g["W" + lay] = A.T @ R
+        dg["W" + lay] = _product_bound(A.T, dA.T, R, D, B)
+        g["b" + lay] = dZu.sum(0)
+        dg["b" + lay] = ddZu.sum(0) + _gamma(B) * np.abs(dZu).sum(0)
+    return g, dg
+
+
 def mlp_loss(Y, T):
     """Mean squared error over samples and outputs, and its gradient."""
     Y = np.asarray(Y, F64)

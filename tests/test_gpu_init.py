@@ -108,8 +108,13 @@ def test_mlp_forward(P, b):
     Xd, X = _rand_x(b, 5)
     Y = net.forward(Xd)
     torch.cuda.synchronize()
-    ref, _ = I.mlp_forward(p32, X, bf16=True)
-    y = Y.cpu().numpy()
+    ref, bound, _ = I.mlp_forward_bounds(p32, X)
+    y = Y.cpu().numpy().astype(np.float64)
+    # per element: within the bound of a bf16 / FP32 evaluation (oracle's interval analysis)
+    err = np.abs(y - ref)
+    assert np.all(err <= bound), float(np.max(err / bound))
+    say(f"  mlp forward: max |y - ref| / bound = {np.max(err / bound):.3g}, "
+        f"max |y - ref| / |ref| = {np.max(err / np.abs(ref)):.3g}")
     assert np.linalg.norm(y - ref) <= 2e-3 * np.linalg.norm(ref)
     ref64, _ = I.mlp_forward(p32, X, bf16=False)
     assert np.linalg.norm(y - ref64) <= 1e-2 * np.linalg.norm(ref64)
@@ -128,8 +133,13 @@ def test_mlp_gradient(P):
     Y, cache = I.mlp_forward(p32, X, bf16=True)
     loss, dY = I.mlp_loss(Y, T)
     ref = I.mlp_backward(p32, cache, dY, bf16=True)
+    gb, bound = I.mlp_gradient_bounds(p32, X, T)
     gg = _unflat(g.cpu().numpy())
     for k in ref:
+        np.testing.assert_allclose(gb[k], ref[k], rtol=1e-12, atol=1e-300)
+        err = np.abs(gg[k] - ref[k])
+        assert np.all(err <= bound[k]), (k, float(np.max(err / bound[k])))
+        say(f"  mlp gradient {k}: max err / bound = {np.max(err / bound[k]):.3g}")
         assert np.linalg.norm(gg[k] - ref[k]) <= 1e-2 * np.linalg.norm(ref[k]), k
     assert abs(ls.item() / (b * 10) - loss) <= 1e-3 * loss
 
@@ -183,11 +193,20 @@ def test_init_learned_matches_oracle(P):
     torch.cuda.synchronize()
     ref, o = I.learned_init(pos, power, p32, bf16=True)
     np.testing.assert_array_equal(mu.cpu().numpy(), pos)
-    # network outputs agree to ~2e-3 of their scale; the mapped parameters follow
-    sc = np.abs(o).max()
-    assert np.max(np.abs(ls.cpu().numpy() - ref["log_scale"])) <= 2e-2 * sc + 1e-5
-    assert np.max(np.abs(q.cpu().numpy() - ref["quat"])) <= 2e-2 * sc + 1e-5
-    assert np.max(np.abs(np.log(rgb.cpu().numpy() / ref["rgb"]))) <= 2e-2 * sc + 1e-5
+    # per photon and component: the network outputs' bound, carried through
+    # the parameter map (log-scale and log-flux add the outputs; the
+    # quaternion normalises (1,0,0,0) + o, which moves each component by at
+    # most 2 |do|_1 / |(1,0,0,0) + o|), plus FP32 rounding of the map
+    idx, d2 = I.knn(pos, 16)
+    feat = I.features(pos, power, idx, d2)
+    # the device computes the features in FP32 (a few roundings) before its bf16 rounding
+    _, ob, _ = I.mlp_forward_bounds(p32, feat, dX=8 * I.EPS32 * (np.abs(feat) + 1))
+    v = np.array([1.0, 0, 0, 0]) + o[:, 0:4]
+    qb = 2 * ob[:, 0:4].sum(1, keepdims=True) / np.linalg.norm(v, axis=1, keepdims=True)
+    tiny = 1e-5
+    assert np.all(np.abs(ls.cpu().numpy() - ref["log_scale"]) <= ob[:, 4:7] + tiny)
+    assert np.all(np.abs(q.cpu().numpy() - ref["quat"]) <= qb + tiny)
+    assert np.all(np.abs(np.log(rgb.cpu().numpy() / ref["rgb"])) <= ob[:, 7:10] + tiny)
 
 
 def test_targets_round_trip(P):

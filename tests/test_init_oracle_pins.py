@@ -131,3 +131,82 @@ def test_features_are_scale_free_and_ordered():
     np.testing.assert_array_equal(idx, idx2)
     f2 = I.features(pos * 4, power * 7, idx2, d22)
     np.testing.assert_allclose(f, f2, rtol=1e-5, atol=1e-6)
+
+
+# --------------------------------------------------------------------------
+# Per-element error bounds of a bfloat16 / FP32 evaluation of the network
+# --------------------------------------------------------------------------
+def _torch_bf16_net(p, X, T=None, drop=None):
+    """The network in torch float32 with bfloat16-rounded operands at the
+    kernels' rounding points (inputs, weights, hidden activations, upstream
+    gradients entering products); drop plants a mistake."""
+    import torch
+    bf = lambda a: torch.as_tensor(np.asarray(a, np.float32)).to(torch.bfloat16).to(torch.float32)
+    f32 = lambda a: torch.as_tensor(np.asarray(a, np.float32))
+    W1, W2, W3 = bf(p["W1"]), bf(p["W2"]), bf(p["W3"])
+    b1, b2, b3 = f32(p["b1"]), f32(p["b2"]), f32(p["b3"])
+    if drop == "b2":
+        b2 = 0 * b2
+    if drop == "b3":
+        b3 = 0 * b3
+    if drop == "swap":
+        W3 = W3[:, [1, 0] + list(range(2, W3.shape[1]))]
+    gelu = lambda z: torch.nn.functional.gelu(z)
+    Xb = bf(X)
+    Z1 = Xb @ W1 + b1
+    H1 = gelu(Z1).to(torch.bfloat16).to(torch.float32)
+    Z2 = H1 @ W2 + b2
+    H2 = gelu(Z2).to(torch.bfloat16).to(torch.float32)
+    Y = H2 @ W3 + b3
+    if T is None:
+        return Y.double().numpy()
+    G = 2.0 * (Y - f32(T)) / Y.numel()
+    gp = lambda z: 0.5 * (1 + torch.erf(z * 0.7071067811865476)) + z * torch.exp(-0.5 * z * z) * 0.3989422804014327
+    Gr = G.to(torch.bfloat16).to(torch.float32)
+    g = {"W3": H2.T @ Gr, "b3": G.sum(0)}
+    dZ2 = (Gr @ W3.T) * gp(Z2)
+    R = dZ2.to(torch.bfloat16).to(torch.float32)
+    g["W2"], g["b2"] = H1.T @ R, dZ2.sum(0)
+    dZ1 = (R @ W2.T) * gp(Z1)
+    R = dZ1.to(torch.bfloat16).to(torch.float32)
+    g["W1"], g["b1"] = Xb.T @ R, dZ1.sum(0)
+    return {k: v.double().numpy() for k, v in g.items()}
+
+
+def _net_case(seed, b=700):
+    rng = np.random.default_rng(seed)
+    p = I.mlp_init(seed)
+    p["W3"] = rng.normal(0, 0.1, p["W3"].shape)
+    for k in ("b1", "b2", "b3"):
+        p[k] = rng.normal(0, 0.1, p[k].shape)
+    p = {k: v.astype(np.float32).astype(np.float64) for k, v in p.items()}   # FP32 masters
+    return p, rng.normal(size=(b, 96)), rng.normal(0, 0.3, (b, 10))
+
+
+@pytest.mark.parametrize("seed", [31, 32])
+def test_mlp_forward_bounds_cover_a_bfloat16_float32_evaluation(seed):
+    p, X, _ = _net_case(seed)
+    ref, bound, _ = I.mlp_forward_bounds(p, X)
+    np.testing.assert_allclose(ref, I.mlp_forward(p, X, bf16=True)[0], rtol=1e-12, atol=1e-15)
+    Y = _torch_bf16_net(p, X)
+    err = np.abs(Y - ref)
+    assert np.all(err <= bound)                          # sufficient
+    assert np.median(bound / np.abs(ref)) < 0.05          # not vacuous
+    assert np.max(err / bound) > 1e-3                     # the evaluation uses the room
+    for drop in ("b3", "b2", "swap"):                     # planted mistakes exceed it
+        assert np.any(np.abs(_torch_bf16_net(p, X, drop=drop) - ref) > bound), drop
+
+
+def test_mlp_gradient_bounds_cover_a_bfloat16_float32_evaluation():
+    p, X, T = _net_case(33)
+    g, bound = I.mlp_gradient_bounds(p, X, T)
+    Y, cache = I.mlp_forward(p, X, bf16=True)
+    ref = I.mlp_backward(p, cache, I.mlp_loss(Y, T)[1], bf16=True)
+    emu = _torch_bf16_net(p, X, T)
+    for k in ref:
+        np.testing.assert_allclose(g[k], ref[k], rtol=1e-12, atol=1e-300)
+        assert np.all(np.abs(emu[k] - ref[k]) <= bound[k]), k
+    for k in ("W3", "b3", "W2", "b2"):
+        assert np.median(bound[k] / np.abs(ref[k])) < 0.2, k
+    bad = _torch_bf16_net(p, X, T, drop="b3")
+    assert any(np.any(np.abs(bad[k] - ref[k]) > bound[k]) for k in ref)
