@@ -7,17 +7,24 @@ photon per Gaussian, 32 ring views at 800x800 (20,480,000 points), target
 fields fitted by the library itself (seeds 100-299).
 
     python -m paper_2512_12459_amd.compare_init [--train-fields 200] [--views 32 --res 800]
+        [--seeds 7,8,9] [--dump DIR]
 
-Prints one JSON object.  Wall time of the learned run includes the kNN,
-features and network inference of the initialisation.
+Prints one JSON object (per ground-truth seed, and the mean and range over
+seeds).  Wall time of the learned run includes the kNN, features and network
+inference of the initialisation.  With --dump, each seed's target at 262,144
+sampled points (and their indices) and every fitted field are written to DIR
+as .npz files, for an independent check of the target and of the fits'
+PSNR.
 """
 from __future__ import annotations
 
 import argparse
 import json
+import os
 import sys
 import time
 
+import numpy as np
 import torch
 
 from . import learned_init as LI
@@ -34,13 +41,23 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+DUMP_SAMPLE = 262_144   # points of the target kept for an independent check
+
+
 def compare(net, workload="caustic1m", gt_seed=7, views=32, res=800, target_psnr=35.0,
-            max_steps=1500, check_every=10, cell=0.025, lr=None, query="truncated"):
+            max_steps=1500, check_every=10, cell=0.025, lr=None, query="truncated", dump=None):
     gt, x = S.workload(workload, views=views, res=res, seed=gt_seed)
     pos, power = S.photons_from_field(gt, gt_seed + 1)
     dev = "cuda"
     qs = R.QuerySet(torch.from_numpy(x).to(dev), cell)
     T = LI.render(qs, gt.arrays(), query=query)
+    if dump:
+        os.makedirs(dump, exist_ok=True)
+        sel = np.sort(np.random.default_rng(1000 + gt_seed).choice(
+            x.shape[0], min(DUMP_SAMPLE, x.shape[0]), replace=False))
+        np.savez(os.path.join(dump, f"target_seed{gt_seed}.npz"), sel=sel,
+                 T=T.cpu().numpy()[sel], T_max=float(T.max().item()), workload=workload,
+                 views=views, res=res, gt_seed=gt_seed, query=query)
     pd = torch.from_numpy(pos).to(dev)
     wd = torch.from_numpy(power).to(dev)
     out = {}
@@ -59,6 +76,10 @@ def compare(net, workload="caustic1m", gt_seed=7, views=32, res=800, target_psnr
             pairs0 = fitter.grid.build(*f.arrays()).count_pairs()
         res_ = fitter.run(max_steps, target_psnr, check_every, log=lambda s: log(f"[{name}] {s}"))
         hist = res_["history"]
+        if dump:
+            fp = f.numpy()
+            np.savez(os.path.join(dump, f"fit_seed{gt_seed}_{name}.npz"), steps=fitter.t,
+                     **{k: fp[k] for k in ("mu", "quat", "log_scale", "rgb")})
         # first check at or above each level (checks every `check_every` steps)
         levels = {}
         for lv in sorted(set(THRESHOLDS + (target_psnr,))):
@@ -94,6 +115,9 @@ def main():
     ap.add_argument("--save-weights", default=None)
     ap.add_argument("--check-every", type=int, default=1,
                     help="PSNR check cadence in steps (each check reads the step's loss back)")
+    ap.add_argument("--seeds", default="7", help="ground-truth seeds, comma separated")
+    ap.add_argument("--dump", default=None,
+                    help="directory for sampled targets and fitted fields (.npz)")
     a = ap.parse_args()
     torch.cuda.set_device(0)
     t0 = time.perf_counter()
@@ -113,10 +137,25 @@ def main():
                           epoch_mse=hist)
         if a.save_weights:
             LI.save(net, a.save_weights)
-    res = compare(net, a.workload, views=a.views, res=a.res, target_psnr=a.target,
-                  max_steps=a.max_steps, check_every=a.check_every, query=a.query)
-    res["training"] = train_info
-    print(json.dumps(res))
+    seeds = [int(v) for v in a.seeds.split(",")]
+    per_seed = {}
+    for sd in seeds:
+        per_seed[sd] = compare(net, a.workload, gt_seed=sd, views=a.views, res=a.res,
+                               target_psnr=a.target, max_steps=a.max_steps,
+                               check_every=a.check_every, query=a.query, dump=a.dump)
+    summary = {}
+    for name in ("plain", "learned"):
+        for key in ("steps_to_target", "seconds_to_target", "init_psnr"):
+            vals = [per_seed[sd]["runs"][name][key] for sd in seeds]
+            ok = [v for v in vals if v is not None]
+            summary[f"{name}_{key}"] = dict(values=vals, mean=float(np.mean(ok)) if ok else None,
+                                            min=min(ok) if ok else None, max=max(ok) if ok else None)
+    wins = [per_seed[sd]["runs"]["learned"]["seconds_to_target"] is not None and
+            (per_seed[sd]["runs"]["plain"]["seconds_to_target"] is None or
+             per_seed[sd]["runs"]["learned"]["seconds_to_target"] <
+             per_seed[sd]["runs"]["plain"]["seconds_to_target"]) for sd in seeds]
+    summary["learned_faster_on"] = f"{sum(wins)} of {len(seeds)} seeds"
+    print(json.dumps(dict(seeds=seeds, summary=summary, per_seed=per_seed, training=train_info)))
 
 
 if __name__ == "__main__":
