@@ -3,6 +3,8 @@
 A step is one fitting pass over the whole query set: grid rebuild for the
 current field, forward radiance query, MSE loss and its gradient, backward
 radiance query (gradients to every primitive parameter) and an Adam update.
+With the truncated query one kernel runs the forward, the loss and the
+backward group by group (``--separate`` times them as three launches).
 
 Default workload: 1,000,000 Gaussians (20% in one caustic cluster under the
 sphere, the rest on the five walls), 32 views at 800x800 = 20,480,000 query
@@ -358,6 +360,9 @@ def main():
                     help="hybrid ball radius r; gather radius of the sppm workload")
     ap.add_argument("--paths", type=int, default=100_000,
                     help="photon paths per iteration of the sppm workload")
+    ap.add_argument("--separate", action="store_true",
+                    help="truncated query: run forward, MSE and backward as three launches "
+                         "instead of the one-kernel fitting pass")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-exact-cull", type=int, default=0, metavar="POINTS",
                     help="also time the oracle's exact-cull FP64 forward on this many sampled "
@@ -455,37 +460,49 @@ def main():
     dL = torch.empty((q, 3), device=dev)
     loss = torch.zeros(1, dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream()
-    ev = {k: [] for k in ("build", "fwd", "loss", "bwd", "adam")}
+    fused = not hybrid and not args.separate
+    phases = ("build", "pass", "adam") if fused else ("build", "fwd", "loss", "bwd", "adam")
+    ev = {k: [] for k in phases}
 
     def step(t, timed):
         def mark():
             e = torch.cuda.Event(enable_timing=True)
             e.record(stream)
             return e
-        e0 = mark() if timed else None
+        marks = [mark()] if timed else []
         grid.build(mu, quat, ls, rgb)
-        e1 = mark() if timed else None
-        if hybrid:
-            fwd_out["L"], fwd_out["Z"], fwd_out["count"] = R.eval_hybrid(grid, mu, quat, ls, rgb)
-            Lh = fwd_out["L"]
-        else:
-            Lh = R.eval_radiance(grid, mu, quat, ls, rgb, out=L)
-        e2 = mark() if timed else None
-        loss.zero_()
-        R.mse_loss(Lh, T, dL=dL, loss_sum=loss)
-        G.zero_()
-        e3 = mark() if timed else None
-        if hybrid:
-            R.eval_hybrid_backward(grid, mu, quat, ls, rgb, Lh, fwd_out["Z"], fwd_out["count"],
-                                   dL, grads)
-        else:
-            R.eval_radiance_backward(grid, mu, quat, ls, rgb, dL, grads)
-        e4 = mark() if timed else None
-        R.adam_step(P, G, M, V, t, args.lr)
-        e5 = mark() if timed else None
         if timed:
-            for k, (a, b) in zip(ev, ((e0, e1), (e1, e2), (e2, e3), (e3, e4), (e4, e5))):
-                ev[k].append((a, b))
+            marks.append(mark())
+        if fused:
+            loss.zero_()
+            G.zero_()
+            R.fit_pass(grid, mu, quat, ls, rgb, T, L=L, loss_sum=loss, grads=grads)
+        else:
+            if hybrid:
+                fwd_out["L"], fwd_out["Z"], fwd_out["count"] = R.eval_hybrid(grid, mu, quat, ls,
+                                                                             rgb)
+                Lh = fwd_out["L"]
+            else:
+                Lh = R.eval_radiance(grid, mu, quat, ls, rgb, out=L)
+            if timed:
+                marks.append(mark())
+            loss.zero_()
+            R.mse_loss(Lh, T, dL=dL, loss_sum=loss)
+            G.zero_()
+            if timed:
+                marks.append(mark())
+            if hybrid:
+                R.eval_hybrid_backward(grid, mu, quat, ls, rgb, Lh, fwd_out["Z"],
+                                       fwd_out["count"], dL, grads)
+            else:
+                R.eval_radiance_backward(grid, mu, quat, ls, rgb, dL, grads)
+        if timed:
+            marks.append(mark())
+        R.adam_step(P, G, M, V, t, args.lr)
+        if timed:
+            marks.append(mark())
+            for k, e_a, e_b in zip(ev, marks[:-1], marks[1:]):
+                ev[k].append((e_a, e_b))
 
     for t in range(1, args.warmup + 1):
         step(t, False)
@@ -511,11 +528,15 @@ def main():
     step_ms = wall / args.steps * 1e3
     loss_v = loss.item() / q
     value = q / (step_ms * 1e-3)
-    fb_ms = ms["fwd"] + ms["bwd"]
-    dom = "bwd" if ms["bwd"] >= ms["fwd"] else "fwd"
     fl_fwd, fl_bwd = (FLOPS_FWD_HYBRID, FLOPS_BWD_HYBRID) if hybrid else (FLOPS_FWD, FLOPS_BWD)
-    flops = pairs * (fl_bwd if dom == "bwd" else fl_fwd)
-    achieved = flops / (ms[dom] * 1e-3)
+    if fused:   # one kernel runs forward, loss and backward
+        fb_ms, dom, kname, fl_pair = ms["pass"], "pass", "fit_pass", fl_fwd + fl_bwd
+    else:
+        fb_ms = ms["fwd"] + ms["bwd"]
+        dom = "bwd" if ms["bwd"] >= ms["fwd"] else "fwd"
+        kname = f"hybrid_{dom}" if hybrid else f"eval_{dom}"
+        fl_pair = fl_bwd if dom == "bwd" else fl_fwd
+    achieved = pairs * fl_pair / (ms[dom] * 1e-3)
     result = {
         "metric": f"fwd+bwd radiance queries/s @{n / 1e6:g}M Gaussians"
                   + (", hybrid query (ball r, top-up to 3 nearest, normalised)" if hybrid else ""),
@@ -533,7 +554,9 @@ def main():
         "config": {"query": args.query if not hybrid else f"hybrid r={args.radius} k_min=3 eps=1e-6",
                    "workload": f"{args.workload}: {n} Gaussians, {q} query points "
                                f"({args.views or 'default'} views, res {args.res or 'default'})",
-                   "step": "grid build + forward + MSE + backward + Adam",
+                   "step": ("grid build + fitting pass (forward, MSE, backward in one kernel) "
+                            "+ Adam") if fused else
+                           "grid build + forward + MSE + backward + Adam",
                    "cell": args.cell},
         "fwd_bwd_queries_per_s": q / (fb_ms * 1e-3),
         "kernel_ms": ms,
@@ -542,18 +565,18 @@ def main():
         "loss": loss_v,
         "device_bytes": {"queries": qinfo["device_bytes"], "grid": ginfo["device_bytes"],
                          "torch_peak": torch.cuda.max_memory_allocated()},
-        "roofline": {"bound": "alu", "kernel": (f"hybrid_{dom}" if hybrid else f"eval_{dom}"),
+        "roofline": {"bound": "alu", "kernel": kname,
                      "achieved": achieved / 1e12,
                      "peak": PEAK_FP32_VALU / 1e12, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_VALU,
-                     "traffic": measured_traffic(f"{'hybrid' if hybrid else 'eval'}_{dom}_kernel",
+                     "traffic": measured_traffic(f"{kname}_kernel",
                                                  args.workload,
                                                  not (args.views or args.res) and args.cell == 0.025
                                                  and (not hybrid or args.radius == 0.02), hybrid),
                      "traffic_unit": "bytes per launch",
                      "measured_valu_ceiling": valu_tflops,
                      "frac_of_measured_ceiling": achieved / 1e12 / valu_tflops,
-                     "flops_per_pair": fl_bwd if dom == "bwd" else fl_fwd},
+                     "flops_per_pair": fl_pair},
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")

@@ -149,6 +149,22 @@ gpf_status gpf_eval_radiance_backward(const gpf_grid *grid, const gpf_field *f, 
                                       int64_t q, const float *dL, gpf_field_grad *grad,
                                       void *stream);
 
+/* ---- one fitting pass (Sec. 4.3 MSE loss; Sec. 4.2 forward and backward) -
+ * The forward, the loss and the backward of one optimisation step in one
+ * call, for the truncated query: L[q][3] as gpf_eval_radiance writes it,
+ * loss_sum[0] (device, FP64) += sum_i sum_c (L - T)^2 over the q points
+ * against the targets T[q][3] (device, same order as x), and d(loss)/d(param)
+ * ADDED into grad as gpf_eval_radiance_backward would with
+ * dL = 2 (L - T) / q, each dL value rounded to FP32 as gpf_mse_loss rounds it.
+ * dL itself is never written to memory.  The caller zeroes loss_sum and grad.
+ * The survivor lists are kept as by gpf_eval_radiance, so a later backward on
+ * the same build reuses them.  Errors as for those two calls; L must not
+ * alias T.  Loss and gradient accumulation order is not deterministic
+ * (floating-point atomics). */
+gpf_status gpf_fit_pass(const gpf_grid *grid, const gpf_field *f, const float *x, int64_t q,
+                        const float *T, float *L, double *loss_sum, gpf_field_grad *grad,
+                        void *stream);
+
 /* ---- backward without device allocation ---------------------------------
  * For callers that cannot allocate device memory during the call: code under
  * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.

@@ -60,6 +60,8 @@ _SIG = {
                                                   ctypes.POINTER(FieldGrad), _P]),
     "gpf_eval_radiance_backward_noalloc": (ctypes.c_int, [_P, ctypes.POINTER(Field), _P, _I64, _P,
                                                           ctypes.POINTER(FieldGrad), _P]),
+    "gpf_fit_pass": (ctypes.c_int, [_P, ctypes.POINTER(Field), _P, _I64, _P, _P, _P,
+                                    ctypes.POINTER(FieldGrad), _P]),
     "gpf_count_pairs": (ctypes.c_int, [_P, ctypes.POINTER(Field), ctypes.POINTER(_I64), _P]),
     "gpf_build_grid_hybrid": (ctypes.c_int, [ctypes.POINTER(Field), _F, ctypes.c_int, _P, _P,
                                              ctypes.POINTER(_P)]),

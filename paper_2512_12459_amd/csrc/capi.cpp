@@ -253,6 +253,24 @@ gpf_status gpf_eval_radiance_backward_noalloc(const gpf_grid* g, const gpf_field
   return launch_eval_bwd_noalloc(g, dL, grad, (hipStream_t)stream);
 }
 
+gpf_status gpf_fit_pass(const gpf_grid* g, const gpf_field* f, const float* x, int64_t q,
+                        const float* T, float* L, double* loss_sum, gpf_field_grad* grad,
+                        void* stream) {
+  gpf_status st = check_grid_use(g, f, x, q);
+  if (st != GPF_OK) return st;
+  if (!T || !L || !loss_sum)
+    return set_error(GPF_ERR_INVALID_ARGUMENT, "T, L and loss_sum must be non-NULL");
+  if (T == L) return set_error(GPF_ERR_INVALID_ARGUMENT, "L aliases T");
+  if (!grad || !grad->mu || !grad->quat || !grad->log_scale || !grad->rgb)
+    return set_error(GPF_ERR_INVALID_ARGUMENT, "gradient buffers must be non-NULL");
+  const void* fp[4] = {f->mu, f->quat, f->log_scale, f->rgb};
+  const void* gp[4] = {grad->mu, grad->quat, grad->log_scale, grad->rgb};
+  for (auto a : fp)
+    for (auto b : gp)
+      if (a == b) return set_error(GPF_ERR_INVALID_ARGUMENT, "gradient buffer aliases the field");
+  return launch_fit_pass(g, T, L, loss_sum, grad, (hipStream_t)stream);
+}
+
 gpf_status gpf_build_grid_hybrid(const gpf_field* f, float r, int k_min, const gpf_queries* qs,
                                  void* stream, gpf_grid** grid) {
   if (!grid) return set_error(GPF_ERR_INVALID_ARGUMENT, "grid out-pointer is NULL");

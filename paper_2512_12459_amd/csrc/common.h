@@ -104,7 +104,7 @@ struct gpf_grid {
   int64_t entries = 0;
   float4* grad_rows = nullptr;  // [n][4] backward scratch: one 64-byte row per primitive
   int64_t grad_cap = 0;
-  // Survivors of the forward's cull, per group (primitive | tile mask << 30,
+  // Survivors of the forward's cull, per group (cell entry | tile mask << 30,
   // in cell-list order, at most kSurvPerGroup each) and their number, for the
   // backward of the same build; surv_ready is set by a forward and cleared by
   // a build.
@@ -161,6 +161,8 @@ gpf_status launch_eval_bwd(const gpf_grid* g, const float* dL, gpf_field_grad* g
 constexpr int64_t kNoAllocMaxPrims = (int64_t)1 << 18;
 gpf_status launch_eval_bwd_noalloc(const gpf_grid* g, const float* dL, gpf_field_grad* grad,
                                    hipStream_t s);
+gpf_status launch_fit_pass(const gpf_grid* g, const float* T, float* L, double* loss,
+                           gpf_field_grad* grad, hipStream_t s);
 gpf_status launch_count_pairs(const gpf_grid* g, unsigned long long* d_count, hipStream_t s);
 gpf_status ensure_grad_rows(gpf_grid* g, hipStream_t s);
 void ensure_survivor_lists(gpf_grid* g);

@@ -60,44 +60,23 @@ __device__ __forceinline__ int append_survivor(int* sv, int ns, bool pass, int p
 // ---------------------------------------------------------------------------
 constexpr int kFwdSurvCap = 256;   // staged survivors per wave
 
-// One wave per group of two consecutive tiles of one cell: lane l owns point l
-// of the first tile and point l of the second.  Lane = candidate culls the
-// cell's records (one contiguous block of 64 at a time) against both tile
-// boxes; a survivor is staged in LDS as entry | tile mask << 30.  Every lane then evaluates each survivor for the
+// Forward of one group of two consecutive tiles of one cell, run by one wave:
+// lane l owns point l of the first tile and point l of the second (px, py,
+// pz; acc receives their radiance).  Lane = candidate culls the cell's
+// records [cs, ce) (one contiguous block of 64 at a time) against both tile
+// boxes; a survivor is staged in sv (kFwdSurvCap ints of LDS) as
+// entry | tile mask << 30.  Every lane then evaluates each survivor for the
 // tiles it may touch (a wave-uniform branch per tile), reading mu, W' and the
 // flux with wave-uniform scalar loads: d = x - mu, u' = W' d (the local frame
-// of Alg. S3), w = 2^-|u'|^2 inside the cut.  The survivor loop is bound by the
-// latency of its scalar loads, so the kernel is held to 64 VGPRs (8 waves per
-// SIMD instead of 7).
-__global__ void __launch_bounds__(kWaves * 64) __attribute__((amdgpu_waves_per_eu(8, 8)))
-eval_fwd_kernel(
-    const float4* __restrict__ xs, const int* __restrict__ perm,
-    const GroupInfo* __restrict__ groups, int ngroups, const float4* __restrict__ tlo,
-    const float4* __restrict__ thi, const int* __restrict__ cell_start,
-    const PrimRec* __restrict__ cell_recs, float c2,
-    float* __restrict__ L, int* __restrict__ keep, int* __restrict__ keep_count) {
-  static_assert(kGroupTiles == 2, "the forward pairs the two tiles of a group");
-  __shared__ int surv[kWaves][kFwdSurvCap];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int g = xcd_remap(blockIdx.x) * kWaves + wave;
-  if (g >= ngroups) return;
-  const GroupInfo gi = groups[g];
-  const TileCtx ta = tile_ctx(tlo, thi, gi.first_tile);
-  const bool has_b = gi.count > kTile;
-  const TileCtx tb = has_b ? tile_ctx(tlo, thi, gi.first_tile + 1) : ta;
-  float px[2], py[2], pz[2], acc[2][3];
-#pragma unroll
-  for (int i = 0; i < 2; ++i) {
-    const float4 p = xs[gi.start + min(lane + 64 * i, gi.count - 1)];
-    px[i] = p.x;
-    py[i] = p.y;
-    pz[i] = p.z;
-    acc[i][0] = acc[i][1] = acc[i][2] = 0.f;
-  }
-  const int cs = cell_start[gi.cell], ce = cell_start[gi.cell + 1];
-  int* sv = surv[wave];
-  int ns = 0, kept = 0;  // kept: survivors so far (all of them, also past the list's capacity)
-  int* kl = keep ? keep + (int64_t)g * kSurvPerGroup : nullptr;
+// of Alg. S3), w = 2^-|u'|^2 inside the cut.  With kl non-null the survivors
+// are also stored there in cell-list order (at most kSurvPerGroup of them).
+// Returns the number of survivors, also past the list's capacity.
+__device__ __forceinline__ int fwd_group(const TileCtx& ta, const TileCtx& tb, bool has_b,
+                                         const float (&px)[2], const float (&py)[2],
+                                         const float (&pz)[2], float (&acc)[2][3], int cs, int ce,
+                                         const PrimRec* __restrict__ cell_recs, float c2, int* sv,
+                                         int* __restrict__ kl, int lane) {
+  int ns = 0, kept = 0;
   for (int base = cs; base < ce; base += 64) {
     const int j = base + lane;
     int mask = 0;
@@ -114,10 +93,9 @@ eval_fwd_kernel(
     if (ns > kFwdSurvCap - 64 || base + 64 >= ce) {
       wave_sync_lds();
       const int nsu = __builtin_amdgcn_readfirstlane(ns);  // wave-uniform trip count
-      if (kl) {  // keep the survivors (cell-list order) for the backward
+      if (kl)
         for (int s = lane; s < nsu && kept + s < kSurvPerGroup; s += 64) kl[kept + s] = sv[s];
-        kept += nsu;
-      }
+      kept += nsu;
       for (int s = 0; s < nsu; ++s) {
         const int head = __builtin_amdgcn_readfirstlane(sv[s]);
         const PrimRec r = cell_recs[head & 0x3fffffff];
@@ -139,6 +117,50 @@ eval_fwd_kernel(
       wave_sync_lds();
     }
   }
+  return kept;
+}
+
+// The points of a group as fwd_group takes them (lanes past the group's
+// count repeat its last point).
+__device__ __forceinline__ void load_group_points(const float4* __restrict__ xs,
+                                                  const GroupInfo& gi, float (&px)[2],
+                                                  float (&py)[2], float (&pz)[2],
+                                                  float (&acc)[2][3], int lane) {
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const float4 p = xs[gi.start + min(lane + 64 * i, gi.count - 1)];
+    px[i] = p.x;
+    py[i] = p.y;
+    pz[i] = p.z;
+    acc[i][0] = acc[i][1] = acc[i][2] = 0.f;
+  }
+}
+
+// One wave per group.  The survivor loop is bound by the latency of its
+// scalar loads, so the kernel is held to 64 VGPRs (8 waves per SIMD instead
+// of 7).
+__global__ void __launch_bounds__(kWaves * 64) __attribute__((amdgpu_waves_per_eu(8, 8)))
+eval_fwd_kernel(
+    const float4* __restrict__ xs, const int* __restrict__ perm,
+    const GroupInfo* __restrict__ groups, int ngroups, const float4* __restrict__ tlo,
+    const float4* __restrict__ thi, const int* __restrict__ cell_start,
+    const PrimRec* __restrict__ cell_recs, float c2,
+    float* __restrict__ L, int* __restrict__ keep, int* __restrict__ keep_count) {
+  static_assert(kGroupTiles == 2, "the forward pairs the two tiles of a group");
+  __shared__ int surv[kWaves][kFwdSurvCap];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int g = xcd_remap(blockIdx.x) * kWaves + wave;
+  if (g >= ngroups) return;
+  const GroupInfo gi = groups[g];
+  const TileCtx ta = tile_ctx(tlo, thi, gi.first_tile);
+  const bool has_b = gi.count > kTile;
+  const TileCtx tb = has_b ? tile_ctx(tlo, thi, gi.first_tile + 1) : ta;
+  float px[2], py[2], pz[2], acc[2][3];
+  load_group_points(xs, gi, px, py, pz, acc, lane);
+  const int cs = cell_start[gi.cell], ce = cell_start[gi.cell + 1];
+  int* kl = keep ? keep + (int64_t)g * kSurvPerGroup : nullptr;
+  const int kept = fwd_group(ta, tb, has_b, px, py, pz, acc, cs, ce, cell_recs, c2, surv[wave],
+                             kl, lane);
   if (keep_count && lane == 0) keep_count[g] = kept;
 #pragma unroll
   for (int i = 0; i < 2; ++i) {
@@ -151,15 +173,6 @@ eval_fwd_kernel(
     }
   }
 }
-
-// Four-tile forward: one wave per pair of consecutive groups (groups 2w and
-// 2w + 1).  When both lie in one cell they are culled and evaluated together
-// (lane l owns point l of each of the four tiles); otherwise the wave takes
-// them one after the other.  Each block of 64 cell records is tested against
-// every tile box once, and a staged survivor {entry, 4-bit tile mask} is read
-// with wave-uniform scalar loads and evaluated on the tiles it may touch.
-// The survivors are kept per group (entry | 2-bit mask << 30, cell-list
-// order) for the backward of the same build.
 // ---------------------------------------------------------------------------
 // Exact pair count (same traversal as the forward)
 // ---------------------------------------------------------------------------
@@ -230,16 +243,16 @@ __device__ __forceinline__ void bwd_chunk(int ent, bool valid, int qb, int qe,
   float GP[3] = {0.f, 0.f, 0.f}, A[3] = {0.f, 0.f, 0.f};
   float U[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   bool any = false;
-  for (int k = qb; k < qe; k += 4) {
-    float4 xq[4], gq[4];
+  for (int k = qb; k < qe; k += 2) {
+    float4 xq[2], gq[2];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {   // point k: (x, y), (z, gx), (gy, gz)
+    for (int i = 0; i < 2; ++i) {   // point k: (x, y), (z, gx), (gy, gz)
       const float2 a = qp[3 * (k + i)], b = qp[3 * (k + i) + 1], c = qp[3 * (k + i) + 2];
       xq[i] = make_float4(a.x, a.y, b.x, 0.f);
       gq[i] = make_float4(b.y, c.x, c.y, 0.f);
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < 2; ++i) {
       const float dx = xq[i].x - r.r0.x, dy = xq[i].y - r.r0.y, dz = xq[i].z - r.r0.z;
       const float u0 = fmaf(r.r1.z, dz, fmaf(r.r1.y, dy, r.r1.x * dx));
       const float u1 = fmaf(r.r2.z, dz, fmaf(r.r2.y, dy, r.r2.x * dx));
@@ -284,63 +297,30 @@ __device__ __forceinline__ void bwd_chunk(int ent, bool valid, int qb, int qe,
   wave_sync_lds();
 }
 
-// One wave per group of two consecutive tiles of one cell, with no
-// workgroup-wide synchronisation.  Lane = candidate culls the cell's list
-// against both tile boxes and pushes survivors onto three LDS stacks (first
-// tile only, second tile only, both).  A stack that holds 64 entries is
-// drained at once as a pure chunk over the points of its tiles; the
-// remainders (under 64 each) are taken at the end in the order
+// Backward of one group of two consecutive tiles of one cell, run by one wave
+// with no workgroup-wide synchronisation; the group's points and their
+// upstream gradients are in qp.  The survivors are sorted onto three LDS
+// stacks by tile mask (first tile only, second tile only, both).  A stack
+// that holds 64 entries is drained at once as a pure chunk over the points of
+// its tiles; the remainders (under 64 each) are taken at the end in the order
 // first-tile-only, both, second-tile-only, so a chunk loops over the second
 // tile only if one of its survivors may touch it, and over the first likewise.
-__global__ void __launch_bounds__(kBwdThreads) eval_bwd_kernel(
-    const float4* __restrict__ xs, const int* __restrict__ perm,
-    const GroupInfo* __restrict__ groups, int ngroups, const float4* __restrict__ tlo,
-    const float4* __restrict__ thi, const int* __restrict__ cell_start,
-    const PrimRec* __restrict__ cell_recs, float c2,
-    const float* __restrict__ dL, float* __restrict__ grad_rows, const int* __restrict__ keep,
-    const int* __restrict__ keep_count) {
-  static_assert(kGroupTiles == 2, "the backward splits survivors over the two tiles of a group");
-  __shared__ int sv_all[kBwdWaves][3][kListCap];
-  __shared__ float2 qp_all[kBwdWaves][3 * kGroupQ];   // per point x, y, z, gx, gy, gz
-  __shared__ float rows_all[kBwdWaves][64 * kRowStride];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int g = xcd_remap(blockIdx.x) * kBwdWaves + wave;
-  if (g >= ngroups) return;  // per wave: no workgroup barrier follows
-  const GroupInfo gi = groups[g];
-  const TileCtx ta = tile_ctx(tlo, thi, gi.first_tile);
-  const bool has_b = gi.count > kTile;
-  const TileCtx tb = has_b ? tile_ctx(tlo, thi, gi.first_tile + 1) : ta;
-  float2* qp = qp_all[wave];
-  int* sv0 = sv_all[wave][0];
-  int* sv1 = sv_all[wave][1];
-  int* sv2 = sv_all[wave][2];
-  float* rw = rows_all[wave];
-  for (int k = lane; k < kGroupQ; k += 64) {
-    if (k < gi.count) {
-      const int o = perm[gi.start + k];
-      const float4 p = xs[gi.start + k];
-      qp[3 * k] = make_float2(p.x, p.y);
-      qp[3 * k + 1] = make_float2(p.z, dL[(int64_t)o * 3]);
-      qp[3 * k + 2] = make_float2(dL[(int64_t)o * 3 + 1], dL[(int64_t)o * 3 + 2]);
-    } else {
-      qp[3 * k] = make_float2(ta.cx, ta.cy);   // any finite point; g = 0
-      qp[3 * k + 1] = make_float2(ta.cz, 0.f);
-      qp[3 * k + 2] = make_float2(0.f, 0.f);
-    }
-  }
-  wave_sync_lds();
+// The survivors come from the forward's list kl when it holds all nk of them
+// (nk <= kSurvPerGroup): the same (primitive, tile mask) pairs, in the same
+// order, as the cull would find, so the same (primitive, point) slots are
+// evaluated without testing any candidate again (stacks drain at other
+// moments, which only regroups the sums).  Otherwise lane = candidate culls
+// the cell's records [cs, ce) against both tile boxes.
+__device__ __forceinline__ void bwd_group(const GroupInfo& gi, const TileCtx& ta,
+                                          const TileCtx& tb, bool has_b, int cs, int ce,
+                                          const PrimRec* __restrict__ cell_recs, float c2,
+                                          const float2* qp, int* sv0, int* sv1, int* sv2,
+                                          float* rw, float* __restrict__ grad_rows,
+                                          const int* __restrict__ kl, int nk, int lane) {
   const int qe_a = (min(gi.count, kTile) + 3) & ~3, qe_all = (gi.count + 3) & ~3;
   const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  const int cs = cell_start[gi.cell], ce = cell_start[gi.cell + 1];
   int n0 = 0, n1 = 0, n2 = 0;  // stack heights, each below 64 between batches
-  // The forward's survivors of this group, when it kept them all: the same
-  // (primitive, tile mask) pairs, in the same order, as the cull below would
-  // find, so the same (primitive, point) slots are evaluated without testing
-  // any candidate again (stacks drain at other moments, which only regroups
-  // the sums).
-  const int nk = keep_count ? keep_count[g] : kSurvPerGroup + 1;
-  if (nk <= kSurvPerGroup) {
-    const int* kl = keep + (int64_t)g * kSurvPerGroup;
+  if (kl && nk <= kSurvPerGroup) {
     for (int base = 0; base < nk; base += 64) {
       const int ent = (base + lane < nk) ? kl[base + lane] : 0;
       const int mask = (base + lane < nk) ? ((ent >> 30) & 3) : 0;
@@ -367,41 +347,42 @@ __global__ void __launch_bounds__(kBwdThreads) eval_bwd_kernel(
       }
     }
   } else {
-  // Software pipeline over the candidates in batches of 64: the records of
-  // batch b + 1 are requested before batch b is tested, so their latency
-  // overlaps the tests and the draining of full stacks.  Entries past the end
-  // repeat the cell's last one, keeping every load unconditional and in bounds.
-  PrimRec rec_c{};
-  if (cs < ce) rec_c = cell_recs[min(cs + lane, ce - 1)];
-  for (int base = cs; base < ce; base += 64) {
-    const PrimRec rec_n = cell_recs[min(base + 64 + lane, ce - 1)];
-    const int pid = base + lane;   // cell entry
-    int mask = 0;
-    if (base + lane < ce)
-      mask = (tile_may_touch(rec_c, ta, c2) ? 1 : 0) |
-             ((has_b && tile_may_touch(rec_c, tb, c2)) ? 2 : 0);
-    const uint64_t m0 = __ballot(mask == 1), m1 = __ballot(mask == 2), m2 = __ballot(mask == 3);
-    if (mask == 1) sv0[n0 + __popcll(m0 & below)] = pid;
-    if (mask == 2) sv1[n1 + __popcll(m1 & below)] = pid;
-    if (mask == 3) sv2[n2 + __popcll(m2 & below)] = pid;
-    n0 += __popcll(m0);
-    n1 += __popcll(m1);
-    n2 += __popcll(m2);
-    wave_sync_lds();
-    if (n0 >= 64) {
-      n0 -= 64;
-      bwd_chunk(sv0[n0 + lane], true, 0, qe_a, cell_recs, c2, qp, rw, grad_rows, lane);
+    // Software pipeline over the candidates in batches of 64: the records of
+    // batch b + 1 are requested before batch b is tested, so their latency
+    // overlaps the tests and the draining of full stacks.  Entries past the
+    // end repeat the cell's last one, keeping every load unconditional and in
+    // bounds.
+    PrimRec rec_c{};
+    if (cs < ce) rec_c = cell_recs[min(cs + lane, ce - 1)];
+    for (int base = cs; base < ce; base += 64) {
+      const PrimRec rec_n = cell_recs[min(base + 64 + lane, ce - 1)];
+      const int pid = base + lane;   // cell entry
+      int mask = 0;
+      if (base + lane < ce)
+        mask = (tile_may_touch(rec_c, ta, c2) ? 1 : 0) |
+               ((has_b && tile_may_touch(rec_c, tb, c2)) ? 2 : 0);
+      const uint64_t m0 = __ballot(mask == 1), m1 = __ballot(mask == 2), m2 = __ballot(mask == 3);
+      if (mask == 1) sv0[n0 + __popcll(m0 & below)] = pid;
+      if (mask == 2) sv1[n1 + __popcll(m1 & below)] = pid;
+      if (mask == 3) sv2[n2 + __popcll(m2 & below)] = pid;
+      n0 += __popcll(m0);
+      n1 += __popcll(m1);
+      n2 += __popcll(m2);
+      wave_sync_lds();
+      if (n0 >= 64) {
+        n0 -= 64;
+        bwd_chunk(sv0[n0 + lane], true, 0, qe_a, cell_recs, c2, qp, rw, grad_rows, lane);
+      }
+      if (n1 >= 64) {
+        n1 -= 64;
+        bwd_chunk(sv1[n1 + lane], true, kTile, qe_all, cell_recs, c2, qp, rw, grad_rows, lane);
+      }
+      if (n2 >= 64) {
+        n2 -= 64;
+        bwd_chunk(sv2[n2 + lane], true, 0, qe_all, cell_recs, c2, qp, rw, grad_rows, lane);
+      }
+      rec_c = rec_n;
     }
-    if (n1 >= 64) {
-      n1 -= 64;
-      bwd_chunk(sv1[n1 + lane], true, kTile, qe_all, cell_recs, c2, qp, rw, grad_rows, lane);
-    }
-    if (n2 >= 64) {
-      n2 -= 64;
-      bwd_chunk(sv2[n2 + lane], true, 0, qe_all, cell_recs, c2, qp, rw, grad_rows, lane);
-    }
-    rec_c = rec_n;
-  }
   }
   const int total = n0 + n1 + n2;
   for (int chunk = 0; chunk < total; chunk += 64) {
@@ -421,6 +402,118 @@ __global__ void __launch_bounds__(kBwdThreads) eval_bwd_kernel(
     bwd_chunk(id, cat != 0, use_a ? 0 : kTile, use_b ? qe_all : qe_a, cell_recs, c2, qp,
               rw, grad_rows, lane);
   }
+}
+
+// Point k of a group in the backward's LDS layout: (x, y), (z, gx), (gy, gz).
+// Points past the group's count sit at the first tile's centre (any finite
+// point would do) with a zero upstream gradient.
+__device__ __forceinline__ void put_point(float2* qp, int k, float x, float y, float z, float gx,
+                                          float gy, float gz) {
+  qp[3 * k] = make_float2(x, y);
+  qp[3 * k + 1] = make_float2(z, gx);
+  qp[3 * k + 2] = make_float2(gy, gz);
+}
+
+// One wave per group; dL[q][3] in the points' original order.
+__global__ void __launch_bounds__(kBwdThreads) eval_bwd_kernel(
+    const float4* __restrict__ xs, const int* __restrict__ perm,
+    const GroupInfo* __restrict__ groups, int ngroups, const float4* __restrict__ tlo,
+    const float4* __restrict__ thi, const int* __restrict__ cell_start,
+    const PrimRec* __restrict__ cell_recs, float c2,
+    const float* __restrict__ dL, float* __restrict__ grad_rows, const int* __restrict__ keep,
+    const int* __restrict__ keep_count) {
+  static_assert(kGroupTiles == 2, "the backward splits survivors over the two tiles of a group");
+  __shared__ int sv_all[kBwdWaves][3 * kListCap];
+  __shared__ float2 qp_all[kBwdWaves][3 * kGroupQ];
+  __shared__ float rows_all[kBwdWaves][64 * kRowStride];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int g = xcd_remap(blockIdx.x) * kBwdWaves + wave;
+  if (g >= ngroups) return;  // per wave: no workgroup barrier follows
+  const GroupInfo gi = groups[g];
+  const TileCtx ta = tile_ctx(tlo, thi, gi.first_tile);
+  const bool has_b = gi.count > kTile;
+  const TileCtx tb = has_b ? tile_ctx(tlo, thi, gi.first_tile + 1) : ta;
+  float2* qp = qp_all[wave];
+  for (int k = lane; k < kGroupQ; k += 64) {
+    if (k < gi.count) {
+      const int o = perm[gi.start + k];
+      const float4 p = xs[gi.start + k];
+      put_point(qp, k, p.x, p.y, p.z, dL[(int64_t)o * 3], dL[(int64_t)o * 3 + 1],
+                dL[(int64_t)o * 3 + 2]);
+    } else {
+      put_point(qp, k, ta.cx, ta.cy, ta.cz, 0.f, 0.f, 0.f);
+    }
+  }
+  wave_sync_lds();
+  const int cs = cell_start[gi.cell], ce = cell_start[gi.cell + 1];
+  const int* kl = keep_count ? keep + (int64_t)g * kSurvPerGroup : nullptr;
+  const int nk = keep_count ? keep_count[g] : 0;
+  bwd_group(gi, ta, tb, has_b, cs, ce, cell_recs, c2, qp, sv_all[wave], sv_all[wave] + kListCap,
+            sv_all[wave] + 2 * kListCap, rows_all[wave], grad_rows, kl, nk, lane);
+}
+
+// One fitting pass per group (Sec. 4.3), one wave each: the forward of the
+// group's points, their squared error against the targets T (original
+// order) and upstream gradient dL = scale (L - T), then the backward of the
+// same group with that dL, over the survivors the forward has just kept (and
+// stored with their count, as the forward kernel does).
+// L is written in the original order; loss[0] += sum (L - T)^2 in FP64, one
+// atomic per group.  The forward's staging list shares LDS with the
+// backward's stacks.
+__global__ void __launch_bounds__(kBwdThreads) fit_pass_kernel(
+    const float4* __restrict__ xs, const int* __restrict__ perm,
+    const GroupInfo* __restrict__ groups, int ngroups, const float4* __restrict__ tlo,
+    const float4* __restrict__ thi, const int* __restrict__ cell_start,
+    const PrimRec* __restrict__ cell_recs, float c2, const float* __restrict__ T, float scale,
+    float* __restrict__ L, double* __restrict__ loss, int* __restrict__ keep,
+    int* __restrict__ keep_count, float* __restrict__ grad_rows) {
+  static_assert(kGroupTiles == 2, "the pass pairs the two tiles of a group");
+  static_assert(kFwdSurvCap <= 3 * kListCap, "the forward staging fits in the backward stacks");
+  __shared__ int sv_all[kBwdWaves][3 * kListCap];
+  __shared__ float2 qp_all[kBwdWaves][3 * kGroupQ];
+  __shared__ float rows_all[kBwdWaves][64 * kRowStride];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int g = xcd_remap(blockIdx.x) * kBwdWaves + wave;
+  if (g >= ngroups) return;  // per wave: no workgroup barrier follows
+  const GroupInfo gi = groups[g];
+  const TileCtx ta = tile_ctx(tlo, thi, gi.first_tile);
+  const bool has_b = gi.count > kTile;
+  const TileCtx tb = has_b ? tile_ctx(tlo, thi, gi.first_tile + 1) : ta;
+  float px[2], py[2], pz[2], acc[2][3];
+  load_group_points(xs, gi, px, py, pz, acc, lane);
+  const int cs = cell_start[gi.cell], ce = cell_start[gi.cell + 1];
+  int* kl = keep ? keep + (int64_t)g * kSurvPerGroup : nullptr;
+  const int nk = fwd_group(ta, tb, has_b, px, py, pz, acc, cs, ce, cell_recs, c2,
+                           sv_all[wave], kl, lane);
+  if (keep_count && lane == 0) keep_count[g] = nk;   // the lists stay valid for a later backward
+  // other lanes of this wave read the list back below
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  float2* qp = qp_all[wave];
+  double part = 0.0;
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int k = lane + 64 * i;
+    if (k < gi.count) {
+      const int o = perm[gi.start + k];
+      float d[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        d[c] = acc[i][c] - T[(int64_t)o * 3 + c];
+        L[(int64_t)o * 3 + c] = acc[i][c];
+        part += (double)d[c] * (double)d[c];
+      }
+      put_point(qp, k, px[i], py[i], pz[i], scale * d[0], scale * d[1], scale * d[2]);
+    } else {
+      put_point(qp, k, ta.cx, ta.cy, ta.cz, 0.f, 0.f, 0.f);
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off, 64);
+  if (lane == 0) unsafeAtomicAdd(loss, part);
+  wave_sync_lds();
+  bwd_group(gi, ta, tb, has_b, cs, ce, cell_recs, c2, qp, sv_all[wave], sv_all[wave] + kListCap,
+            sv_all[wave] + 2 * kListCap, rows_all[wave], grad_rows, kl, nk, lane);
 }
 
 
@@ -514,6 +607,25 @@ gpf_status launch_eval_bwd(const gpf_grid* gc, const float* dL, gpf_field_grad* 
   gpf_status st = ensure_grad_rows(g, s);
   if (st != GPF_OK) return st;
   return launch_eval_bwd_rows(g, dL, grad, g->grad_rows, s);
+}
+
+// One fitting pass into the handle's gradient rows, then the finalize pass.
+gpf_status launch_fit_pass(const gpf_grid* gc, const float* T, float* L, double* loss,
+                           gpf_field_grad* grad, hipStream_t s) {
+  gpf_grid* g = const_cast<gpf_grid*>(gc);  // survivor lists and rows live in the handle
+  const gpf_queries* qs = g->qs;
+  const float c2 = (float)(kKappa2 * g->cutoff * g->cutoff);
+  const float scale = (float)(2.0 / (double)qs->q);   // as gpf_mse_loss
+  ensure_survivor_lists(g);
+  gpf_status st = ensure_grad_rows(g, s);
+  if (st != GPF_OK) return st;
+  hipLaunchKernelGGL(fit_pass_kernel, dim3(xcd_grid((qs->ngroups + kBwdWaves - 1) / kBwdWaves)),
+                     dim3(kBwdThreads), 0, s, qs->xs, qs->perm, qs->groups, (int)qs->ngroups,
+                     qs->tile_lo, qs->tile_hi, g->cell_start, g->cell_recs, c2, T, scale, L, loss,
+                     g->surv, g->surv ? g->surv_count : nullptr, (float*)g->grad_rows);
+  GPF_HIP(hipGetLastError());
+  g->surv_ready = g->surv != nullptr;
+  return launch_grad_finalize(g, g->grad_rows, grad, s);
 }
 
 // Device address of `scratch`, looked up once per device (with that device

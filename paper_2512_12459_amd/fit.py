@@ -3,7 +3,9 @@
 
 Every step rebuilds the cull grid for the current parameters, evaluates the
 radiance, takes the MSE and its gradient, runs the recompute backward and
-updates each parameter group with Adam.  All of it runs in libgpf.so.
+updates each parameter group with Adam.  With the truncated query the
+forward, the loss and the backward are one fitting pass (one kernel).  All of
+it runs in libgpf.so.
 """
 from __future__ import annotations
 
@@ -65,10 +67,12 @@ class Fitter:
     """Fits ``field`` to targets T [q,3] at the points of ``queries``, with the
     truncated query (3-sigma, un-normalised) or, with ``query="hybrid"``, the
     paper's hybrid query (ball of radius ``r``, top-up to ``k_min`` nearest,
-    falloff, normalised)."""
+    falloff, normalised).  ``fused=False`` runs the truncated query's
+    forward, loss and backward as three separate calls."""
 
     def __init__(self, field: Field, queries: R.QuerySet, T: torch.Tensor, lr=None,
-                 cutoff: float = 3.0, query: str = "truncated", r: float = 0.02, k_min: int = 3):
+                 cutoff: float = 3.0, query: str = "truncated", r: float = 0.02, k_min: int = 3,
+                 fused: bool = True):
         self.f = field
         self.qs = queries
         self.T = T
@@ -78,6 +82,7 @@ class Fitter:
             raise ValueError(f"unknown query {query!r}")
         self.hybrid = query == "hybrid"
         self.grid = R.HybridGrid(queries, r, k_min) if self.hybrid else R.Grid(queries, cutoff)
+        self.fused = fused and not self.hybrid
         self.L = torch.empty_like(T)
         self.dL = torch.empty_like(T)
         self.loss = torch.zeros(1, dtype=torch.float64, device=T.device)
@@ -96,17 +101,27 @@ class Fitter:
 
     def step(self):
         f = self.f
+        if self.fused:
+            self.grid.build(*f.arrays())
+            self.loss.zero_()
+            f.G.zero_()
+            R.fit_pass(self.grid, *f.arrays(), self.T, L=self.L, loss_sum=self.loss, grads=f.g)
+        else:
+            self._separate_pass()
+        self.t += 1
+        # a non-finite loss skips the update on the device: the parameters keep
+        # the last state whose loss was finite until the next check stops the run
+        for k, _ in Field.GROUPS:
+            R.adam_step(f.p[k], f.g[k], f.m[k], f.v[k], self.t, self.lr[k], guard=self.loss)
+
+    def _separate_pass(self):
+        f = self.f
         self._forward()
         f.G.zero_()
         if self.hybrid:
             R.eval_hybrid_backward(self.grid, *f.arrays(), self.L, self.Z, self.count, self.dL, f.g)
         else:
             R.eval_radiance_backward(self.grid, *f.arrays(), self.dL, f.g)
-        self.t += 1
-        # a non-finite loss skips the update on the device: the parameters keep
-        # the last state whose loss was finite until the next check stops the run
-        for k, _ in Field.GROUPS:
-            R.adam_step(f.p[k], f.g[k], f.m[k], f.v[k], self.t, self.lr[k], guard=self.loss)
 
     def mse(self) -> float:
         """Per-element mean squared error of the radiance before the last step."""

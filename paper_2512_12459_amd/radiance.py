@@ -152,6 +152,34 @@ def eval_radiance_backward(grid: Grid, mu, quat, log_scale, rgb, dL, grads=None)
     return grads
 
 
+def fit_pass(grid: Grid, mu, quat, log_scale, rgb, T, L=None, loss_sum=None, grads=None):
+    """Forward, MSE against targets T [q,3] and backward of one fitting step in
+    one call (truncated query).  Writes L, adds sum (L - T)^2 into
+    ``loss_sum`` (float64 [1], zeroed if allocated here) and d(loss)/d(params)
+    for dL = 2 (L - T) / q into ``grads`` (zero-initialised tensors, allocated
+    if None).  Returns (L, loss_sum, grads)."""
+    fs = field_struct(mu, quat, log_scale, rgb)
+    x = grid.queries.x
+    _need(T, "T", 3)
+    if T.shape[0] != x.shape[0]:
+        raise ValueError(f"T holds {T.shape[0]} points, the query set {x.shape[0]}")
+    if L is None:
+        L = torch.empty_like(T)
+    _need(L, "L", 3)
+    if loss_sum is None:
+        loss_sum = torch.zeros(1, dtype=torch.float64, device=T.device)
+    if loss_sum.dtype != torch.float64 or loss_sum.device.type != "cuda":
+        raise ValueError("loss_sum must be a float64 device tensor")
+    if grads is None:
+        grads = dict(mu=torch.zeros_like(mu), quat=torch.zeros_like(quat),
+                     log_scale=torch.zeros_like(log_scale), rgb=torch.zeros_like(rgb))
+    gs = C.FieldGrad(C.ptr(grads["mu"]), C.ptr(grads["quat"]), C.ptr(grads["log_scale"]),
+                     C.ptr(grads["rgb"]))
+    C.check(C.lib().gpf_fit_pass(grid.handle, ctypes.byref(fs), C.ptr(x), x.shape[0], C.ptr(T),
+                                 C.ptr(L), C.ptr(loss_sum), ctypes.byref(gs), _stream()))
+    return L, loss_sum, grads
+
+
 class GPFRadiance(torch.autograd.Function):
     """L = GPFRadiance.apply(mu, quat, log_scale, rgb, grid).
 

@@ -56,6 +56,7 @@ def check_host_validation(L):
     assert L.gpf_queries_info(None, ctypes.byref(q), None, None, None) == 1
     assert L.gpf_eval_radiance_backward_noalloc(None, ctypes.byref(f), fake, 5, fake, None,
                                                 None) == 1
+    assert L.gpf_fit_pass(None, ctypes.byref(f), fake, 5, fake, fake, fake, None, None) == 1
     L.gpf_queries_destroy(None)
     L.gpf_grid_destroy(None)
     assert L.gpf_version().startswith(b"gpf")

@@ -292,6 +292,56 @@ def test_permutation_invariance(rad, c1, case):
         assert np.all(np.abs(g1[k] - g0[k]) <= 1e-4 * gref[k + "_abs"] + 1e-30 + 2 * 2.0 ** -24 * gref[k + "_cond"]), k
 
 
+@pytest.mark.parametrize("case", ["plain4k", "crowded"])
+def test_fit_pass_matches_separate_calls_and_the_oracle(rad, c1, case):
+    """The one-kernel fitting pass (forward, MSE, backward per group) writes
+    the forward's L bit for bit and the loss sum of the MSE kernel up to FP64
+    summation order; its gradients match the oracle's for the same FP32 dL,
+    and so do those of a later backward that reuses the survivor lists the
+    pass kept.  The crowded case overflows the lists (the pass culls again)."""
+    rng = np.random.default_rng(41)
+    if case == "plain4k":
+        f, x, ref = c1
+        arrays, cell = f.arrays(), 0.025
+    else:
+        n = 3000
+        arrays = (0.5 + rng.normal(0, 0.002, (n, 3)), rng.normal(size=(n, 4)),
+                  np.log(0.01) + rng.normal(0, 0.2, (n, 3)), np.exp(rng.normal(0, 1, (n, 3))))
+        arrays = tuple(a.astype(np.float32) for a in arrays)
+        x = (0.5 + rng.normal(0, 0.01, (400, 3))).astype(np.float32)
+        ref = O.radiance(*arrays, x)
+        cell = 0.05
+    say(f"case: fit pass vs separate calls, {case}")
+    L_s, g, dev, qs = _eval(rad, arrays, x, cell)
+    # targets: random, except at points with a cutoff-ambiguous pair, where
+    # T = L makes dL exactly zero on both paths
+    T = (rng.random((len(x), 3)) * 2 * np.maximum(L_s, 1e-3)).astype(np.float32)
+    amb = ref["n_amb"] > 0
+    T[amb] = L_s[amb]
+    (Td,) = to_dev(T)
+    loss_s, dL_s = rad.mse_loss(torch.from_numpy(L_s).cuda(), Td)
+    g_sep = {k: v.cpu().numpy()
+             for k, v in rad.eval_radiance_backward(g, *dev, dL_s).items()}
+    L_f, loss_f, g_f = rad.fit_pass(g, *dev, Td)
+    torch.cuda.synchronize()
+    L_f = L_f.cpu().numpy()
+    assert np.array_equal(L_f.view(np.int32), L_s.view(np.int32))
+    ls_, lf_ = loss_s.item(), loss_f.item()
+    assert abs(lf_ - ls_) <= 1e-12 * ls_, (lf_, ls_)
+    dL = dL_s.cpu().numpy()
+    assert np.all(dL[amb] == 0)
+    gref = O.radiance_backward(*arrays, x, dL)
+    g_f = {k: v.cpu().numpy() for k, v in g_f.items()}
+    check_grads(g_f, gref)
+    check_grads(g_sep, gref)
+    for k in g_f:   # the same slots; only the order of the atomic additions differs
+        assert np.all(np.abs(g_f[k] - g_sep[k]) <=
+                      1e-4 * gref[k + "_abs"] + 1e-30 + 2 * 2.0 ** -24 * gref[k + "_cond"]), k
+    say(f"case: backward after the fit pass, reusing its survivor lists, {case}")
+    g_after = {k: v.cpu().numpy() for k, v in rad.eval_radiance_backward(g, *dev, dL_s).items()}
+    check_grads(g_after, gref)
+
+
 def test_autograd_function_matches_direct_call(rad):
     mu, q, ls, rgb, x = _grad_problem(6, 200, 1000, 0.15)
     dev = [t.clone().requires_grad_(True) for t in to_dev(mu, q, ls, rgb)]
