@@ -201,6 +201,7 @@ void gpf_grid_destroy(gpf_grid* g) {
   dev_free(g->surv, (size_t)g->surv_groups * kSurvPerGroup * sizeof(int));
   dev_free(g->surv_count, (size_t)g->surv_groups * sizeof(int));
   free_centre_grid(g);
+  if (g->readback) (void)hipHostFree(g->readback);
   delete g;
 }
 

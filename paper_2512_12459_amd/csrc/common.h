@@ -89,6 +89,7 @@ struct gpf_grid {
   int64_t rec_cap = 0;
   int* prim_off = nullptr;      // per-(primitive, sub-thread) entry counts and their scan
   int64_t prim_off_len = 0;     // allocated entries of prim_off
+  int* readback = nullptr;      // pinned host pair: entry total, degenerate primitives
   int* cell_start = nullptr;    // [ncells + 1]
   int64_t cell_start_cap = 0;   // allocated entries of cell_start
   uint64_t qs_gen = 0;          // query-set binning this grid was built on

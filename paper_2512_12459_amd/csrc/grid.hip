@@ -3,12 +3,13 @@
 // count per primitive -> scan -> emit (cell, primitive) entries in primitive
 // order -> stable radix sort by cell, so each cell lists its primitives in
 // ascending index order (deterministic sums downstream).
-#include <rocprim/device/device_radix_sort.hpp>
 #include <rocprim/device/device_scan.hpp>
 
+#include <algorithm>
 #include <cmath>
 
 #include "common.h"
+#include "sort.h"
 
 namespace gpf {
 namespace {
@@ -186,8 +187,9 @@ __device__ __forceinline__ int visit_cells(const PrimRec& r, const float ext[3],
 __global__ void __launch_bounds__(256) frame_kernel(
     const float* __restrict__ mu, const float* __restrict__ quat, const float* __restrict__ ls,
     const float* __restrict__ rgb, int n, float cutoff, float ball, PrimRec* __restrict__ recs,
-    float4* __restrict__ exts, int* __restrict__ bad) {
+    float4* __restrict__ exts, int* __restrict__ bad, int* __restrict__ scan_pad) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) *scan_pad = 0;   // the count past the last one, so the scan yields the total
   if (i >= n) return;
   PrimRec r;
   float ext[3];
@@ -309,13 +311,15 @@ gpf_status launch_build_grid(gpf_grid* g, hipStream_t s) {
            qs->dims[2]};
   const int nb = (n + 255) / 256;
   const unsigned mb = (unsigned)((m + 255) / 256);
-  // counts: prim_off[0 .. m] (entry m stays 0), degenerate counter at m + 1;
-  // offsets: prim_off[m + 2 .. 2m + 2]
+  // counts: prim_off[0 .. m] (entry m is 0); offsets: prim_off[m + 1 .. 2m + 1]
+  // (the total last); degenerate counter at 2m + 2, next to the total, so
+  // that one copy reads both back
   int* cnt = g->prim_off;
-  int* off = g->prim_off + m + 2;
-  GPF_HIP(hipMemsetAsync(cnt + m, 0, 2 * sizeof(int), s));
+  int* off = g->prim_off + m + 1;
+  int* bad = off + m + 1;
+  GPF_HIP(hipMemsetAsync(bad, 0, sizeof(int), s));
   hipLaunchKernelGGL(frame_kernel, dim3(nb), dim3(256), 0, s, g->mu, g->quat, g->log_scale, g->rgb,
-                     n, g->cutoff, g->ball, g->rec, g->ext, cnt + m + 1);
+                     n, g->cutoff, g->ball, g->rec, g->ext, bad, cnt + m);
   hipLaunchKernelGGL(count_kernel, dim3(mb), dim3(256), 0, s, n, S, g->cutoff, g->ball, geo,
                      qs->occ_bits, qs->occ_of_dense, g->rec, g->ext, cnt);
   size_t scan_bytes = 0;
@@ -329,13 +333,18 @@ gpf_status launch_build_grid(gpf_grid* g, hipStream_t s) {
     if (st != GPF_OK) return st;
     g->sort_tmp_bytes = scan_bytes;
   }
-  int host[2] = {0, 0};
+  if (!g->readback) {   // pinned, so that the copy below is one asynchronous transfer
+    void* p = nullptr;
+    const hipError_t e = hipHostMalloc(&p, 2 * sizeof(int), hipHostMallocDefault);
+    if (e != hipSuccess) return hip_fail(e, "hipHostMalloc(read-back)");
+    g->readback = static_cast<int*>(p);
+  }
   size_t tb = g->sort_tmp_bytes;
   GPF_HIP(rocprim::exclusive_scan(g->sort_tmp, tb, cnt, off, 0, (size_t)(m + 1),
                                   rocprim::plus<int>(), s));
-  GPF_HIP(hipMemcpyAsync(&host[1], cnt + m + 1, sizeof(int), hipMemcpyDeviceToHost, s));
-  GPF_HIP(hipMemcpyAsync(&host[0], off + m, sizeof(int), hipMemcpyDeviceToHost, s));
+  GPF_HIP(hipMemcpyAsync(g->readback, off + m, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
   GPF_HIP(hipStreamSynchronize(s));
+  const int host[2] = {g->readback[0], g->readback[1]};   // total entries, degenerate primitives
   if (host[1] > 0)
     return set_error(GPF_ERR_INVALID_ARGUMENT,
                      "field has a zero-norm quaternion or a non-finite parameter");
@@ -365,9 +374,15 @@ gpf_status launch_build_grid(gpf_grid* g, hipStream_t s) {
   int bits_needed = 1;
   while ((1 << bits_needed) <= nc) ++bits_needed;
   size_t sort_bytes = 0;
-  GPF_HIP(rocprim::radix_sort_pairs(nullptr, sort_bytes, g->keys, g->keys_sorted, g->vals,
-                                    g->cell_prims, (size_t)E, 0, bits_needed, s));
+  GPF_HIP(sort_pairs(nullptr, sort_bytes, g->keys, g->keys_sorted, g->vals, g->cell_prims,
+                     (size_t)E, 0, bits_needed, s));
   if (g->sort_tmp_bytes < sort_bytes) {
+    // sized for the lists' capacity, so that builds with more entries (up to
+    // g->cap) reuse it: freeing device memory waits for the whole device
+    size_t cap_bytes = 0;
+    GPF_HIP(sort_pairs(nullptr, cap_bytes, g->keys, g->keys_sorted, g->vals, g->cell_prims,
+                       (size_t)g->cap, 0, bits_needed, s));
+    sort_bytes = std::max(sort_bytes, cap_bytes);
     dev_free(g->sort_tmp, g->sort_tmp_bytes);
     g->sort_tmp = nullptr;
     g->sort_tmp_bytes = 0;
@@ -376,8 +391,8 @@ gpf_status launch_build_grid(gpf_grid* g, hipStream_t s) {
     g->sort_tmp_bytes = sort_bytes;
   }
   sort_bytes = g->sort_tmp_bytes;
-  GPF_HIP(rocprim::radix_sort_pairs(g->sort_tmp, sort_bytes, g->keys, g->keys_sorted, g->vals,
-                                    g->cell_prims, (size_t)E, 0, bits_needed, s));
+  GPF_HIP(sort_pairs(g->sort_tmp, sort_bytes, g->keys, g->keys_sorted, g->vals, g->cell_prims,
+                     (size_t)E, 0, bits_needed, s));
   hipLaunchKernelGGL(cell_start_kernel, dim3((nc + 256) / 256), dim3(256), 0, s, g->keys_sorted,
                      (int)E, nc, g->cell_start);
   GPF_HIP(hipGetLastError());

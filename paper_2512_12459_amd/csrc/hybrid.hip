@@ -24,10 +24,10 @@
 //    single-precision weight is exactly zero there whatever the Gaussian: the
 //    search only looks within D (cells of edge just over D/2, two rings), and
 //    nearest centres beyond D, which would add exact zeros, are left out.
-#include <rocprim/device/device_radix_sort.hpp>
 
 #include "pointgrid.h"
 #include "radiance_common.h"
+#include "sort.h"
 
 namespace gpf {
 namespace {
@@ -602,8 +602,8 @@ gpf_status build_centre_grid(gpf_grid* g, hipStream_t s) {
   // the sort's scratch depends on n and the key width: grown when needed
   const int bits = cell_key_bits(cells);
   size_t tb = 0;
-  GPF_HIP(rocprim::radix_sort_pairs(nullptr, tb, g->cg_key, g->cg_key + n, g->cg_val, g->cg_sorted,
-                                    (size_t)n, 0, bits, s));
+  GPF_HIP(sort_pairs(nullptr, tb, g->cg_key, g->cg_key + n, g->cg_val, g->cg_sorted, (size_t)n, 0,
+                     bits, s));
   if (g->cg_tmp_bytes < tb) {
     dev_free(g->cg_tmp, g->cg_tmp_bytes);
     g->cg_tmp = nullptr;
@@ -624,8 +624,8 @@ gpf_status build_centre_grid(gpf_grid* g, hipStream_t s) {
   hipLaunchKernelGGL(point_key_kernel, dim3(blocks), dim3(256), 0, s, g->mu, n, pg, g->cg_key,
                      g->cg_val);
   tb = g->cg_tmp_bytes;
-  GPF_HIP(rocprim::radix_sort_pairs(g->cg_tmp, tb, g->cg_key, g->cg_key + n, g->cg_val,
-                                    g->cg_sorted, (size_t)n, 0, bits, s));
+  GPF_HIP(sort_pairs(g->cg_tmp, tb, g->cg_key, g->cg_key + n, g->cg_val, g->cg_sorted, (size_t)n, 0,
+                     bits, s));
   hipLaunchKernelGGL(sorted_cell_starts_kernel, dim3((unsigned)((cells + 256) / 256)), dim3(256), 0,
                      s, g->cg_key + n, n, cells, g->cg_start);
   hipLaunchKernelGGL(centre_near_kernel, dim3((unsigned)((cells + 255) / 256)), dim3(256), 0, s,

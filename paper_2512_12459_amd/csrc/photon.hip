@@ -18,10 +18,12 @@
 // otherwise; a face stores (position, power, face) in slot event-1, then
 // continues when u0 < q = max(albedo) with power * albedo / q and a cosine
 // direction about the normal (azimuth 2 pi u1, sin^2 of the polar angle u2).
-#include <rocprim/device/device_radix_sort.hpp>
 #include <rocprim/device/device_scan.hpp>
 
+#include <algorithm>
+
 #include "common.h"
+#include "sort.h"
 #include "pointgrid.h"
 #include "scene.h"
 
@@ -406,6 +408,9 @@ gpf_status photon_map_fill(gpf_photon_map* m, const float* ppos, const float* pp
     m->cells_cap = cells;
   }
   if (m->np_cap < np) {
+    // with headroom: the stored-photon count varies from iteration to
+    // iteration, and freeing device memory waits for the whole device
+    const int64_t want = np + np / 8 + 1024;
     dev_free(m->rec, 2 * m->np_cap * sizeof(float4));
     dev_free(m->key, 2 * m->np_cap * 4);
     dev_free(m->val, m->np_cap * 4);
@@ -414,19 +419,19 @@ gpf_status photon_map_fill(gpf_photon_map* m, const float* ppos, const float* pp
     m->key = nullptr;
     m->val = m->sorted = nullptr;
     m->np_cap = 0;
-    if ((st = dev_alloc((void**)&m->rec, 2 * np * sizeof(float4), "photon records")) != GPF_OK ||
-        (st = dev_alloc((void**)&m->key, 2 * np * 4, "photon keys")) != GPF_OK ||
-        (st = dev_alloc((void**)&m->val, np * 4, "photon order")) != GPF_OK ||
-        (st = dev_alloc((void**)&m->sorted, np * 4, "photon order")) != GPF_OK) {
-      dev_free(m->rec, 2 * np * sizeof(float4));
-      dev_free(m->key, 2 * np * 4);
-      dev_free(m->val, np * 4);
+    if ((st = dev_alloc((void**)&m->rec, 2 * want * sizeof(float4), "photon records")) != GPF_OK ||
+        (st = dev_alloc((void**)&m->key, 2 * want * 4, "photon keys")) != GPF_OK ||
+        (st = dev_alloc((void**)&m->val, want * 4, "photon order")) != GPF_OK ||
+        (st = dev_alloc((void**)&m->sorted, want * 4, "photon order")) != GPF_OK) {
+      dev_free(m->rec, 2 * want * sizeof(float4));
+      dev_free(m->key, 2 * want * 4);
+      dev_free(m->val, want * 4);
       m->rec = nullptr;
       m->key = nullptr;
       m->val = nullptr;
       return st;
     }
-    m->np_cap = np;
+    m->np_cap = want;
   }
   // photons by cell: a stable radix sort of (cell, index), so each cell lists
   // its photons in index order and the gather's summation order does not
@@ -434,9 +439,12 @@ gpf_status photon_map_fill(gpf_photon_map* m, const float* ppos, const float* pp
   // crowded cells of a caustic cost nothing extra)
   const int bits = cell_key_bits(cells);
   size_t tb = 0;
-  GPF_HIP(rocprim::radix_sort_pairs(nullptr, tb, m->key, m->key + np, m->val, m->sorted, (size_t)np,
-                                    0, bits, s));
+  GPF_HIP(sort_pairs(nullptr, tb, m->key, m->key + np, m->val, m->sorted, (size_t)np, 0, bits, s));
   if (m->tmp_bytes < tb) {
+    size_t cap_bytes = 0;   // sized for the capacity, as the arrays above
+    GPF_HIP(sort_pairs(nullptr, cap_bytes, m->key, m->key + np, m->val, m->sorted,
+                       (size_t)m->np_cap, 0, bits, s));
+    tb = std::max(tb, cap_bytes);
     dev_free(m->tmp, m->tmp_bytes);
     m->tmp = nullptr;
     m->tmp_bytes = 0;
@@ -446,8 +454,7 @@ gpf_status photon_map_fill(gpf_photon_map* m, const float* ppos, const float* pp
   const unsigned pb = (unsigned)((np + 255) / 256);
   hipLaunchKernelGGL(point_key_kernel, dim3(pb), dim3(256), 0, s, ppos, np, g, m->key, m->val);
   tb = m->tmp_bytes;
-  GPF_HIP(rocprim::radix_sort_pairs(m->tmp, tb, m->key, m->key + np, m->val, m->sorted, (size_t)np,
-                                    0, bits, s));
+  GPF_HIP(sort_pairs(m->tmp, tb, m->key, m->key + np, m->val, m->sorted, (size_t)np, 0, bits, s));
   hipLaunchKernelGGL(sorted_cell_starts_kernel, dim3((unsigned)((cells + 256) / 256)), dim3(256), 0,
                      s, m->key + np, np, cells, m->start);
   hipLaunchKernelGGL(photon_gather_kernel, dim3(pb), dim3(256), 0, s, m->sorted, np, ppos, ppw,
