@@ -124,10 +124,11 @@ __device__ __forceinline__ bool ball_may_touch(const PrimRec& r, float bx, float
 // Visits the occupied cells of the primitive's cutoff box (or, with ball > 0,
 // of the box of its ball) that pass the whitened-frame (or ball) test; counts
 // them, or (kEmit) writes (cell slot, primitive) entries from `base` on.  The
-// box's cells are taken in (z, y, x) order by linear index, and sub-thread
-// `sub` of S takes indices sub, sub + S, ...; count and emit read the
-// same stored record and extents with the same split, so they make identical
-// decisions.
+// box is taken row by row (one row = the cells of one (y, z) along x; rows in
+// (z, y) order), sub-thread `sub` of S taking rows sub, sub + S, ...; within a
+// row the occupancy bits are read 32 cells at a time and only occupied cells
+// are tested, in ascending x.  Count and emit read the same stored record and
+// extents with the same split, so they make identical decisions.
 template <bool kEmit>
 __device__ __forceinline__ int visit_cells(const PrimRec& r, const float ext[3], const Geom& g,
                                            const uint32_t* __restrict__ bits,
@@ -146,36 +147,34 @@ __device__ __forceinline__ int visit_cells(const PrimRec& r, const float ext[3],
     if (a1 < -1e-3f || a0 > (float)d[a] + 1e-3f) return 0;  // box misses the grid
     lo[a] = max(0, (int)floorf(a0 - 1e-3f));
     hi[a] = min(d[a] - 1, (int)floorf(a1 + 1e-3f));
-    // clamping can leave an empty range (a box starting on the grid's far
-    // face); the stepping below needs at least one cell per axis
-    if (!(lo[a] <= hi[a])) return 0;
+    if (!(lo[a] <= hi[a])) return 0;   // a box starting on the grid's far face
   }
-  const int nx = hi[0] - lo[0] + 1, ny = hi[1] - lo[1] + 1;
-  // first index of this sub-thread, then steps of S along x with carries
-  int cx = lo[0] + sub % nx, cy = lo[1] + (sub / nx) % ny, cz = lo[2] + sub / (nx * ny);
+  const int ny = hi[1] - lo[1] + 1, rows = ny * (hi[2] - lo[2] + 1);
   const float hh = 0.5f * g.h;
   int cnt = 0;
-  while (cz <= hi[2]) {
-    const int dc = (cz * g.dy + cy) * g.dx + cx;
-    if ((bits[dc >> 5] >> (dc & 31)) & 1u) {
-      const float bx = o[0] + (cx + 0.5f) * g.h, by = o[1] + (cy + 0.5f) * g.h,
-                  bz = o[2] + (cz + 0.5f) * g.h;
-      const bool touch = ball > 0.f ? ball_may_touch(r, bx, by, bz, hh, ball)
-                                    : box_may_touch(r, bx, by, bz, hh, c2);
-      if (touch) {
-        if (kEmit && cnt < limit) {
-          keys[base + cnt] = occ_of_dense[dc];
-          vals[base + cnt] = pid;
+  for (int row = sub; row < rows; row += S) {
+    const int cy = lo[1] + row % ny, cz = lo[2] + row / ny;
+    const int row0 = (cz * g.dy + cy) * g.dx;          // dense index of x = 0
+    const int first = row0 + lo[0], last = row0 + hi[0];
+    const float by = o[1] + (cy + 0.5f) * g.h, bz = o[2] + (cz + 0.5f) * g.h;
+    for (int w = first >> 5; w <= (last >> 5); ++w) {
+      const int w0 = w << 5;
+      uint32_t word = bits[w];
+      if (first > w0) word &= ~0u << (first - w0);          // shift in [1, 31]
+      if (last < w0 + 31) word &= ~0u >> (w0 + 31 - last);  // shift in [1, 31]
+      while (word) {
+        const int dc = w0 + __builtin_ctz(word);
+        word &= word - 1;
+        const float bx = o[0] + (dc - row0 + 0.5f) * g.h;
+        const bool touch = ball > 0.f ? ball_may_touch(r, bx, by, bz, hh, ball)
+                                      : box_may_touch(r, bx, by, bz, hh, c2);
+        if (touch) {
+          if (kEmit && cnt < limit) {
+            keys[base + cnt] = occ_of_dense[dc];
+            vals[base + cnt] = pid;
+          }
+          ++cnt;
         }
-        ++cnt;
-      }
-    }
-    cx += S;
-    while (cx > hi[0]) {
-      cx -= nx;
-      if (++cy > hi[1]) {
-        cy = lo[1];
-        ++cz;
       }
     }
   }
