@@ -399,6 +399,7 @@ def main():
         bench_render(args)
         return
 
+    from paper_2512_12459_amd import probe
     from paper_2512_12459_amd import radiance as R
     from paper_2512_12459_amd import scenes as S
 
@@ -512,7 +513,7 @@ def main():
         pairs = int(torch.where(c >= 3, c, torch.full_like(c, min(3, n))).sum().item())
     else:
         pairs = grid.count_pairs()
-    valu_tflops = R.valu_probe()   # measured FP32 FMA ceiling of this device
+    valu_tflops = probe.valu_probe()   # measured FP32 FMA ceiling of this device
     log(f"measured FP32 FMA rate {valu_tflops:.1f} TFLOP/s")
     ginfo = grid.info()
     log(f"grid: {ginfo}; contributing pairs {pairs} ({pairs / q:.1f} per point)")

@@ -352,15 +352,6 @@ gpf_status gpf_camera_compose_backward(const float *dL_pix, int64_t n_pix, int s
  * m^2 <= cutoff^2.  Synchronises `stream`. */
 gpf_status gpf_count_pairs(const gpf_grid *grid, const gpf_field *f, int64_t *pairs, void *stream);
 
-/* ---- VALU ceiling probe (measurement helper, not part of the method) ------
- * Enqueues `blocks` workgroups of 256 threads; each thread runs iters x 64
- * independent FP32 fused multiply-adds (8 chains) and writes one float to
- * out[blocks * 256] (device, caller-owned, out_len >= blocks * 256).  The
- * work is blocks * 256 * iters * 128 flops; timing it on `stream` gives the
- * non-packed FP32 FMA rate the radiance kernels are compared with.
- * GPF_ERR_INVALID_ARGUMENT for blocks < 1, iters < 1 or a short buffer. */
-gpf_status gpf_valu_probe(float *out, int64_t out_len, int blocks, int iters, void *stream);
-
 /* ---- loss (Sec. 4.3 MSE over visible points) ------------------------------
  * loss_sum[0] (device, FP64) += sum_i sum_c (L - T)^2 over the q points and
  * dL[q][3] = 2 (L - T) / q.  The caller zeroes loss_sum; MSE = loss_sum / q. */

@@ -68,7 +68,6 @@ _SIG = {
     "gpf_eval_hybrid": (ctypes.c_int, [_P, ctypes.POINTER(Field), _P, _I64, _F, _P, _P, _P, _P]),
     "gpf_eval_hybrid_backward": (ctypes.c_int, [_P, ctypes.POINTER(Field), _P, _I64, _F, _P, _P, _P,
                                                 _P, ctypes.POINTER(FieldGrad), _P]),
-    "gpf_valu_probe": (ctypes.c_int, [_P, _I64, ctypes.c_int, ctypes.c_int, _P]),
     "gpf_trace_photons": (ctypes.c_int, [_I64, ctypes.c_uint64, ctypes.c_int, _F, _F, ctypes.c_int,
                                          _P, _P, _P, _P]),
     "gpf_compact_photons": (ctypes.c_int, [_P, _P, _P, _I64, _P, _P, _P, _P, _I64,

@@ -1,4 +1,5 @@
-"""Builds libgpf.so (all HIP kernels + the C ABI) for gfx950 with hipcc, in-tree.
+"""Builds libgpf.so (all HIP kernels + the C ABI) for gfx950 with hipcc, in-tree,
+and the separate measurement helper libgpf_probe.so.
 
 Usage: python -m paper_2512_12459_amd.build_lib [-j N]
 """
@@ -15,10 +16,12 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgpf.so")
+PROBE_LIB = os.path.join(HERE, "libgpf_probe.so")
+PROBE_SRC = os.path.join(CSRC, "probe", "valu_probe.hip")
 ARCH = "gfx950"
 
 SOURCES = ["capi.cpp", "capi_init.cpp", "bin_queries.hip", "grid.hip", "eval.hip", "optim.hip",
-           "mlp.hip", "init.hip", "probe.hip", "hybrid.hip", "photon.hip", "camera.hip"]
+           "mlp.hip", "init.hip", "hybrid.hip", "photon.hip", "camera.hip"]
 
 COMMON = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", f"-I{INCLUDE}", f"-I{CSRC}",
@@ -64,7 +67,23 @@ def build(jobs: int | None = None, verbose: bool = False, defines=(), out: str |
     os.replace(tmp, out)
     if verbose:
         print(f"built {out}")
+    if out == LIB:
+        build_probe(verbose)
     return out
+
+
+def build_probe(verbose: bool = False) -> str:
+    """The FP32 FMA-rate probe as its own shared library (not part of the
+    radiance library's ABI)."""
+    tmp = PROBE_LIB + ".tmp"
+    cmd = [hipcc(), *COMMON, "-shared", "-Wl,--no-undefined", "-o", tmp, PROBE_SRC]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"probe build failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, PROBE_LIB)
+    if verbose:
+        print(f"built {PROBE_LIB}")
+    return PROBE_LIB
 
 
 def build_host_sanitized(out_dir: str) -> str:

@@ -494,14 +494,6 @@ gpf_status gpf_camera_compose_backward(const float* dL_pix, int64_t n_pix, int s
                                         (hipStream_t)stream);
 }
 
-gpf_status gpf_valu_probe(float* out, int64_t out_len, int blocks, int iters, void* stream) {
-  if (!out) return set_error(GPF_ERR_INVALID_ARGUMENT, "out is NULL");
-  if (blocks < 1 || iters < 1) return set_error(GPF_ERR_INVALID_ARGUMENT, "blocks and iters must be >= 1");
-  if (out_len < (int64_t)blocks * 256)
-    return set_error(GPF_ERR_INVALID_ARGUMENT, "out holds fewer than blocks * 256 floats");
-  return launch_valu_probe(out, blocks, iters, (hipStream_t)stream);
-}
-
 gpf_status gpf_mse_loss(const float* L, const float* T, int64_t q, double* loss_sum, float* dL,
                         void* stream) {
   if (!L || !T || !loss_sum || !dL) return set_error(GPF_ERR_INVALID_ARGUMENT, "NULL argument");

@@ -199,7 +199,6 @@ gpf_status launch_camera_compose(const float* Le, int64_t n_pix, int S, const in
 gpf_status launch_camera_compose_backward(const float* dL, int64_t n_pix, int S,
                                           const int64_t* slot, const float* beta_c, int64_t m,
                                           float* dLq, hipStream_t s);
-gpf_status launch_valu_probe(float* out, int blocks, int iters, hipStream_t s);
 gpf_status launch_mse(const float* L, const float* T, int64_t q, double* loss, float* dL,
                       hipStream_t s);
 gpf_status launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr,

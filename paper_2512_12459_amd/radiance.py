@@ -303,19 +303,3 @@ def adam_step(p, g, m, v, step: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-1
     C.check(C.lib().gpf_adam_step(C.ptr(p), C.ptr(g), C.ptr(m), C.ptr(v), p.numel(), float(lr),
                                   float(beta1), float(beta2), float(eps), int(step),
                                   C.ptr(guard), _stream()))
-
-
-def valu_probe(blocks: int = 4096, iters: int = 2000, reps: int = 5) -> float:
-    """Measured non-packed FP32 FMA rate of the current device (TFLOP/s): the
-    mean over `reps` launches of the library's FMA stream, timed with events
-    on the current stream."""
-    out = torch.empty(blocks * 256, dtype=torch.float32, device="cuda")
-    C.check(C.lib().gpf_valu_probe(C.ptr(out), out.numel(), blocks, iters, _stream()))  # warm-up
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        C.check(C.lib().gpf_valu_probe(C.ptr(out), out.numel(), blocks, iters, _stream()))
-    e1.record()
-    e1.synchronize()
-    sec = e0.elapsed_time(e1) * 1e-3 / reps
-    return blocks * 256 * iters * 128 / sec / 1e12
