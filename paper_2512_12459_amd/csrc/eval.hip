@@ -232,8 +232,9 @@ constexpr int kRowStride = 14;                // transpose row stride (12 sums, 
 // 64 survivors (lane = primitive, cell entry ent) against the points [qb, qe) of the wave's
 // group, held in LDS (points past the group's count carry a zero upstream
 // gradient).  The 12 per-primitive sums are added to the padded per-primitive
-// buffer with row-coalesced atomics: after an LDS transpose, 16 lanes update
-// one 64-byte row per instruction.
+// buffer with row-coalesced atomics: after an LDS transpose (16 rows at a
+// time, so that the buffer stays small), 16 lanes update one 64-byte row per
+// instruction.
 __device__ __forceinline__ void bwd_chunk(int ent, bool valid, int qb, int qe,
                                           const PrimRec* __restrict__ cell_recs, float c2,
                                           const float2* qp, float* rw,
@@ -282,19 +283,24 @@ __device__ __forceinline__ void bwd_chunk(int ent, bool valid, int qb, int qe,
   // gradients once per primitive by the finalize pass
   const bool write = valid && any;
   const float sums[12] = {GP[0], GP[1], GP[2], A[0], A[1], A[2], U[0], U[1], U[2], U[3], U[4], U[5]};
-#pragma unroll
-  for (int e = 0; e < 12; ++e) rw[lane * kRowStride + e] = write ? sums[e] : 0.f;
-  rw[lane * kRowStride + 13] = __int_as_float(write ? id : -1);
-  wave_sync_lds();
-  // instruction rr covers rows 4 rr .. 4 rr + 3, 16 lanes each
   const int sub = lane >> 4, e = lane & 15;
+#pragma unroll
+  for (int h = 0; h < 4; ++h) {   // 16 rows at a time
+    if ((lane >> 4) == h) {
+      const int rl = lane & 15;
+#pragma unroll
+      for (int k = 0; k < 12; ++k) rw[rl * kRowStride + k] = write ? sums[k] : 0.f;
+      rw[rl * kRowStride + 13] = __int_as_float(write ? id : -1);
+    }
+    wave_sync_lds();
 #pragma unroll 4
-  for (int rr = 0; rr < 16; ++rr) {
-    const int row = rr * 4 + sub;
-    const int rid = __float_as_int(rw[row * kRowStride + 13]);
-    if (e < 12 && rid >= 0) unsafeAtomicAdd(grad_rows + (int64_t)rid * 16 + e, rw[row * kRowStride + e]);
+    for (int rr = 0; rr < 4; ++rr) {
+      const int row = rr * 4 + sub;
+      const int rid = __float_as_int(rw[row * kRowStride + 13]);
+      if (e < 12 && rid >= 0) unsafeAtomicAdd(grad_rows + (int64_t)rid * 16 + e, rw[row * kRowStride + e]);
+    }
+    wave_sync_lds();
   }
-  wave_sync_lds();
 }
 
 // Backward of one group of two consecutive tiles of one cell, run by one wave
@@ -347,15 +353,13 @@ __device__ __forceinline__ void bwd_group(const GroupInfo& gi, const TileCtx& ta
       }
     }
   } else {
-    // Software pipeline over the candidates in batches of 64: the records of
-    // batch b + 1 are requested before batch b is tested, so their latency
-    // overlaps the tests and the draining of full stacks.  Entries past the
-    // end repeat the cell's last one, keeping every load unconditional and in
-    // bounds.
-    PrimRec rec_c{};
-    if (cs < ce) rec_c = cell_recs[min(cs + lane, ce - 1)];
+    // The candidates in batches of 64.  Entries past the end repeat the
+    // cell's last one, keeping every load unconditional and in bounds.  (No
+    // prefetch of the next batch: its 16 registers would set the whole
+    // kernel's register count, and this path only runs where a group's list
+    // overflowed or no forward kept one.)
     for (int base = cs; base < ce; base += 64) {
-      const PrimRec rec_n = cell_recs[min(base + 64 + lane, ce - 1)];
+      const PrimRec rec_c = cell_recs[min(base + lane, ce - 1)];
       const int pid = base + lane;   // cell entry
       int mask = 0;
       if (base + lane < ce)
@@ -381,7 +385,6 @@ __device__ __forceinline__ void bwd_group(const GroupInfo& gi, const TileCtx& ta
         n2 -= 64;
         bwd_chunk(sv2[n2 + lane], true, 0, qe_all, cell_recs, c2, qp, rw, grad_rows, lane);
       }
-      rec_c = rec_n;
     }
   }
   const int total = n0 + n1 + n2;
@@ -414,8 +417,11 @@ __device__ __forceinline__ void put_point(float2* qp, int k, float x, float y, f
   qp[3 * k + 2] = make_float2(gy, gz);
 }
 
-// One wave per group; dL[q][3] in the points' original order.
-__global__ void __launch_bounds__(kBwdThreads) eval_bwd_kernel(
+// One wave per group; dL[q][3] in the points' original order.  Six waves per
+// SIMD: at most 80 VGPRs, and 5.5 KB of LDS per wave (points 3 KB, stacks
+// 1.5 KB, transpose rows 0.9 KB).
+__global__ void __launch_bounds__(kBwdThreads) __attribute__((amdgpu_waves_per_eu(6, 6)))
+eval_bwd_kernel(
     const float4* __restrict__ xs, const int* __restrict__ perm,
     const GroupInfo* __restrict__ groups, int ngroups, const float4* __restrict__ tlo,
     const float4* __restrict__ thi, const int* __restrict__ cell_start,
@@ -425,7 +431,7 @@ __global__ void __launch_bounds__(kBwdThreads) eval_bwd_kernel(
   static_assert(kGroupTiles == 2, "the backward splits survivors over the two tiles of a group");
   __shared__ int sv_all[kBwdWaves][3 * kListCap];
   __shared__ float2 qp_all[kBwdWaves][3 * kGroupQ];
-  __shared__ float rows_all[kBwdWaves][64 * kRowStride];
+  __shared__ float rows_all[kBwdWaves][16 * kRowStride];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int g = xcd_remap(blockIdx.x) * kBwdWaves + wave;
   if (g >= ngroups) return;  // per wave: no workgroup barrier follows
@@ -459,8 +465,9 @@ __global__ void __launch_bounds__(kBwdThreads) eval_bwd_kernel(
 // stored with their count, as the forward kernel does).
 // L is written in the original order; loss[0] += sum (L - T)^2 in FP64, one
 // atomic per group.  The forward's staging list shares LDS with the
-// backward's stacks.
-__global__ void __launch_bounds__(kBwdThreads) fit_pass_kernel(
+// backward's stacks; occupancy as for the backward kernel.
+__global__ void __launch_bounds__(kBwdThreads) __attribute__((amdgpu_waves_per_eu(6, 6)))
+fit_pass_kernel(
     const float4* __restrict__ xs, const int* __restrict__ perm,
     const GroupInfo* __restrict__ groups, int ngroups, const float4* __restrict__ tlo,
     const float4* __restrict__ thi, const int* __restrict__ cell_start,
@@ -471,7 +478,7 @@ __global__ void __launch_bounds__(kBwdThreads) fit_pass_kernel(
   static_assert(kFwdSurvCap <= 3 * kListCap, "the forward staging fits in the backward stacks");
   __shared__ int sv_all[kBwdWaves][3 * kListCap];
   __shared__ float2 qp_all[kBwdWaves][3 * kGroupQ];
-  __shared__ float rows_all[kBwdWaves][64 * kRowStride];
+  __shared__ float rows_all[kBwdWaves][16 * kRowStride];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int g = xcd_remap(blockIdx.x) * kBwdWaves + wave;
   if (g >= ngroups) return;  // per wave: no workgroup barrier follows
