@@ -432,7 +432,9 @@ eval_bwd_kernel(
   __shared__ int sv_all[kBwdWaves][3 * kListCap];
   __shared__ float2 qp_all[kBwdWaves][3 * kGroupQ];
   __shared__ float rows_all[kBwdWaves][16 * kRowStride];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  // wave-uniform (the compiler cannot see it): the group and everything
+  // derived from it live in scalar registers and the loops stay uniform
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int g = xcd_remap(blockIdx.x) * kBwdWaves + wave;
   if (g >= ngroups) return;  // per wave: no workgroup barrier follows
   const GroupInfo gi = groups[g];
@@ -479,7 +481,9 @@ fit_pass_kernel(
   __shared__ int sv_all[kBwdWaves][3 * kListCap];
   __shared__ float2 qp_all[kBwdWaves][3 * kGroupQ];
   __shared__ float rows_all[kBwdWaves][16 * kRowStride];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  // wave-uniform (the compiler cannot see it): the group and everything
+  // derived from it live in scalar registers and the loops stay uniform
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int g = xcd_remap(blockIdx.x) * kBwdWaves + wave;
   if (g >= ngroups) return;  // per wave: no workgroup barrier follows
   const GroupInfo gi = groups[g];
