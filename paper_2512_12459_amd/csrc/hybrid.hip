@@ -81,7 +81,7 @@ __global__ void __launch_bounds__(kHWaves * 64) hybrid_fwd_kernel(
     int* __restrict__ keep, int* __restrict__ keep_count) {
   static_assert(kGroupTiles == 2, "the forward pairs the two tiles of a group");
   __shared__ int surv[kHWaves][kHFwdCap];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int g = xcd_remap(blockIdx.x) * kHWaves + wave;
   if (g >= ngroups) return;
   const GroupInfo gi = groups[g];
@@ -318,15 +318,15 @@ __device__ __forceinline__ void hybrid_chunk(int id, bool valid, int qb, int qe,
   float GP[3] = {0.f, 0.f, 0.f}, A[3] = {0.f, 0.f, 0.f};
   float U[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   bool any = false;
-  for (int k = qb; k < qe; k += 4) {
-    float4 xq[4], gq[4];
+  for (int k = qb; k < qe; k += 2) {
+    float4 xq[2], gq[2];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < 2; ++i) {
       xq[i] = qx[k + i];
       gq[i] = qg[k + i];
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < 2; ++i) {
       const float dx = xq[i].x - r.r0.x, dy = xq[i].y - r.r0.y, dz = xq[i].z - r.r0.z;
       const bool in = sq_len(dx, dy, dz) <= r2;
       float u[3];
@@ -353,21 +353,30 @@ __device__ __forceinline__ void hybrid_chunk(int id, bool valid, int qb, int qe,
   }
   const bool write = valid && any;
   const float sums[12] = {GP[0], GP[1], GP[2], A[0], A[1], A[2], U[0], U[1], U[2], U[3], U[4], U[5]};
-#pragma unroll
-  for (int e = 0; e < 12; ++e) rw[lane * kHRowStride + e] = write ? sums[e] : 0.f;
-  rw[lane * kHRowStride + 13] = __int_as_float(write ? id : -1);
-  wave_sync_lds();
   const int sub = lane >> 4, e = lane & 15;
+#pragma unroll
+  for (int h = 0; h < 4; ++h) {   // 16 rows at a time through a small transpose buffer
+    if ((lane >> 4) == h) {
+      const int rl = lane & 15;
+#pragma unroll
+      for (int k = 0; k < 12; ++k) rw[rl * kHRowStride + k] = write ? sums[k] : 0.f;
+      rw[rl * kHRowStride + 13] = __int_as_float(write ? id : -1);
+    }
+    wave_sync_lds();
 #pragma unroll 4
-  for (int rr = 0; rr < 16; ++rr) {
-    const int row = rr * 4 + sub;
-    const int rid = __float_as_int(rw[row * kHRowStride + 13]);
-    if (e < 12 && rid >= 0) unsafeAtomicAdd(grad_rows + (int64_t)rid * 16 + e, rw[row * kHRowStride + e]);
+    for (int rr = 0; rr < 4; ++rr) {
+      const int row = rr * 4 + sub;
+      const int rid = __float_as_int(rw[row * kHRowStride + 13]);
+      if (e < 12 && rid >= 0) unsafeAtomicAdd(grad_rows + (int64_t)rid * 16 + e, rw[row * kHRowStride + e]);
+    }
+    wave_sync_lds();
   }
-  wave_sync_lds();
 }
 
-__global__ void __launch_bounds__(kHWaves * 64) hybrid_bwd_kernel(
+// Six waves per SIMD (at most 80 VGPRs; LDS per wave: points and their
+// upstream terms 4 KB, stacks 1.5 KB, transpose rows 0.9 KB).
+__global__ void __launch_bounds__(kHWaves * 64) __attribute__((amdgpu_waves_per_eu(6, 6)))
+hybrid_bwd_kernel(
     const float4* __restrict__ xs, const int* __restrict__ perm,
     const GroupInfo* __restrict__ groups, int ngroups, const float4* __restrict__ tlo,
     const float4* __restrict__ thi, const int* __restrict__ cell_start,
@@ -379,8 +388,8 @@ __global__ void __launch_bounds__(kHWaves * 64) hybrid_bwd_kernel(
   __shared__ int sv_all[kHWaves][3][kHListCap];
   __shared__ float4 qx_all[kHWaves][kHGroupQ];
   __shared__ float4 qg_all[kHWaves][kHGroupQ];
-  __shared__ float rows_all[kHWaves][64 * kHRowStride];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __shared__ float rows_all[kHWaves][16 * kHRowStride];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int g = xcd_remap(blockIdx.x) * kHWaves + wave;
   if (g >= ngroups) return;
   const GroupInfo gi = groups[g];
