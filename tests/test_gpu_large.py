@@ -123,6 +123,33 @@ def _zero_ambiguous(f, rows, sups, x, dL):
     return n
 
 
+def _fit_targets(L, dL_want):
+    """Targets T for the one-kernel fitting pass such that its upstream
+    gradient 2 (L - T) / q is dL_want up to FP32 rounding (exactly zero where
+    dL_want is), and that gradient as the pass forms it (FP32 difference, then
+    FP32 product with the FP32 scale)."""
+    scale = np.float32(2.0 / L.shape[0])
+    T = (L - dL_want / scale).astype(np.float32)
+    zero = dL_want == 0
+    T[zero] = L[zero]
+    dL = scale * (L - T)
+    assert dL.dtype == np.float32 and np.all(dL[zero] == 0)
+    return T, dL
+
+
+def _check_fit_pass(R, g, dev, L, T, rows):
+    """Runs the fitting pass on the grid's build: L bit for bit as the forward
+    wrote it, the loss sum against the FP64 sum of the FP32 differences, and
+    the gradient rows (returned)."""
+    Lf, loss, grads = R.fit_pass(g, *dev, torch.from_numpy(T).cuda())
+    torch.cuda.synchronize()
+    assert np.array_equal(Lf.cpu().numpy().view(np.int32), L.view(np.int32))
+    d = (L - T).astype(np.float64)
+    want = float(np.sum(d * d))
+    assert abs(loss.item() - want) <= 1e-9 * want, (loss.item(), want)   # FP64 order only
+    return {k: v.cpu().numpy()[rows] for k, v in grads.items()}
+
+
 def test_caustic1m_full_size_forward_and_backward_rows(R):
     f, x = S.workload("caustic1m")
     q = x.shape[0]
@@ -142,12 +169,17 @@ def test_caustic1m_full_size_forward_and_backward_rows(R):
     sups = _row_supports(index, f, rows)
     dL = rng.normal(size=(q, 3)).astype(np.float32)
     n_amb = _zero_ambiguous(f, rows, sups, x, dL)
+    Lh = L.cpu().numpy()
+    T, dL = _fit_targets(Lh, dL)
     say(f"case: caustic1m backward rows, {len(rows)} primitives, "
         f"{sum(len(sp) for sp in sups)} support points ({n_amb} on a cutoff)")
     grads = R.eval_radiance_backward(g, *dev, torch.from_numpy(dL).cuda())
     torch.cuda.synchronize()
     gg = {k: v.cpu().numpy()[rows] for k, v in grads.items()}
-    check_grads(gg, _rows_gradient_ref(f, rows, sups, x, dL))
+    gref = _rows_gradient_ref(f, rows, sups, x, dL)
+    check_grads(gg, gref)
+    say("case: caustic1m one-kernel fitting pass (the bench's step), same rows")
+    check_grads(_check_fit_pass(R, g, dev, Lh, T, rows), gref)
 
 
 def test_fit200k_subset_gradient_and_finite_differences(R):
@@ -261,6 +293,8 @@ def test_stress4m_full_size_forward_and_backward_rows(R):
     sups = _row_supports(index, f, rows)
     dL = rng.normal(size=(q, 3)).astype(np.float32)
     n_amb = _zero_ambiguous(f, rows, sups, x, dL)
+    Lh = L.cpu().numpy()
+    T, dL = _fit_targets(Lh, dL)
     say(f"case: stress4m backward rows, {len(rows)} primitives (max rho {rho[rows].max():.1f}), "
         f"{sum(len(sp) for sp in sups)} support points ({n_amb} on a cutoff)")
     grads = R.eval_radiance_backward(g, *dev, torch.from_numpy(dL).cuda())
@@ -268,11 +302,14 @@ def test_stress4m_full_size_forward_and_backward_rows(R):
     say(f"  torch peak after the backward {torch.cuda.max_memory_allocated()}, "
         f"grid bytes {g.info()['device_bytes']}")
     gg = {k: v.cpu().numpy()[rows] for k, v in grads.items()}
+    del grads
     gref = _rows_gradient_ref(f, rows, sups, x, dL)
     check_grads(gg, gref)
     for k in gg:
         err = np.linalg.norm(gg[k] - gref[k]) / np.linalg.norm(gref[k])
         say(f"  stress4m {k}: group 2-norm relative error {err:.3g}")
+    say("case: stress4m one-kernel fitting pass (the bench's step), same rows")
+    check_grads(_check_fit_pass(R, g, dev, Lh, T, rows), gref)
 
 
 def test_caustic1m_hybrid_query_full_size(R):
