@@ -202,3 +202,102 @@ class Fitter:
             self.t = int(z["step"])
             self.lr = {str(k): float(v) for k, v in zip(z["lr_keys"], z["lr_vals"])}
         return self
+
+
+class ViewBatchFitter(Fitter):
+    """Fits ``field`` with a random subset of the camera views per step (the
+    paper's training samples the supervised points from randomly selected
+    views at each iteration, supplementary Sec. A.2).  ``x`` [q,3] and ``T``
+    [q,3] hold the views' points one view after another, view v owning
+    ``view_sizes[v]`` consecutive rows.  Each view gets its own binned query
+    set and grid, built once; a step draws ``views_per_step`` distinct views
+    (numpy generator seeded with ``seed``), runs the fitting pass on each into
+    the same gradient and loss sum, then one Adam update.  Every selected
+    view's loss is its own mean, dL = 2 (L - T) / q_view, so views of equal
+    size weigh equally.  Truncated query only."""
+
+    def __init__(self, field: Field, x: torch.Tensor, T: torch.Tensor, view_sizes, views_per_step: int,
+                 lr=None, cutoff: float = 3.0, cell: float = 0.025, seed: int = 0):
+        sizes = [int(v) for v in view_sizes]
+        if sum(sizes) != x.shape[0] or x.shape != T.shape or min(sizes) < 1:
+            raise ValueError("view sizes must partition the points of x and T")
+        if not 1 <= views_per_step <= len(sizes):
+            raise ValueError(f"views_per_step must lie in [1, {len(sizes)}]")
+        self.f = field
+        self.T = T
+        self.q = T.shape[0]
+        self.lr = dict(DEFAULT_LR if lr is None else lr)
+        self.hybrid = False
+        self.fused = True
+        self.k = views_per_step
+        self.rng = np.random.default_rng(seed)
+        off = np.concatenate([[0], np.cumsum(sizes)])
+        self.xv = [x[a:b] for a, b in zip(off[:-1], off[1:])]
+        self.Tv = [T[a:b] for a, b in zip(off[:-1], off[1:])]
+        self.qsv = [R.QuerySet(xv, cell) for xv in self.xv]
+        self.gridv = [R.Grid(qs, cutoff) for qs in self.qsv]
+        self.Lv = [torch.empty_like(t) for t in self.Tv]
+        self.qs = self.qsv[0]
+        self.grid = self.gridv[0]
+        self.L = self.Lv[0]
+        self.dL = torch.empty_like(self.Lv[0])
+        self.loss = torch.zeros(1, dtype=torch.float64, device=T.device)
+        self.t = 0
+        self.peak = float(T.max().item())
+        self.q_batch = 0
+        self.last_views = []
+
+    def accumulate(self, views=None):
+        """The fitting passes of one step into the field's zeroed gradient and
+        the loss sum, over ``views`` (default: a fresh random draw)."""
+        f = self.f
+        if views is None:
+            views = sorted(self.rng.choice(len(self.xv), self.k, replace=False).tolist())
+        self.loss.zero_()
+        f.G.zero_()
+        for v in views:
+            self.gridv[v].build(*f.arrays())
+            R.fit_pass(self.gridv[v], *f.arrays(), self.Tv[v], L=self.Lv[v], loss_sum=self.loss,
+                       grads=f.g)
+        self.last_views = list(views)
+        self.q_batch = sum(self.xv[v].shape[0] for v in views)
+
+    def step(self):
+        f = self.f
+        self.accumulate()
+        self.t += 1
+        for k, _ in Field.GROUPS:
+            R.adam_step(f.p[k], f.g[k], f.m[k], f.v[k], self.t, self.lr[k], guard=self.loss)
+
+    def mse(self) -> float:
+        """Per-element mean squared error over the last step's views (before
+        its update)."""
+        return self.loss.item() / (3 * max(self.q_batch, 1))
+
+    def current_psnr(self) -> float:
+        """PSNR of the current parameters over every view (one forward each)."""
+        f = self.f
+        total = torch.zeros(1, dtype=torch.float64, device=self.T.device)
+        for v in range(len(self.xv)):
+            self.gridv[v].build(*f.arrays())
+            R.eval_radiance(self.gridv[v], *f.arrays(), out=self.Lv[v])
+            R.mse_loss(self.Lv[v], self.Tv[v], dL=torch.empty_like(self.Lv[v]), loss_sum=total)
+        return psnr_from_mse(total.item() / (3 * self.q), self.peak)
+
+    def save(self, path: str):
+        """As Fitter.save, plus the view generator's state (JSON text), so a
+        resumed run draws the views the uninterrupted one would."""
+        f = self.f
+        torch.cuda.synchronize()
+        np.savez(path, n=np.int64(f.n), step=np.int64(self.t), query=np.array("truncated"),
+                 lr_keys=np.array([k for k, _ in Field.GROUPS]),
+                 lr_vals=np.array([self.lr[k] for k, _ in Field.GROUPS], np.float64),
+                 P=f.P.cpu().numpy(), M=f.M.cpu().numpy(), V=f.V.cpu().numpy(),
+                 view_rng=np.array(json.dumps(self.rng.bit_generator.state)))
+
+    def load(self, path: str):
+        super().load(path)
+        with np.load(path, allow_pickle=False) as z:
+            if "view_rng" in z:
+                self.rng.bit_generator.state = json.loads(str(z["view_rng"]))
+        return self
