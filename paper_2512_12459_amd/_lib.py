@@ -130,4 +130,12 @@ def check(status: int):
 
 
 def ptr(t) -> int | None:
-    return None if t is None else int(t.data_ptr())
+    """Device address of a tensor for the library (every pointer the library
+    takes through this binding is a device pointer); a host tensor is refused
+    here rather than handed to a kernel."""
+    if t is None:
+        return None
+    if t.device.type != "cuda":
+        raise ValueError(f"a {tuple(t.shape)} {t.dtype} tensor on {t.device} was passed where "
+                         "the library needs device memory")
+    return int(t.data_ptr())

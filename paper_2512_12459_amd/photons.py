@@ -28,10 +28,12 @@ def photon_knn(pos: torch.Tensor, k: int):
 def photon_features(pos, power, idx, d2) -> torch.Tensor:
     """[p,96] bfloat16 network inputs (returned as torch.bfloat16)."""
     _need(pos, "pos", 3)
-    _need(power, "power", 3)
-    if idx.shape[1] != 16 or idx.dtype != torch.int32 or not idx.is_contiguous():
-        raise ValueError("idx must be contiguous int32 [p,16]")
     p = pos.shape[0]
+    _need(power, "power", 3, rows=p)
+    if (idx.dim() != 2 or tuple(idx.shape) != (p, 16) or idx.dtype != torch.int32
+            or not idx.is_contiguous() or idx.device.type != "cuda"):
+        raise ValueError("idx must be contiguous int32 [p,16] on the GPU")
+    _need(d2, "d2", 16, rows=p)
     X = torch.empty((p, N_IN), dtype=torch.bfloat16, device=pos.device)
     C.check(C.lib().gpf_photon_features(C.ptr(pos), C.ptr(power), p, C.ptr(idx), C.ptr(d2),
                                         C.ptr(X), _stream()))
@@ -69,7 +71,7 @@ class MLP:
     def gradient(self, X: torch.Tensor, T: torch.Tensor):
         """(grad [n_params], sum of squared errors) of mean((Y - T)^2)."""
         self._need_x(X)
-        _need(T, "T", N_OUT)
+        _need(T, "T", N_OUT, rows=X.shape[0])
         g = torch.empty(self.n_params, dtype=torch.float32, device=X.device)
         ls = torch.zeros(1, dtype=torch.float64, device=X.device)
         C.check(C.lib().gpf_mlp_gradient(self.handle, C.ptr(X), C.ptr(T), X.shape[0], C.ptr(g),
@@ -79,7 +81,10 @@ class MLP:
     def train_step(self, X: torch.Tensor, T: torch.Tensor, lr: float,
                    loss_sum: torch.Tensor | None = None):
         self._need_x(X)
-        _need(T, "T", N_OUT)
+        _need(T, "T", N_OUT, rows=X.shape[0])
+        if loss_sum is not None and (loss_sum.dtype != torch.float64 or loss_sum.numel() < 1
+                                     or loss_sum.device.type != "cuda"):
+            raise ValueError("loss_sum must be a float64 device tensor")
         C.check(C.lib().gpf_mlp_train_step(self.handle, C.ptr(X), C.ptr(T), X.shape[0], float(lr),
                                             C.ptr(loss_sum) if loss_sum is not None else None,
                                             _stream()))
@@ -107,8 +112,8 @@ def init_from_photons(pos: torch.Tensor, power: torch.Tensor, k: int = 16,
                       mlp: MLP | None = None):
     """(mu, quat, log_scale, rgb) device tensors, one Gaussian per photon."""
     _need(pos, "pos", 3)
-    _need(power, "power", 3)
     p = pos.shape[0]
+    _need(power, "power", 3, rows=p)
     dev = pos.device
     out = (torch.empty((p, 3), device=dev), torch.empty((p, 4), device=dev),
            torch.empty((p, 3), device=dev), torch.empty((p, 3), device=dev))

@@ -16,7 +16,7 @@ def _stream():
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
-def _need(t, name, cols):
+def _need(t, name, cols, rows=None):
     if not isinstance(t, torch.Tensor):
         raise TypeError(f"{name} must be a torch tensor")
     if t.device.type != "cuda":
@@ -25,8 +25,21 @@ def _need(t, name, cols):
         raise ValueError(f"{name} must be float32")
     if t.dim() != 2 or t.shape[1] != cols:
         raise ValueError(f"{name} must have shape [n, {cols}], got {tuple(t.shape)}")
+    if rows is not None and t.shape[0] != rows:
+        raise ValueError(f"{name} must have {rows} rows, got {t.shape[0]}")
     if not t.is_contiguous():
         raise ValueError(f"{name} must be contiguous")
+
+
+def _grad_struct(grads, mu, quat, log_scale, rgb) -> "C.FieldGrad":
+    """Gradient buffers (a dict of tensors shaped like the field's), checked
+    before their pointers reach the library."""
+    for k, like in (("mu", mu), ("quat", quat), ("log_scale", log_scale), ("rgb", rgb)):
+        if k not in grads:
+            raise ValueError(f"grads lacks {k!r}")
+        _need(grads[k], f"grads[{k!r}]", like.shape[1], rows=like.shape[0])
+    return C.FieldGrad(C.ptr(grads["mu"]), C.ptr(grads["quat"]), C.ptr(grads["log_scale"]),
+                       C.ptr(grads["rgb"]))
 
 
 def field_struct(mu, quat, log_scale, rgb) -> C.Field:
@@ -130,7 +143,7 @@ def eval_radiance(grid: Grid, mu, quat, log_scale, rgb, out: torch.Tensor | None
     x = grid.queries.x
     if out is None:
         out = torch.empty((x.shape[0], 3), device=x.device, dtype=torch.float32)
-    _need(out, "L", 3)
+    _need(out, "L", 3, rows=x.shape[0])
     C.check(C.lib().gpf_eval_radiance(grid.handle, ctypes.byref(fs), C.ptr(x), x.shape[0],
                                       C.ptr(out), _stream()))
     return out
@@ -141,12 +154,11 @@ def eval_radiance_backward(grid: Grid, mu, quat, log_scale, rgb, dL, grads=None)
     zero-initialised tensors shaped like the field, allocated if None)."""
     fs = field_struct(mu, quat, log_scale, rgb)
     x = grid.queries.x
-    _need(dL, "dL", 3)
+    _need(dL, "dL", 3, rows=x.shape[0])
     if grads is None:
         grads = dict(mu=torch.zeros_like(mu), quat=torch.zeros_like(quat),
                      log_scale=torch.zeros_like(log_scale), rgb=torch.zeros_like(rgb))
-    gs = C.FieldGrad(C.ptr(grads["mu"]), C.ptr(grads["quat"]), C.ptr(grads["log_scale"]),
-                     C.ptr(grads["rgb"]))
+    gs = _grad_struct(grads, mu, quat, log_scale, rgb)
     C.check(C.lib().gpf_eval_radiance_backward(grid.handle, ctypes.byref(fs), C.ptr(x), x.shape[0],
                                                C.ptr(dL), ctypes.byref(gs), _stream()))
     return grads
@@ -160,21 +172,19 @@ def fit_pass(grid: Grid, mu, quat, log_scale, rgb, T, L=None, loss_sum=None, gra
     if None).  Returns (L, loss_sum, grads)."""
     fs = field_struct(mu, quat, log_scale, rgb)
     x = grid.queries.x
-    _need(T, "T", 3)
-    if T.shape[0] != x.shape[0]:
-        raise ValueError(f"T holds {T.shape[0]} points, the query set {x.shape[0]}")
+    _need(T, "T", 3, rows=x.shape[0])
     if L is None:
         L = torch.empty_like(T)
-    _need(L, "L", 3)
+    _need(L, "L", 3, rows=x.shape[0])
     if loss_sum is None:
         loss_sum = torch.zeros(1, dtype=torch.float64, device=T.device)
-    if loss_sum.dtype != torch.float64 or loss_sum.device.type != "cuda":
+    if (loss_sum.dtype != torch.float64 or loss_sum.device.type != "cuda"
+            or loss_sum.numel() < 1):
         raise ValueError("loss_sum must be a float64 device tensor")
     if grads is None:
         grads = dict(mu=torch.zeros_like(mu), quat=torch.zeros_like(quat),
                      log_scale=torch.zeros_like(log_scale), rgb=torch.zeros_like(rgb))
-    gs = C.FieldGrad(C.ptr(grads["mu"]), C.ptr(grads["quat"]), C.ptr(grads["log_scale"]),
-                     C.ptr(grads["rgb"]))
+    gs = _grad_struct(grads, mu, quat, log_scale, rgb)
     C.check(C.lib().gpf_fit_pass(grid.handle, ctypes.byref(fs), C.ptr(x), x.shape[0], C.ptr(T),
                                  C.ptr(L), C.ptr(loss_sum), ctypes.byref(gs), _stream()))
     return L, loss_sum, grads
@@ -239,16 +249,16 @@ def eval_hybrid_backward(grid: HybridGrid, mu, quat, log_scale, rgb, L, Z, count
     forward's L, Z and count."""
     fs = field_struct(mu, quat, log_scale, rgb)
     x = grid.queries.x
-    _need(dL, "dL", 3)
-    _need(L, "L", 3)
+    _need(dL, "dL", 3, rows=x.shape[0])
+    _need(L, "L", 3, rows=x.shape[0])
     for t, name, dt in ((Z, "Z", torch.float32), (count, "count", torch.int32)):
-        if t.dtype != dt or not t.is_contiguous() or t.shape != (x.shape[0],):
-            raise ValueError(f"{name} must be a contiguous [q] {dt} tensor")
+        if (t.dtype != dt or not t.is_contiguous() or t.shape != (x.shape[0],)
+                or t.device.type != "cuda"):
+            raise ValueError(f"{name} must be a contiguous [q] {dt} device tensor")
     if grads is None:
         grads = dict(mu=torch.zeros_like(mu), quat=torch.zeros_like(quat),
                      log_scale=torch.zeros_like(log_scale), rgb=torch.zeros_like(rgb))
-    gs = C.FieldGrad(C.ptr(grads["mu"]), C.ptr(grads["quat"]), C.ptr(grads["log_scale"]),
-                     C.ptr(grads["rgb"]))
+    gs = _grad_struct(grads, mu, quat, log_scale, rgb)
     C.check(C.lib().gpf_eval_hybrid_backward(grid.handle, ctypes.byref(fs), C.ptr(x), x.shape[0],
                                              getattr(grid, "eps", 1e-6), C.ptr(L), C.ptr(Z),
                                              C.ptr(count), C.ptr(dL),
@@ -280,11 +290,15 @@ def mse_loss(L: torch.Tensor, T: torch.Tensor, dL: torch.Tensor | None = None,
              loss_sum: torch.Tensor | None = None):
     """Returns (loss_sum [1] float64 device tensor, dL); MSE = loss_sum / q."""
     _need(L, "L", 3)
-    _need(T, "T", 3)
+    _need(T, "T", 3, rows=L.shape[0])
     if dL is None:
         dL = torch.empty_like(L)
+    _need(dL, "dL", 3, rows=L.shape[0])
     if loss_sum is None:
         loss_sum = torch.zeros(1, dtype=torch.float64, device=L.device)
+    if (loss_sum.dtype != torch.float64 or loss_sum.device.type != "cuda"
+            or loss_sum.numel() < 1):
+        raise ValueError("loss_sum must be a float64 device tensor")
     C.check(C.lib().gpf_mse_loss(C.ptr(L), C.ptr(T), L.shape[0], C.ptr(loss_sum), C.ptr(dL),
                                  _stream()))
     return loss_sum, dL

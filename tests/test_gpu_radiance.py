@@ -342,6 +342,35 @@ def test_fit_pass_matches_separate_calls_and_the_oracle(rad, c1, case):
     check_grads(g_after, gref)
 
 
+def test_binding_rejects_mismatched_buffers(rad, c1):
+    """Buffers whose size does not match the grid's points or the field, and
+    host tensors, are refused before any pointer reaches the library."""
+    f, x, _ = c1
+    L, g, dev, qs = _eval(rad, f.arrays(), x)
+    q = x.shape[0]
+    good = torch.zeros((q, 3), device="cuda")
+    say("case: binding argument checks")
+    with pytest.raises(ValueError):
+        rad.eval_radiance(g, *dev, out=torch.empty((q - 1, 3), device="cuda"))
+    with pytest.raises(ValueError):
+        rad.eval_radiance_backward(g, *dev, good[:-1].contiguous())
+    short = {k: torch.zeros_like(v) for k, v in zip(("mu", "quat", "log_scale", "rgb"), dev)}
+    short["rgb"] = torch.zeros((dev[3].shape[0] - 1, 3), device="cuda")
+    with pytest.raises(ValueError):
+        rad.eval_radiance_backward(g, *dev, good, grads=short)
+    with pytest.raises(ValueError):
+        rad.fit_pass(g, *dev, good, grads=short)
+    with pytest.raises(ValueError):
+        rad.fit_pass(g, *dev, torch.zeros((q + 1, 3), device="cuda"))
+    with pytest.raises(ValueError):
+        rad.fit_pass(g, *dev, good.cpu())
+    with pytest.raises(ValueError):
+        rad.mse_loss(good, good, dL=torch.empty((q - 1, 3), device="cuda"))
+    # the calls above changed nothing: a correct one still matches the forward
+    L2, _, _ = rad.fit_pass(g, *dev, good)
+    assert np.array_equal(L2.cpu().numpy().view(np.int32), L.view(np.int32))
+
+
 def test_autograd_function_matches_direct_call(rad):
     mu, q, ls, rgb, x = _grad_problem(6, 200, 1000, 0.15)
     dev = [t.clone().requires_grad_(True) for t in to_dev(mu, q, ls, rgb)]
