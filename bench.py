@@ -78,6 +78,25 @@ def measured_traffic(kernel: str, workload: str, default_shape: bool, hybrid: bo
     return None if k is None else float(k["hbm_bytes"])
 
 
+def copy_bandwidth(nbytes: int = 1 << 30, reps: int = 5) -> float:
+    """Measured HBM copy rate (GB/s, bytes read + written) of a plain
+    device-to-device copy of ``nbytes``, timed with events on the current
+    stream: the bandwidth ceiling beside the published 8 TB/s."""
+    import torch
+    a = torch.empty(nbytes // 4, device="cuda")
+    b = torch.ones(nbytes // 4, device="cuda")
+    a.copy_(b)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        a.copy_(b)
+    e1.record()
+    e1.synchronize()
+    sec = e0.elapsed_time(e1) * 1e-3 / reps
+    del a, b
+    return 2 * nbytes / sec / 1e9
+
+
 def cpu_baseline(field, x, sample: int, seed: int = 11, hybrid: bool = False):
     """The FP64 oracle (brute force over all primitives) forward + backward on
     a bounded random sample of query points, over a process pool."""
@@ -515,6 +534,10 @@ def main():
         pairs = grid.count_pairs()
     valu_tflops = probe.valu_probe()   # measured FP32 FMA ceiling of this device
     log(f"measured FP32 FMA rate {valu_tflops:.1f} TFLOP/s")
+    peak_before_copy = torch.cuda.max_memory_allocated()
+    copy_gbs = copy_bandwidth()          # measured device-to-device copy rate
+    torch.cuda.reset_peak_memory_stats()  # the copy's 2 GiB are not the path's memory
+    log(f"measured copy bandwidth {copy_gbs:.0f} GB/s")
     ginfo = grid.info()
     log(f"grid: {ginfo}; contributing pairs {pairs} ({pairs / q:.1f} per point)")
     torch.cuda.synchronize()
@@ -565,7 +588,7 @@ def main():
         "pairs_per_query": pairs / q,
         "loss": loss_v,
         "device_bytes": {"queries": qinfo["device_bytes"], "grid": ginfo["device_bytes"],
-                         "torch_peak": torch.cuda.max_memory_allocated()},
+                         "torch_peak": max(peak_before_copy, torch.cuda.max_memory_allocated())},
         "roofline": {"bound": "alu", "kernel": kname,
                      "achieved": achieved / 1e12,
                      "peak": PEAK_FP32_VALU / 1e12, "unit": "TFLOP/s",
@@ -576,6 +599,7 @@ def main():
                                                  and (not hybrid or args.radius == 0.02), hybrid),
                      "traffic_unit": "bytes per launch",
                      "measured_valu_ceiling": valu_tflops,
+                     "measured_copy_gbs": copy_gbs,
                      "frac_of_measured_ceiling": achieved / 1e12 / valu_tflops,
                      "flops_per_pair": fl_pair},
     }
