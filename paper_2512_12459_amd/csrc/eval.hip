@@ -10,7 +10,10 @@
 //  - backward: one wave per group, lane = survivor (64 at a time), looping
 //              over the group's points broadcast from LDS; the 12 sums per
 //              primitive are added to padded rows with row-coalesced atomics
-//              and mapped to parameter gradients once per primitive.
+//              and mapped to parameter gradients once per primitive;
+//  - fitting pass: one wave per group runs the forward, the squared error
+//              against the targets and the backward with the resulting
+//              upstream gradient, over the survivors it has just kept.
 // Weights are recomputed in the backward; nothing per pair is stored.
 #include <mutex>
 
