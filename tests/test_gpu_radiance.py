@@ -494,6 +494,20 @@ def test_device_byte_budget(rad):
         assert torch.equal(L, L_ref)
         assert g.info()["device_bytes"] < g_ref.info()["device_bytes"]  # g keeps no lists
         check_grads({k: v.cpu().numpy() for k, v in grads.items()}, gref)
+        say("case: fitting pass without survivor lists (its backward half culls)")
+        Lh = L.cpu().numpy()
+        scale = np.float32(2.0 / len(x))
+        T = (Lh - dL / scale).astype(np.float32)
+        T[dL == 0] = Lh[dL == 0]
+        dL_pass = scale * (Lh - T)
+        os.environ[key] = "1"
+        g.build(*dev)
+        L2, _, g2 = rad.fit_pass(g, *dev, torch.from_numpy(T).cuda())
+        torch.cuda.synchronize()
+        del os.environ[key]
+        assert torch.equal(L2, L_ref)
+        check_grads({k: v.cpu().numpy() for k, v in g2.items()},
+                    O.radiance_backward(mu, q, ls, rgb, x, dL_pass))
     finally:
         os.environ.pop(key, None)
 
