@@ -364,8 +364,8 @@ def bench_render(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="caustic1m")
     ap.add_argument("--views", type=int, default=None)
     ap.add_argument("--res", type=int, default=None)
@@ -527,11 +527,16 @@ def main():
     for t in range(1, args.warmup + 1):
         step(t, False)
     torch.cuda.synchronize()
-    if hybrid:   # neighbourhood pairs: the ball, or min(3, n) nearest centres
-        c = fwd_out["count"].to(torch.int64)
-        pairs = int(torch.where(c >= 3, c, torch.full_like(c, min(3, n))).sum().item())
-    else:
-        pairs = grid.count_pairs()
+
+    def count_pairs():
+        """Contributing pairs of the current build (the field moves during
+        the timed steps, so they are counted before and after)."""
+        if hybrid:   # neighbourhood pairs: the ball, or min(3, n) nearest centres
+            c = fwd_out["count"].to(torch.int64)
+            return int(torch.where(c >= 3, c, torch.full_like(c, min(3, n))).sum().item())
+        return grid.count_pairs()
+
+    pairs_first = pairs = count_pairs()
     valu_tflops = probe.valu_probe()   # measured FP32 FMA ceiling of this device
     log(f"measured FP32 FMA rate {valu_tflops:.1f} TFLOP/s")
     peak_before_copy = torch.cuda.max_memory_allocated()
@@ -551,6 +556,8 @@ def main():
     ms = {k: float(np.mean([a.elapsed_time(b) for a, b in v])) for k, v in ev.items()}
     step_ms = wall / args.steps * 1e3
     loss_v = loss.item() / q
+    pairs_last = count_pairs()
+    pairs = (pairs_first + pairs_last) // 2   # the timed steps' mean, to first order
     value = q / (step_ms * 1e-3)
     fl_fwd, fl_bwd = (FLOPS_FWD_HYBRID, FLOPS_BWD_HYBRID) if hybrid else (FLOPS_FWD, FLOPS_BWD)
     if fused:   # one kernel runs forward, loss and backward
@@ -585,6 +592,7 @@ def main():
         "fwd_bwd_queries_per_s": q / (fb_ms * 1e-3),
         "kernel_ms": ms,
         "pairs": pairs,
+        "pairs_first_last": [pairs_first, pairs_last],
         "pairs_per_query": pairs / q,
         "loss": loss_v,
         "device_bytes": {"queries": qinfo["device_bytes"], "grid": ginfo["device_bytes"],
