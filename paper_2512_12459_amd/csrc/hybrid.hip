@@ -14,8 +14,9 @@
 // Work decomposition:
 //  - the grid lists, per occupied query cell, the Gaussians whose ball may
 //    reach the cell.  The ball part runs like the truncated kernels: one wave
-//    per group of two tiles, forward lane = point over survivors read with
-//    scalar loads, backward lane = Gaussian over the group's points in LDS;
+//    per group of two tiles, forward lane = point over survivors whose
+//    records are staged in LDS and read back into vector registers,
+//    backward lane = Gaussian over the group's points in LDS;
 //    psi = 1 inside the ball, so only the Gaussian factor varies;
 //  - points whose ball holds fewer than k_min centres are finished by a
 //    thread-per-point pass that searches a uniform grid over the centres in
@@ -33,7 +34,6 @@ namespace gpf {
 namespace {
 
 constexpr int kHWaves = 4;         // waves (groups) per workgroup
-constexpr int kHFwdCap = 256;      // staged survivors per wave (forward)
 constexpr int kHListCap = 128;     // survivor slots per stack and wave (backward)
 constexpr int kHRowStride = 14;    // transpose row stride (12 sums, pad, row id)
 constexpr int kHGroupQ = kTile * kGroupTiles;
@@ -80,7 +80,7 @@ __global__ void __launch_bounds__(kHWaves * 64) hybrid_fwd_kernel(
     float eps, float* __restrict__ L, float* __restrict__ Zout, int* __restrict__ count,
     int* __restrict__ keep, int* __restrict__ keep_count) {
   static_assert(kGroupTiles == 2, "the forward pairs the two tiles of a group");
-  __shared__ int surv[kHWaves][kHFwdCap];
+  __shared__ float4 stage_all[kHWaves][64 * 4];   // staged survivor records, 64 per wave
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int g = xcd_remap(blockIdx.x) * kHWaves + wave;
   if (g >= ngroups) return;
@@ -102,8 +102,8 @@ __global__ void __launch_bounds__(kHWaves * 64) hybrid_fwd_kernel(
   }
   const int cs = cell_start[gi.cell], ce = cell_start[gi.cell + 1];
   const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  int* sv = surv[wave];
-  int ns = 0, kept = 0;  // kept: survivors so far (all of them, also past the list's capacity)
+  float4* stage = stage_all[wave];
+  int kept = 0;  // survivors so far (all of them, also past the list's capacity)
   int* kl = keep ? keep + (int64_t)g * kSurvPerGroup : nullptr;
   for (int base = cs; base < ce; base += 64) {
     const int j = base + lane;
@@ -115,38 +115,48 @@ __global__ void __launch_bounds__(kHWaves * 64) hybrid_fwd_kernel(
              ((has_b && ball_touch(m.x, m.y, m.z, tb, r2pad)) ? 2 : 0);
     }
     const uint64_t bal = __ballot(mask != 0);
-    if (mask) sv[ns + __popcll(bal & below)] = pid | (mask << 30);
-    ns += __popcll(bal);
-    if (ns > kHFwdCap - 64 || base + 64 >= ce) {
-      wave_sync_lds();
-      const int nsu = __builtin_amdgcn_readfirstlane(ns);
-      if (kl) {  // keep the survivors (cell-list order) for the backward
-        for (int s = lane; s < nsu && kept + s < kSurvPerGroup; s += 64) kl[kept + s] = sv[s];
-        kept += nsu;
-      }
-      for (int s = 0; s < nsu; ++s) {
-        const int head = __builtin_amdgcn_readfirstlane(sv[s]);
-        const PrimRec r = recs[head & 0x3fffffff];
-#pragma unroll
-        for (int i = 0; i < 2; ++i) {
-          if (!((head >> (30 + i)) & 1)) continue;   // wave-uniform
-          const float dx = px[i] - r.r0.x, dy = py[i] - r.r0.y, dz = pz[i] - r.r0.z;
-          const bool in = sq_len(dx, dy, dz) <= r2;
-          float u[3];
-          whiten(r, dx, dy, dz, u);
-          const float m2 = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-          const float w = in ? __builtin_amdgcn_exp2f(-m2) : 0.f;
-          acc[i][0] += w * r.r0.w;
-          acc[i][1] += w * r.r1.w;
-          acc[i][2] += w * r.r2.w;
-          z[i] += w;
-          cnt[i] += in ? 1 : 0;
-        }
-      }
-      ns = 0;
-      wave_sync_lds();
+    const int nb = __popcll(bal);   // wave-uniform
+    if (nb == 0) continue;
+    if (mask) {
+      // the survivor's whole record, staged with the tile mask in place of
+      // the primitive index
+      const int slot = __popcll(bal & below);
+      const PrimRec r = recs[pid];
+      stage[slot * 4 + 0] = r.r0;
+      stage[slot * 4 + 1] = r.r1;
+      stage[slot * 4 + 2] = r.r2;
+      stage[slot * 4 + 3] = make_float4(r.r3.x, r.r3.y, r.r3.z, __int_as_float(mask));
+      // keep the survivors (cell-list order) for the backward
+      if (kl && kept + slot < kSurvPerGroup) kl[kept + slot] = pid | (mask << 30);
     }
+    wave_sync_lds();
+    for (int s = 0; s < nb; ++s) {
+      // broadcast LDS loads: the record in vector registers (an instruction
+      // with a scalar-register operand issues at half rate on gfx950)
+      const float4 R0 = stage[s * 4], R1 = stage[s * 4 + 1], R2 = stage[s * 4 + 2],
+                   R3 = stage[s * 4 + 3];
+      const int tiles = __builtin_amdgcn_readfirstlane(__float_as_int(R3.w));
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        if (!((tiles >> i) & 1)) continue;   // wave-uniform
+        const float dx = px[i] - R0.x, dy = py[i] - R0.y, dz = pz[i] - R0.z;
+        const bool in = sq_len(dx, dy, dz) <= r2;
+        const float u0 = fmaf(R1.z, dz, fmaf(R1.y, dy, R1.x * dx));
+        const float u1 = fmaf(R2.z, dz, fmaf(R2.y, dy, R2.x * dx));
+        const float u2 = fmaf(R3.z, dz, fmaf(R3.y, dy, R3.x * dx));
+        const float m2 = u0 * u0 + u1 * u1 + u2 * u2;
+        const float w = in ? __builtin_amdgcn_exp2f(-m2) : 0.f;
+        acc[i][0] += w * R0.w;
+        acc[i][1] += w * R1.w;
+        acc[i][2] += w * R2.w;
+        z[i] += w;
+        cnt[i] += in ? 1 : 0;
+      }
+    }
+    kept += nb;
+    wave_sync_lds();   // the next batch overwrites the stage
   }
+  if (!kl) kept = 0;
   if (keep_count && lane == 0) keep_count[g] = kept;
 #pragma unroll
   for (int i = 0; i < 2; ++i) {
