@@ -137,6 +137,8 @@ __device__ __forceinline__ int fwd_group(const TileCtx& ta, const TileCtx& tb, b
 // pairs in the same order with the same arithmetic and give identical sums.
 constexpr int kStage = 64;   // staged survivor records per wave (64 bytes each)
 
+// x must be wave-uniform: the scalar-register operand of the copy takes one
+// lane's value (the compiler reads the first lane of a vector register).
 __device__ __forceinline__ float in_vgpr(float x) {
   float v;
   asm("v_mov_b32 %0, %1" : "=v"(v) : "s"(x));
